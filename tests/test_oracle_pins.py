@@ -1,0 +1,299 @@
+"""Pins for the CPU oracle: brute force, BFS, a library routine, closed forms,
+the worked example of Fig. 1 and the properties of Algorithm 3 with R.
+
+None of these re-derives the oracle's own code: each check computes the
+expected value by an independent route (transitive closure, breadth-first
+search, scipy's connected_components, hand-built graphs with known answers).
+"""
+import itertools
+import os
+from collections import deque
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---- independent references -------------------------------------------------
+
+def closure_labels(n, edges):
+    """L_v = min{u : reach(u, v)} from the boolean reachability closure."""
+    R = np.eye(n, dtype=bool)
+    for u, v in edges:
+        R[u, v] = R[v, u] = True
+    for k in range(n):                       # Warshall
+        R |= R[:, k:k + 1] & R[k:k + 1, :]
+    return np.array([int(np.flatnonzero(R[:, v])[0]) for v in range(n)], dtype=np.uint32)
+
+
+def bfs_labels(n, edges):
+    """Scan start vertices in increasing ID order; BFS labels each new component
+    with its start, which is then its smallest ID."""
+    adj = [[] for _ in range(n)]
+    for u, v in edges:
+        adj[int(u)].append(int(v))
+        adj[int(v)].append(int(u))
+    L = np.full(n, -1, dtype=np.int64)
+    for s in range(n):
+        if L[s] >= 0:
+            continue
+        L[s] = s
+        q = deque([s])
+        while q:
+            x = q.popleft()
+            for y in adj[x]:
+                if L[y] < 0:
+                    L[y] = s
+                    q.append(y)
+    return L.astype(np.uint32)
+
+
+def scipy_min_labels(n, edges):
+    """Partition from scipy.sparse.csgraph, relabelled by each class's minimum."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    e = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
+    A = coo_matrix((np.ones(len(e), np.int8), (e[:, 0], e[:, 1])), shape=(n, n))
+    _, comp = connected_components(A, directed=True, connection="weak")
+    first = np.full(comp.max() + 1 if n else 0, np.iinfo(np.int64).max, dtype=np.int64)
+    np.minimum.at(first, comp, np.arange(n))
+    return first[comp].astype(np.uint32)
+
+
+def check_label_invariants(n, edges, L):
+    e = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
+    L = np.asarray(L, dtype=np.int64)
+    assert np.all(L[e[:, 0]] == L[e[:, 1]]), "an edge's endpoints have different labels"
+    assert np.all(L <= np.arange(n)), "a label exceeds its vertex ID"
+    assert np.all(L[L] == L), "a label is not a fixed point"
+
+
+# ---- brute force ------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_exhaustive_simple_graphs(n):
+    pairs = list(itertools.combinations(range(n), 2))
+    for mask in range(1 << len(pairs)):
+        edges = [pairs[i] for i in range(len(pairs)) if mask >> i & 1]
+        e = np.array(edges, dtype=np.uint32).reshape(-1, 2)
+        got = oracle.cc_labels(n, e)
+        np.testing.assert_array_equal(got, closure_labels(n, edges), err_msg=f"n={n} {edges}")
+
+
+def test_random_multigraphs_small():
+    rng = np.random.default_rng(12345)
+    for trial in range(400):
+        n = int(rng.integers(1, 13))
+        m = int(rng.integers(0, 3 * n + 1))
+        e = rng.integers(0, n, size=(m, 2)).astype(np.uint32)   # self-loops, repeats allowed
+        if m and trial % 3 == 0:
+            e = np.concatenate([e, e[: m // 2], e[:, ::-1]])      # explicit repeats / reversals
+        got = oracle.cc_labels(n, e)
+        np.testing.assert_array_equal(got, closure_labels(n, e.tolist()))
+
+
+# ---- BFS and library routine -----------------------------------------------
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_bfs_er_sparse(seed):
+    n = 3000
+    e = graphgen.er(n, 1400 + 300 * seed, seed)          # sparse: many components
+    got = oracle.cc_labels(n, e)
+    np.testing.assert_array_equal(got, bfs_labels(n, e))
+    check_label_invariants(n, e, got)
+
+
+def test_bfs_rmat():
+    e = graphgen.rmat(12, 3 * 4096, 77)
+    n = 4096
+    got = oracle.cc_labels(n, e)
+    np.testing.assert_array_equal(got, bfs_labels(n, e))
+
+
+@pytest.mark.parametrize("kind", ["er", "rmat", "rmat_sym"])
+def test_scipy_partition_large(kind):
+    if kind == "er":
+        n, e = 1 << 18, graphgen.er(1 << 18, 1 << 17, 5)
+    elif kind == "rmat":
+        n, e = 1 << 18, graphgen.rmat(18, 1 << 20, 6)
+    else:
+        n, e = 1 << 16, graphgen.rmat_sym(16, 1 << 19, 7)
+    got = oracle.cc_labels(n, e)
+    np.testing.assert_array_equal(got, scipy_min_labels(n, e))
+    check_label_invariants(n, e, got)
+
+
+# ---- closed forms -------------------------------------------------------------
+
+def test_empty_graph():
+    for n in [1, 7, 1000]:
+        np.testing.assert_array_equal(oracle.cc_labels(n, np.empty((0, 2), np.uint32)),
+                                      np.arange(n, dtype=np.uint32))
+
+
+def test_path_star_clique():
+    n = 50
+    path = [(i + 1, i) for i in range(n - 1)][::-1]
+    star = [(17, i) for i in range(n) if i != 17]
+    clique = list(itertools.combinations(range(n), 2))
+    for edges in (path, star, clique):
+        np.testing.assert_array_equal(oracle.cc_labels(n, edges), np.zeros(n, np.uint32))
+    # a star that does not include vertex 0 ... 4
+    star2 = [(40, i) for i in range(5, n) if i != 40]
+    want = np.arange(n, dtype=np.uint32)
+    want[5:] = 5
+    np.testing.assert_array_equal(oracle.cc_labels(n, star2), want)
+
+
+def test_disjoint_cliques_with_known_minima():
+    rng = np.random.default_rng(3)
+    n = 600
+    perm = rng.permutation(n)
+    groups = np.array_split(perm, 37)
+    edges = []
+    want = np.empty(n, np.uint32)
+    for grp in groups:
+        want[grp] = grp.min()
+        edges += [(int(a), int(b)) for a, b in itertools.combinations(grp, 2)]
+    rng.shuffle(edges)
+    got = oracle.cc_labels(n, edges)
+    np.testing.assert_array_equal(got, want)
+    assert oracle.count_components(got) == 37
+
+
+def test_extras_closed_form():
+    g = graphgen.rmat_extras(10, 4, 99, n_paths=50)
+    L = oracle.cc_labels(g.n, g.edges)
+    lo, hi = g.isolated
+    np.testing.assert_array_equal(L[lo:hi], np.arange(lo, hi, dtype=np.uint32))
+    for s, ln in zip(g.path_starts, g.path_lens):
+        np.testing.assert_array_equal(L[int(s):int(s) + int(ln)], np.full(int(ln), s, np.uint32))
+    assert np.all(L[: g.n_rmat] < g.n_rmat)
+
+
+def test_out_of_range_endpoint():
+    with pytest.raises(oracle.OracleError) as ei:
+        oracle.cc_labels(4, [(0, 1), (2, 4)])
+    assert ei.value.code == oracle.ERANGE
+
+
+# ---- the worked example (Fig. 1) ---------------------------------------------
+
+def _read_fig1():
+    rows = [ln.split() for ln in open(os.path.join(GOLDEN, "fig1_jt_steps.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    n = int(rows[0][0])
+    edges = [tuple(map(int, r)) for r in rows[1:] if len(r) == 2]
+    states = [list(map(int, r)) for r in rows[1:] if len(r) == n + 1]
+    return n, edges, states
+
+
+def test_fig1_worked_example():
+    n, edges, states = _read_fig1()
+    e = np.array(edges, np.uint32)
+    for row in states:
+        steps, want = row[0], row[1:]
+        np.testing.assert_array_equal(oracle.jt_seq(n, e, steps=steps), np.array(want, np.uint32))
+
+
+def test_jt_seq_reaches_min_labels():
+    """Algorithm 1 with pointer jumping gives each component its lowest ID."""
+    rng = np.random.default_rng(8)
+    for _ in range(200):
+        n = int(rng.integers(1, 40))
+        e = rng.integers(0, n, size=(int(rng.integers(0, 2 * n)), 2)).astype(np.uint32)
+        np.testing.assert_array_equal(oracle.jt_seq(n, e, jump=True), closure_labels(n, e.tolist()))
+
+
+# ---- Algorithm 3 with the root function R (Formulas 1-2) ----------------------
+
+def test_root_function_jt_closed_form():
+    """With R, the root of a component is zmax if it belongs to it (R = 0), else its
+    lowest ID (R = ID + 1); Algorithm 3's P holds that root's R value."""
+    rng = np.random.default_rng(21)
+    for _ in range(200):
+        n = int(rng.integers(1, 30))
+        e = rng.integers(0, n, size=(int(rng.integers(0, 2 * n)), 2)).astype(np.uint32)
+        z = int(rng.integers(0, n))
+        L = closure_labels(n, e.tolist())
+        want = np.where(L == L[z], 0, L.astype(np.uint64) + 1)
+        np.testing.assert_array_equal(oracle.rf_jt(n, e, z), want)
+
+
+def test_root_function_zero_at_vertex0_matches_alg1():
+    """zmax = 0 makes R order-isomorphic to the identity, so Algorithm 3 reduces to
+    Algorithm 1 (Sec. IV: f = identity gives JT)."""
+    e = graphgen.er(500, 300, 4)
+    P1 = oracle.jt_seq(500, e, jump=True).astype(np.uint64)
+    P3 = oracle.rf_jt(500, e, 0)
+    np.testing.assert_array_equal(P3, np.where(P1 == 0, 0, P1 + 1))
+
+
+# ---- zero root and initial push -------------------------------------------------
+
+def test_zroot_star_and_ties():
+    star = [(i, 9) for i in range(20) if i != 9]
+    assert oracle.zroot(20, star, 0) == 9
+    # a perfect matching on 2..9: every counted vertex has count 1 -> lowest is 2
+    assert oracle.zroot(10, [(3, 2), (5, 4), (7, 6), (9, 8)], 0) == 2
+    # self-loops do not count
+    loops = [(5, 5)] * 10 + [(3, 1), (3, 2)]
+    assert oracle.zroot(6, loops, 0) == 3
+    # nothing counted -> vertex 0
+    assert oracle.zroot(6, [(4, 4)], 0) == 0
+    assert oracle.zroot(6, np.empty((0, 2), np.uint32), 0) == 0
+
+
+def test_zroot_stride_sample():
+    """K-sampling reads entries floor(j*m/K): sampled positions hold a star at 7,
+    the others a larger star at 11."""
+    m, K = 1000, 100
+    sampled = {(j * m) // K for j in range(K)}
+    e = np.empty((m, 2), np.uint32)
+    a = b = 0
+    for i in range(m):
+        if i in sampled:
+            e[i] = (7, 20 + a % 50); a += 1
+        else:
+            e[i] = (11, 20 + b % 50); b += 1
+    assert oracle.zroot(100, e, K) == 7
+    assert oracle.zroot(100, e, 0) == 11
+
+
+def test_push_star():
+    n, z = 30, 12
+    e = np.array([(z, i) for i in range(0, n, 3) if i != z] + [(1, 2), (z, z)], np.uint32)
+    P = oracle.push(n, e, 0, z)
+    want = np.arange(n, dtype=np.uint32)
+    for i in range(0, n, 3):
+        want[i] = z
+    want[z] = z
+    np.testing.assert_array_equal(P, want)
+
+
+# ---- forest checker -------------------------------------------------------------
+
+def test_check_forest():
+    assert oracle.check_forest(np.array([0, 0, 1, 3], np.uint32)) == 2
+    with pytest.raises(AssertionError):
+        oracle.check_forest(np.array([1, 0], np.uint32))          # cycle
+    with pytest.raises(AssertionError):
+        oracle.check_forest(np.array([0, 2, 2], np.uint32))       # parent with greater key
+    # with the zero root 2, 0 -> 2 is key-decreasing
+    assert oracle.check_forest(np.array([2, 0, 2], np.uint32), True, 2) == 1
+
+
+# ---- batch ----------------------------------------------------------------------
+
+def test_batch_matches_single():
+    b = graphgen.batch(40, 11, lg_n_lo=3, lg_n_hi=9)
+    L, st = oracle.cc_labels_batch(b.vtx_off, b.edge_off, b.edges)
+    assert np.all(st == 0)
+    for g in range(b.G):
+        e, n = b.graph(g)
+        np.testing.assert_array_equal(L[b.vtx_off[g]:b.vtx_off[g + 1]].astype(np.uint32),
+                                      closure_labels(n, e.tolist()) if n <= 64 else bfs_labels(n, e))
