@@ -1,0 +1,278 @@
+#!/usr/bin/env python3
+"""Benchmark of the connected-components path on one MI355X.
+
+A step is one pass of the whole single-graph path over the workload, with the
+edge list already resident in HBM: init, zero root (sampled), Initial Push,
+hook, compress and the zero-component relabelling (flags CC_F_ZROOT), i.e.
+cc_init / cc_zroot / cc_push / cc_hook / cc_compress / cc_canon enqueued on one
+stream. The hook kernel is bracketed by its own HIP events on that stream
+inside the timed region (the roofline figure).
+
+Prints one JSON line. Default workload: R-MAT scale 26, edgefactor 16, permuted
+IDs, plus 1 % isolated vertices and 10,000 paths of 2..64 vertices.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    import graphgen
+    if name == "rmat26":
+        g = graphgen.rmat26_extras()
+        return g.edges, g.n, {"workload": "rmat26_ef16_permuted+1pct_isolated+10k_paths",
+                              "scale": 26, "edgefactor": 16, "n": g.n, "m": int(len(g.edges))}
+    if name == "rmat22":
+        e, n = graphgen.rmat22_sym()
+        return e, n, {"workload": "rmat22_ef16_permuted_symmetrised", "scale": 22,
+                      "edgefactor": 16, "n": n, "m": int(len(e))}
+    if name == "er65k":
+        e, n = graphgen.er_65k()
+        return e, n, {"workload": "er_n65536_m1048576", "n": n, "m": int(len(e))}
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(edges, n, target_s=15.0):
+    """The oracle on a bounded prefix of the same entries (1 host thread)."""
+    import oracle
+    m = len(edges)
+    k = min(m, 1 << 22)
+    t0 = time.perf_counter()
+    oracle.cc_labels(n, edges[:k])
+    t1 = time.perf_counter() - t0
+    k2 = int(min(m, max(k, k * target_s / max(t1, 1e-3))))
+    if k2 > k:
+        t0 = time.perf_counter()
+        oracle.cc_labels(n, edges[:k2])
+        t1 = time.perf_counter() - t0
+        k = k2
+    return {"value": round(k / t1 / 1e9, 6), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "sample": f"first {k} of {m} entries with all {n} vertices; union-find + min-ID pass, "
+                      f"{t1:.2f} s on one host thread"}
+
+
+def bench_single(cc, torch, ed, n, m, steps, warmup, flags):
+    ctx = cc.Context()
+    stream = torch.cuda.current_stream()
+    L = torch.empty(n, dtype=torch.int32, device="cuda")
+
+    def one_step(ev=None):
+        ctx.init(n, L, stream)
+        if flags & cc.F_ZROOT:
+            ctx.zroot(ed, n, flags=flags, stream=stream)
+            ctx.push(ed, n, L, stream=stream)
+        if ev is not None:
+            ev[0].record(stream)
+        ctx.hook(ed, n, L, flags=flags, stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+        ctx.compress(n, L, flags=flags, stream=stream)
+        if flags & cc.F_ZROOT:
+            ctx.canon(n, L, stream=stream)
+
+    for _ in range(warmup):
+        one_step()
+    rc = ctx.sync(stream)
+    assert rc == cc.CC_OK, rc
+    hook_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for i in range(steps):
+        one_step(hook_ev[i])
+    end.record(stream)
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(end)
+    hook_ms = [a.elapsed_time(b) for a, b in hook_ev]
+    rc = ctx.sync(stream)
+    assert rc == cc.CC_OK, rc
+    ctx.close()
+    return total_ms / steps, float(np.mean(hook_ms)), L
+
+
+def bench_batch(cc, torch, reps=5):
+    """4,096 graphs: one persistent cc_batch launch vs one cc_solve_async per graph."""
+    import graphgen
+    b = graphgen.batch_4096()
+    vo = torch.from_numpy(b.vtx_off).cuda()
+    eo = torch.from_numpy(b.edge_off).cuda()
+    ed = torch.from_numpy(np.ascontiguousarray(b.edges)).cuda()
+    ctx = cc.Context()
+    L = torch.empty(int(b.vtx_off[-1]), dtype=torch.int32, device="cuda")
+    st = torch.empty(b.G, dtype=torch.int32, device="cuda")
+    ctx.batch(vo, eo, ed, L, st)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        ctx.batch(vo, eo, ed, L, st)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    t_batch = float(np.median(ts))
+    # per-graph launches on one stream
+    L2 = torch.empty_like(L)
+    views = [(ed[b.edge_off[g]:b.edge_off[g + 1]], int(b.vtx_off[g + 1] - b.vtx_off[g]),
+              L2[b.vtx_off[g]:b.vtx_off[g + 1]]) for g in range(b.G)]
+    stream = torch.cuda.current_stream()
+    for e, n, l in views:
+        ctx.solve_async(e, n, l, stream=stream)
+    ctx.sync(stream)
+    ts = []
+    for _ in range(max(1, reps // 2)):
+        t0 = time.perf_counter()
+        for e, n, l in views:
+            ctx.solve_async(e, n, l, stream=stream)
+        ctx.sync(stream)
+        ts.append(time.perf_counter() - t0)
+    t_loop = float(np.median(ts))
+    same = bool(torch.equal(L, L2))
+    ctx.close()
+    m = int(b.edge_off[-1])
+    return {"graphs": b.G, "sum_n": int(b.vtx_off[-1]), "sum_m": m,
+            "batched_graphs_per_s": round(b.G / t_batch, 1),
+            "batched_ms": round(t_batch * 1e3, 3),
+            "per_graph_launch_graphs_per_s": round(b.G / t_loop, 1),
+            "per_graph_launch_ms": round(t_loop * 1e3, 3),
+            "speedup": round(t_loop / t_batch, 2), "identical_labels": same}
+
+
+def bench_serve(cc, torch, count=2000, seed=0x2507036950000005):
+    """Poisson stream of requests (Pareto n in [2^10, 2^24]) through cc_serve at an
+    offered load above a FIFO plain-path server's capacity; p50/p99 latency."""
+    import graphgen
+    reqs = graphgen.serve_stream(count, seed, rate_per_s=1.0)
+    data = []
+    for r in reqs:
+        e = np.ascontiguousarray(r.edges().view(np.uint32).reshape(-1, 2))
+        data.append((e, r.n))
+
+    def run(srv_kwargs, rate):
+        ctx = cc.Context()
+        srv = cc.Server(ctx, **srv_kwargs)
+        outs = [np.empty(n, np.uint32) for _, n in data]
+        tickets = []
+        t0 = time.perf_counter()
+        for i, ((e, n), r) in enumerate(zip(data, reqs)):
+            due = t0 + r.arrival_s / rate
+            while time.perf_counter() < due:
+                pass
+            tickets.append(srv.submit(e, n, outs[i]))
+        lat = []
+        for t in tickets:
+            rc, s = srv.wait(t)
+            assert rc == cc.CC_OK, rc
+            lat.append((s.t_done_ns - s.t_submit_ns) / 1e6)
+        wall = time.perf_counter() - t0
+        srv.close()
+        ctx.close()
+        return outs, np.array(lat), wall
+
+    # capacity of a FIFO plain-path server: one stream, no batching, back to back
+    outs_fifo, lat_fifo, wall_fifo = run({"streams": 1, "small_n": 1, "max_inflight": 1}, 1e9)
+    cap = count / wall_fifo
+    rate = 1.2 * cap
+    outs, lat, wall = run({"streams": 4}, rate)
+    same = all(np.array_equal(a, b) for a, b in zip(outs, outs_fifo))
+    return {"requests": count, "offered_rate_per_s": round(rate, 1),
+            "fifo_capacity_graphs_per_s": round(cap, 1),
+            "served_graphs_per_s": round(count / wall, 1),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "fifo_p50_ms_saturated": round(float(np.percentile(lat_fifo, 50)), 3),
+            "fifo_p99_ms_saturated": round(float(np.percentile(lat_fifo, 99)), 3),
+            "identical_to_fifo": same}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rmat26", choices=["rmat26", "rmat22", "er65k"])
+    ap.add_argument("--variant", default="zroot", choices=["zroot", "plain"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batch and serve lines")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU sharding is a design, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2507_03695_amd as cc
+    cc.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    t0 = time.time()
+    edges, n, cfg = make_workload(args.workload)
+    m = len(edges)
+    log(f"workload {cfg['workload']}: n={n} m={m} generated in {time.time() - t0:.1f} s")
+    ed = torch.from_numpy(edges.view(np.int32)).cuda()
+    torch.cuda.synchronize()
+
+    flags = cc.F_ZROOT if args.variant == "zroot" else 0
+    ms, hook_ms, L = bench_single(cc, torch, ed, n, m, args.steps, args.warmup, flags)
+    log(f"step {ms:.3f} ms, hook {hook_ms:.3f} ms")
+    other = "plain" if args.variant == "zroot" else "zroot"
+    ms_o, hook_o, L_o = bench_single(cc, torch, ed, n, m, max(3, args.steps // 2), 1,
+                                     0 if flags else cc.F_ZROOT)
+    assert torch.equal(L, L_o), "variants disagree"
+    del L_o
+
+    alg_bytes = 8 * m + 12 * n
+    gteps = m / (ms * 1e-3) / 1e9
+    hook_gbs = 8 * m / (hook_ms * 1e-3) / 1e9
+    line = {
+        "metric": "GTEPS (COO entries per second, whole path: init+zroot+push+hook+compress+canon)",
+        "value": round(gteps, 3),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": dict(cfg, variant=args.variant, parallelism="single_gpu"),
+        "hbm_roofline_frac_whole_path": round(alg_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+        "roofline": {"bound": "hbm", "kernel": "k_hook", "achieved": round(hook_gbs, 1),
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(hook_gbs / PEAK_HBM_GBS, 4), "traffic": None,
+                     "algorithmic_bytes_per_launch": 8 * m, "avg_launch_ms": round(hook_ms, 4)},
+        other: {"ms_per_step": round(ms_o, 4), "hook_ms": round(hook_o, 4),
+                "GTEPS": round(m / (ms_o * 1e-3) / 1e9, 3)},
+    }
+    del ed, L
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        t1 = time.time()
+        line["batch"] = bench_batch(cc, torch)
+        log(f"batch done in {time.time() - t1:.1f} s")
+        t1 = time.time()
+        line["serve"] = bench_serve(cc, torch)
+        log(f"serve done in {time.time() - t1:.1f} s")
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(edges, n)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,241 @@
+/*
+ * cc.h — connected-components labelling on AMD Instinct MI355X (gfx950).
+ *
+ * The library labels the connected components of an undirected graph given as
+ * a COO list of unordered vertex pairs. It follows the Jayanti-Tarjan
+ * disjoint-set-union method of Sec. II (Algorithm 1): one pass over the edges
+ * in which every worker finds the roots of both endpoints in one shared parent
+ * array P and links the root of greater key under the other with a
+ * compare-and-swap, then pointer jumping. The root-function generalisation of
+ * Sec. IV (Algorithm 3 with RobinCC's R, Formulas 1-2) is the CC_F_ZROOT
+ * variant: the vertex of largest (sampled) degree takes the smallest key, its
+ * sampled neighbours are attached to it first (Initial Push), and edges whose
+ * endpoints both already hang from it are dropped.
+ *
+ * Output labelling. Sec. II defines the output as an array L with L_u == L_v
+ * iff u and v are connected. Every entry point here returns the canonical such
+ * array: L_v is the smallest vertex ID of v's component (the identity JT with
+ * link by index reaches, Sec. II text after Algorithm 1). The CC_F_ZROOT
+ * variant reaches the same array after a final relabelling of the zero root's
+ * component, so results never depend on thread schedule, edge order, the zero
+ * root chosen, or the batch a graph was solved in.
+ *
+ * Conventions.
+ *  - Device pointers are HIP device memory owned by the caller (for instance
+ *    torch tensors). The library never frees or retains them past the call
+ *    (synchronous entry points) or past completion of the stream (async
+ *    entry points).
+ *  - `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ *  - Edge lists are 2*m uint32 (or int32) values: entry i is the unordered
+ *    pair (edge[2i], edge[2i+1]). Self-loops and repeated pairs are allowed
+ *    and change nothing. The input need not be symmetric (Sec. II: processing
+ *    (u,v) makes (v,u) a no-op).
+ *  - Vertex IDs are 32-bit (Sec. V uses 4-byte IDs below 2^32 vertices), so
+ *    n <= 2^32 - 1.
+ *  - Every function returns a status code; on failure a thread-local
+ *    description is available from cc_last_error_detail().
+ */
+#ifndef CCMI_CC_H
+#define CCMI_CC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define CC_OK         0
+#define CC_EINVAL   (-1)  /* bad argument: n >= 2^32, NULL with nonzero size, bad offsets */
+#define CC_ERANGE   (-2)  /* some endpoint >= n; labels are then unspecified */
+#define CC_ENOMEM   (-3)  /* device memory or the configured HBM budget is exhausted */
+#define CC_EDEVICE  (-4)  /* a HIP call failed; the detail string names it */
+#define CC_EAGAIN   (-5)  /* server queue full; submit again later */
+#define CC_ECANCELED (-6) /* server closed before the request ran */
+#define CC_ETIMEDOUT (-7) /* wait timed out; the request is still pending */
+
+/* Human-readable name of a status code (static storage). */
+const char* cc_strerror(int code);
+/* Detail of the last failure on the calling thread (thread-local storage). */
+const char* cc_last_error_detail(void);
+/* Library version as 10000*major + 100*minor + patch. */
+int cc_version(void);
+
+/* ---- solve flags ------------------------------------------------------ */
+/* Zero planting (Sec. IV, Formula 1): the sampled max-degree vertex is the
+   root of smallest key; Initial Push from it; giant-component edge skip.   */
+#define CC_F_ZROOT        0x1u
+/* With CC_F_ZROOT: take the exact maximum-degree vertex (a full counting
+   pass over all entries) instead of the sampled estimate.                  */
+#define CC_F_ZROOT_EXACT  0x2u
+/* With CC_F_ZROOT: the zero root is `zroot_hint` (must be < n).            */
+#define CC_F_ZROOT_HINT   0x4u
+/* Plain root walks without path splitting (Algorithm 1's finds as printed). */
+#define CC_F_NO_SPLIT     0x8u
+
+/* ---- context ----------------------------------------------------------- */
+typedef struct cc_ctx cc_ctx;
+
+typedef struct cc_ctx_opts {
+    int      device;          /* HIP device ordinal; -1 = the current device   */
+    uint32_t zroot_samples;   /* entries sampled for the zero root; 0 = 65536  */
+    uint64_t hbm_budget;      /* bytes the server may hold resident; 0 = 3/4 of
+                                 free memory at creation                        */
+} cc_ctx_opts;
+
+/* Create a context on a device: it owns scratch memory (status word, zero
+   root selection state, a sampled-degree hash table), pinned host staging
+   and nothing else. opts may be NULL (defaults). */
+int cc_create(cc_ctx** out, const cc_ctx_opts* opts);
+/* Release a context and everything it owns. Waits for its work to finish. */
+void cc_destroy(cc_ctx* ctx);
+
+/* ---- single graph --------------------------------------------------------- */
+
+/*
+ * Label the components of one graph (plain path, Algorithm 1 with path
+ * splitting), synchronously, on the current device's default context and the
+ * null stream.
+ *   n          vertex count (IDs are 0..n-1), n <= 2^32-1; n == 0 is a no-op
+ *   m          number of entries (unordered pairs)
+ *   edge_list  device, 2*m uint32, read only; may be NULL iff m == 0
+ *   L          device, n uint32, written: L_v = min ID of v's component;
+ *              may be NULL iff n == 0. L doubles as the parent array.
+ * Returns CC_OK, CC_EINVAL, CC_ERANGE (an endpoint >= n), CC_EDEVICE.
+ */
+int cc_solve(uint64_t n, uint64_t m, const uint32_t* edge_list, uint32_t* L);
+
+/*
+ * Enqueue the whole path on `stream` and return without waiting:
+ * init (Algorithm 1 / 3 initialisation), [zero root + Initial Push when
+ * CC_F_ZROOT], hook (one pass over the entries), compress (pointer jumping)
+ * and, with CC_F_ZROOT, the min-ID relabelling of the zero root's component.
+ * Argument errors are returned at once; out-of-range endpoints are recorded
+ * in the context's status word and reported by the next cc_sync.
+ * Buffers must stay valid until the stream reaches the end of this work.
+ * Solves queued on one context share its status word and zero-root state:
+ * queue them on one stream, or use one context per concurrent stream.
+ */
+int cc_solve_async(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edge_list,
+                   uint32_t* L, uint32_t flags, uint32_t zroot_hint, void* stream);
+
+/* Wait for `stream`, then return (and clear) the status accumulated by the
+   context's work since the previous cc_sync: CC_OK or CC_ERANGE. */
+int cc_sync(cc_ctx* ctx, void* stream);
+
+/* ---- the steps, one entry point each (asynchronous on `stream`) ----------
+ * Precondition of cc_push, cc_hook and cc_compress: P holds a parent forest
+ * made by the preceding steps on the same n (every entry < n). Any other
+ * content of P is undefined behaviour (the walks follow whatever P holds).  */
+
+/* Algorithm 1 / 3 initialisation: P_v = v for v < n (P holds vertex IDs; a
+   vertex is a root iff P_v == v). Also resets the zero-root relabelling
+   state. P: device, n uint32, written. */
+int cc_init(cc_ctx* ctx, uint64_t n, uint32_t* P, void* stream);
+
+/* Zero root selection (Algorithm 4 max_degree; Sec. IV Zero Planting).
+   Sampled (default): entries i_j = floor(j*m/K), j < K (all entries when
+   m <= K, K = zroot_samples); exact (CC_F_ZROOT_EXACT): all entries. The
+   root is the vertex with the most endpoint occurrences among those entries
+   that are not self-loops, ties to the lowest ID; vertex 0 when nothing is
+   counted. CC_F_ZROOT_HINT stores zroot_hint instead. The choice stays in
+   the context (read it with cc_get_zroot). edges: device, 2*m uint32. */
+int cc_zroot(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t flags,
+             uint32_t zroot_hint, void* stream);
+
+/* Initial Push (Algorithm 4 initial-push loop): for every entry of the
+   zero-root sample with exactly one endpoint equal to the zero root z, the
+   other endpoint x gets P_x = z. Run after cc_init and cc_zroot, before
+   cc_hook. P: device, n uint32, updated in place. */
+int cc_push(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
+            void* stream);
+
+/* Hooking (Algorithm 1 / 3 hooking loop): one pass over the m entries; per
+   entry both roots are found (with path splitting unless CC_F_NO_SPLIT) and
+   the root of greater key is linked under the other by compare-and-swap,
+   retrying from the value the failed CAS returns. key(x) = x, or with
+   CC_F_ZROOT key(z) = 0 and key(x) = x + 1 (R of Formula 1). With
+   CC_F_ZROOT, entries whose endpoints both have parent z are skipped.
+   Out-of-range endpoints set the status word and are skipped. */
+int cc_hook(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
+            uint32_t flags, void* stream);
+
+/* Pointer jumping (Algorithm 1 / 3 final loop): P_v <- root of v for every
+   v. On the plain path the result is the min-ID labelling. With CC_F_ZROOT
+   it also records the smallest vertex whose root is z. */
+int cc_compress(cc_ctx* ctx, uint64_t n, uint32_t* P, uint32_t flags, void* stream);
+
+/* Relabelling of the zero root's component (CC_F_ZROOT only): L_v == z is
+   replaced by the smallest ID of z's component recorded by cc_compress. */
+int cc_canon(cc_ctx* ctx, uint64_t n, uint32_t* L, void* stream);
+
+/* Synchronously read the context's current zero root (after cc_zroot). */
+int cc_get_zroot(cc_ctx* ctx, void* stream, uint32_t* zroot_out);
+
+/* ---- many graphs in one launch ------------------------------------------- */
+
+/*
+ * Label G independent graphs with local int32 IDs in one persistent launch.
+ *   vtx_off, edge_off  device, G+1 int64 each, non-decreasing, starting at 0
+ *   edges              device, 2*edge_off[G] int32: graph g's entries are
+ *                      edges[2*edge_off[g] .. 2*edge_off[g+1]) with IDs in
+ *                      [0, n_g), n_g = vtx_off[g+1] - vtx_off[g] < 2^31
+ *   L                  device, vtx_off[G] int32, written: L[vtx_off[g] + v]
+ *                      = smallest local ID of v's component in graph g
+ *   status             device, G int32, written: CC_OK or CC_ERANGE per graph
+ * The schedule (graph to workgroup mapping, LDS-resident parent arrays for
+ * small graphs) is chosen by the context's tuner from the size mix.
+ * Synchronous: returns after the labels are written.
+ * Returns CC_OK when the launch ran (per-graph outcomes are in `status`).
+ */
+int cc_batch(cc_ctx* ctx, uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,
+             const int32_t* edges, int32_t* L, int32_t* status, void* stream);
+
+/* ---- continuous-batching server ------------------------------------------- */
+typedef struct cc_server cc_server;
+
+typedef struct cc_serve_opts {
+    uint32_t max_inflight;     /* requests resident on the device at once; 0 = 64   */
+    uint32_t queue_capacity;   /* submitted but not yet admitted; 0 = 4096           */
+    uint32_t streams;          /* HIP streams used for overlap; 0 = 4                */
+    uint32_t small_n;          /* requests with n <= small_n go to batched launches;
+                                  0 = 65536                                          */
+    uint64_t hbm_budget;       /* bytes of device memory the server may hold; 0 =
+                                  the context's budget                              */
+} cc_serve_opts;
+
+typedef struct cc_req_stats {
+    int32_t  status;          /* the request's outcome (CC_OK, CC_ERANGE, ...)       */
+    uint32_t batched;         /* 1 if it ran inside a batched launch                 */
+    uint64_t t_submit_ns;     /* CLOCK_MONOTONIC timestamps                           */
+    uint64_t t_admit_ns;
+    uint64_t t_done_ns;
+} cc_req_stats;
+
+/* Start a server thread on ctx's device. */
+int cc_serve_open(cc_ctx* ctx, const cc_serve_opts* opts, cc_server** out);
+
+/*
+ * Submit one request (non-blocking). edges_host: 2*m uint32 in host memory,
+ * L_host: n uint32 in host memory; both stay owned by the caller and must
+ * remain valid until cc_serve_wait returns for this ticket. Admission waits
+ * until the request's device footprint (8m + 4n bytes plus scratch) fits the
+ * budget. Returns CC_EAGAIN when the queue is full, CC_ENOMEM when the
+ * request alone exceeds the budget, CC_EINVAL for bad arguments.
+ */
+int cc_serve_submit(cc_server* srv, uint64_t n, uint64_t m, const uint32_t* edges_host,
+                    uint32_t* L_host, uint32_t flags, uint64_t* ticket);
+
+/* Wait up to timeout_us (< 0: forever) for a ticket; fills stats if non-NULL
+   and returns the request's status, or CC_ETIMEDOUT. A ticket can be waited
+   for once. */
+int cc_serve_wait(cc_server* srv, uint64_t ticket, int64_t timeout_us, cc_req_stats* stats);
+
+/* Stop accepting requests, finish everything admitted, cancel what is still
+   queued (their wait returns CC_ECANCELED), join the thread, free. */
+int cc_serve_close(cc_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CCMI_CC_H */

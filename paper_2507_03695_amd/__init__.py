@@ -1,0 +1,288 @@
+"""Python binding of libccmi (include/cc.h): connected components on MI355X.
+
+Argument marshalling only: every step runs in the HIP library. PyTorch provides
+device memory and streams; tensors are passed as raw device pointers. The
+binding refuses to run when the library is missing (no CPU fallback).
+
+Entry points mirror the C ABI:
+
+    solve(edges, n)                      -> int32/uint32 labels (synchronous)
+    Context().solve_async(edges, n, L, flags=..., stream=...)
+    Context().sync(stream)
+    Context().init / zroot / push / hook / compress / canon   (one step each)
+    Context().batch(vtx_off, edge_off, edges, L, status)
+    Server(ctx).submit / wait / close
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libccmi.so")
+
+CC_OK, CC_EINVAL, CC_ERANGE, CC_ENOMEM, CC_EDEVICE, CC_EAGAIN, CC_ECANCELED, CC_ETIMEDOUT = \
+    0, -1, -2, -3, -4, -5, -6, -7
+F_ZROOT, F_ZROOT_EXACT, F_ZROOT_HINT, F_NO_SPLIT = 0x1, 0x2, 0x4, 0x8
+
+
+class CCError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        lib = _lib_or_none()
+        detail = lib.cc_last_error_detail().decode() if lib else ""
+        name = lib.cc_strerror(code).decode() if lib else str(code)
+        super().__init__(f"{where}: {name} ({detail})")
+        self.code = code
+
+
+class _CtxOpts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("zroot_samples", ctypes.c_uint32),
+                ("hbm_budget", ctypes.c_uint64)]
+
+
+class _ServeOpts(ctypes.Structure):
+    _fields_ = [("max_inflight", ctypes.c_uint32), ("queue_capacity", ctypes.c_uint32),
+                ("streams", ctypes.c_uint32), ("small_n", ctypes.c_uint32),
+                ("hbm_budget", ctypes.c_uint64)]
+
+
+class ReqStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("batched", ctypes.c_uint32),
+                ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
+                ("t_done_ns", ctypes.c_uint64)]
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_P, _U64, _U32, _I32, _I64 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, \
+    ctypes.c_int64
+SIGNATURES = {
+    "cc_strerror": (ctypes.c_char_p, [_I32]),
+    "cc_last_error_detail": (ctypes.c_char_p, []),
+    "cc_version": (_I32, []),
+    "cc_create": (_I32, [ctypes.POINTER(_P), ctypes.POINTER(_CtxOpts)]),
+    "cc_destroy": (None, [_P]),
+    "cc_solve": (_I32, [_U64, _U64, _P, _P]),
+    "cc_solve_async": (_I32, [_P, _U64, _U64, _P, _P, _U32, _U32, _P]),
+    "cc_sync": (_I32, [_P, _P]),
+    "cc_init": (_I32, [_P, _U64, _P, _P]),
+    "cc_zroot": (_I32, [_P, _U64, _U64, _P, _U32, _U32, _P]),
+    "cc_push": (_I32, [_P, _U64, _U64, _P, _P, _P]),
+    "cc_hook": (_I32, [_P, _U64, _U64, _P, _P, _U32, _P]),
+    "cc_compress": (_I32, [_P, _U64, _P, _U32, _P]),
+    "cc_canon": (_I32, [_P, _U64, _P, _P]),
+    "cc_get_zroot": (_I32, [_P, _P, ctypes.POINTER(_U32)]),
+    "cc_batch": (_I32, [_P, _U32, _P, _P, _P, _P, _P, _P]),
+    "cc_serve_open": (_I32, [_P, ctypes.POINTER(_ServeOpts), ctypes.POINTER(_P)]),
+    "cc_serve_submit": (_I32, [_P, _U64, _U64, _P, _P, _U32, ctypes.POINTER(_U64)]),
+    "cc_serve_wait": (_I32, [_P, _U64, _I64, ctypes.POINTER(ReqStats)]),
+    "cc_serve_close": (_I32, [_P]),
+}
+
+
+def _lib_or_none():
+    return _lib
+
+
+def load():
+    """Load libccmi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              f"`python -c 'import __graft_entry__ as g; g.build()'`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int, where: str):
+    if rc != CC_OK:
+        raise CCError(rc, where)
+
+
+def _dptr(t: torch.Tensor | None, dtypes) -> int | None:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if t.dtype not in dtypes:
+        raise TypeError(f"dtype {t.dtype} not in {dtypes}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr() if t.numel() else None
+
+
+_ID = (torch.int32, torch.uint32)
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream or None
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream or None
+    return int(stream) or None
+
+
+def solve(edges: torch.Tensor, n: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """cc_solve: labels L (n entries, dtype of `edges`) with L_v = min ID of v's component.
+
+    `edges` is an (m, 2) int32/uint32 device tensor of unordered pairs. Runs on the
+    null stream and waits for it; the current torch stream is synchronised first.
+    """
+    lib = load()
+    m = edges.shape[0] if edges.dim() == 2 else edges.numel() // 2
+    if out is None:
+        out = torch.empty(n, dtype=edges.dtype, device=edges.device)
+    torch.cuda.current_stream().synchronize()
+    _check(lib.cc_solve(n, m, _dptr(edges, _ID), _dptr(out, _ID)), "cc_solve")
+    return out
+
+
+class Context:
+    """A cc_ctx: scratch for one solve at a time per stream (see cc.h)."""
+
+    def __init__(self, device: int | None = None, zroot_samples: int = 0, hbm_budget: int = 0):
+        lib = load()
+        o = _CtxOpts(-1 if device is None else device, zroot_samples, hbm_budget)
+        h = ctypes.c_void_p()
+        _check(lib.cc_create(ctypes.byref(h), ctypes.byref(o)), "cc_create")
+        self._h = h
+        self.lib = lib
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            self.lib.cc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # whole path
+    def solve_async(self, edges, n, L, flags=0, zroot_hint=0, stream=None):
+        m = edges.shape[0] if edges.dim() == 2 else edges.numel() // 2
+        _check(self.lib.cc_solve_async(self._h, n, m, _dptr(edges, _ID), _dptr(L, _ID), flags,
+                                       zroot_hint, _stream(stream)), "cc_solve_async")
+
+    def sync(self, stream=None) -> int:
+        """Wait for the stream; returns CC_OK or CC_ERANGE (does not raise for ERANGE)."""
+        rc = self.lib.cc_sync(self._h, _stream(stream))
+        if rc not in (CC_OK, CC_ERANGE):
+            _check(rc, "cc_sync")
+        return rc
+
+    def solve(self, edges, n, flags=0, zroot_hint=0, out=None, stream=None):
+        if out is None:
+            out = torch.empty(n, dtype=edges.dtype, device=edges.device)
+        self.solve_async(edges, n, out, flags, zroot_hint, stream)
+        rc = self.sync(stream)
+        _check(rc, "solve")
+        return out
+
+    # steps
+    def init(self, n, P, stream=None):
+        _check(self.lib.cc_init(self._h, n, _dptr(P, _ID), _stream(stream)), "cc_init")
+
+    def zroot(self, edges, n, flags=0, zroot_hint=0, stream=None):
+        m = edges.shape[0]
+        _check(self.lib.cc_zroot(self._h, n, m, _dptr(edges, _ID), flags, zroot_hint,
+                                 _stream(stream)), "cc_zroot")
+
+    def get_zroot(self, stream=None) -> int:
+        z = ctypes.c_uint32(0)
+        _check(self.lib.cc_get_zroot(self._h, _stream(stream), ctypes.byref(z)), "cc_get_zroot")
+        return int(z.value)
+
+    def push(self, edges, n, P, stream=None):
+        _check(self.lib.cc_push(self._h, n, edges.shape[0], _dptr(edges, _ID), _dptr(P, _ID),
+                                _stream(stream)), "cc_push")
+
+    def hook(self, edges, n, P, flags=0, stream=None):
+        _check(self.lib.cc_hook(self._h, n, edges.shape[0], _dptr(edges, _ID), _dptr(P, _ID), flags,
+                                _stream(stream)), "cc_hook")
+
+    def compress(self, n, P, flags=0, stream=None):
+        _check(self.lib.cc_compress(self._h, n, _dptr(P, _ID), flags, _stream(stream)), "cc_compress")
+
+    def canon(self, n, L, stream=None):
+        _check(self.lib.cc_canon(self._h, n, _dptr(L, _ID), _stream(stream)), "cc_canon")
+
+    # batch
+    def batch(self, vtx_off, edge_off, edges, L=None, status=None, stream=None):
+        G = vtx_off.numel() - 1
+        if L is None:
+            L = torch.empty(int(vtx_off[-1].item()), dtype=torch.int32, device=edges.device)
+        if status is None:
+            status = torch.empty(G, dtype=torch.int32, device=edges.device)
+        _check(self.lib.cc_batch(self._h, G, _dptr(vtx_off, (torch.int64,)),
+                                 _dptr(edge_off, (torch.int64,)), _dptr(edges, (torch.int32,)),
+                                 _dptr(L, (torch.int32,)), _dptr(status, (torch.int32,)),
+                                 _stream(stream)), "cc_batch")
+        return L, status
+
+
+class Server:
+    """cc_serve_*: continuous batching of CC requests held in host memory."""
+
+    def __init__(self, ctx: Context, max_inflight=0, queue_capacity=0, streams=0, small_n=0,
+                 hbm_budget=0):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        o = _ServeOpts(max_inflight, queue_capacity, streams, small_n, hbm_budget)
+        h = ctypes.c_void_p()
+        _check(self.lib.cc_serve_open(ctx.handle, ctypes.byref(o), ctypes.byref(h)), "cc_serve_open")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, edges_host, n: int, L_host, flags: int = 0) -> int:
+        """edges_host: numpy (m, 2) uint32 C-contiguous; L_host: numpy uint32[n] (written)."""
+        import numpy as np
+        assert edges_host.dtype == np.uint32 and edges_host.flags.c_contiguous
+        assert L_host.dtype == np.uint32 and L_host.flags.c_contiguous and len(L_host) >= n
+        t = ctypes.c_uint64(0)
+        m = edges_host.shape[0]
+        rc = self.lib.cc_serve_submit(self._h, n, m, edges_host.ctypes.data if m else None,
+                                      L_host.ctypes.data if n else None, flags, ctypes.byref(t))
+        if rc != CC_OK:
+            raise CCError(rc, "cc_serve_submit")
+        self._keep[t.value] = (edges_host, L_host)
+        return t.value
+
+    def wait(self, ticket: int, timeout_us: int = -1):
+        st = ReqStats()
+        rc = self.lib.cc_serve_wait(self._h, ticket, timeout_us, ctypes.byref(st))
+        if rc != CC_ETIMEDOUT:
+            self._keep.pop(ticket, None)
+        return rc, st
+
+    def close(self):
+        if self._h:
+            _check(self.lib.cc_serve_close(self._h), "cc_serve_close")
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

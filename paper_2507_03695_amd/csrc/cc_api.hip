@@ -1,0 +1,313 @@
+// cc_api.hip — the C ABI of include/cc.h: contexts, argument checks, the
+// single-graph entry points and the step entry points.
+#include <mutex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "cc_internal.h"
+
+struct cc_ctx {
+    int device = 0;
+    ccm::Slot slot;
+    uint64_t hbm_budget = 0;
+    uint32_t samples = 0;
+};
+
+namespace ccm {
+
+static thread_local std::string t_detail;
+
+int fail(int code, const std::string& detail) {
+    t_detail = detail;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    t_detail = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+    return CC_EDEVICE;
+}
+
+int device_cu_count(int device) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        return 256;
+    return cus > 0 ? cus : 256;
+}
+
+static uint32_t next_pow2(uint64_t x) {
+    uint32_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+int slot_create(Slot* s, int device, uint32_t samples) {
+    *s = Slot{};
+    s->device = device;
+    s->samples = samples;
+    s->table = next_pow2(4ull * samples);
+    if (s->table < 1024) s->table = 1024;
+    CCM_HIP(hipSetDevice(device));
+    size_t bytes = sizeof(DevState) + 2ull * s->table * sizeof(uint32_t);
+    char* base = nullptr;
+    hipError_t e = hipMalloc(&base, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(CC_ENOMEM, "slot scratch allocation failed");
+    }
+    s->st = reinterpret_cast<DevState*>(base);
+    s->hkeys = reinterpret_cast<uint32_t*>(base + sizeof(DevState));
+    s->hcounts = s->hkeys + s->table;
+    CCM_HIP(hipMemset(s->st, 0, sizeof(DevState)));
+    e = hipHostMalloc(&s->host_status, sizeof(uint32_t), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        hipFree(base);
+        s->st = nullptr;
+        return fail(CC_ENOMEM, "pinned host status allocation failed");
+    }
+    *s->host_status = 0;
+    CCM_HIP(hipDeviceSynchronize());
+    return CC_OK;
+}
+
+void slot_destroy(Slot* s) {
+    if (!s) return;
+    if (hipSetDevice(s->device) != hipSuccess) return;
+    (void)hipDeviceSynchronize();
+    if (s->st) (void)hipFree(s->st);
+    if (s->deg) (void)hipFree(s->deg);
+    batch_scratch_free(&s->batch);
+    if (s->host_status) (void)hipHostFree(s->host_status);
+    *s = Slot{};
+}
+
+__global__ void k_status_take(DevState* st, uint32_t* out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *out = st->status;
+        st->status = 0;
+    }
+}
+
+int slot_sync(Slot* s, hipStream_t stream) {
+    // read-and-clear in one kernel writing to pinned host memory
+    k_status_take<<<1, 64, 0, stream>>>(s->st, s->host_status);
+    CCM_HIP(hipGetLastError());
+    CCM_HIP(hipStreamSynchronize(stream));
+    const uint32_t w = __atomic_load_n(s->host_status, __ATOMIC_ACQUIRE);
+    if (w & kStatusRange) return fail(CC_ERANGE, "an endpoint is >= n");
+    return CC_OK;
+}
+
+}  // namespace ccm
+
+using namespace ccm;
+
+// ---- errors / version -------------------------------------------------------------------
+
+extern "C" const char* cc_strerror(int code) {
+    switch (code) {
+        case CC_OK: return "CC_OK";
+        case CC_EINVAL: return "CC_EINVAL: invalid argument";
+        case CC_ERANGE: return "CC_ERANGE: vertex ID out of range";
+        case CC_ENOMEM: return "CC_ENOMEM: out of device memory or budget";
+        case CC_EDEVICE: return "CC_EDEVICE: HIP runtime error";
+        case CC_EAGAIN: return "CC_EAGAIN: queue full";
+        case CC_ECANCELED: return "CC_ECANCELED: cancelled";
+        case CC_ETIMEDOUT: return "CC_ETIMEDOUT: timed out";
+        default: return "unknown status";
+    }
+}
+
+extern "C" const char* cc_last_error_detail(void) { return t_detail.c_str(); }
+
+extern "C" int cc_version(void) { return 100; }
+
+// ---- contexts -----------------------------------------------------------------------------
+
+extern "C" int cc_create(cc_ctx** out, const cc_ctx_opts* opts) {
+    if (!out) return fail(CC_EINVAL, "out is NULL");
+    *out = nullptr;
+    int dev = opts ? opts->device : -1;
+    if (dev < 0) CCM_HIP(hipGetDevice(&dev));
+    int ndev = 0;
+    CCM_HIP(hipGetDeviceCount(&ndev));
+    if (dev >= ndev) return fail(CC_EINVAL, "device ordinal out of range");
+    uint32_t samples = (opts && opts->zroot_samples) ? opts->zroot_samples : 65536u;
+    if (samples > (1u << 24)) return fail(CC_EINVAL, "zroot_samples above 2^24");
+    cc_ctx* c = new cc_ctx();
+    c->device = dev;
+    c->samples = samples;
+    int rc = slot_create(&c->slot, dev, samples);
+    if (rc) { delete c; return rc; }
+    if (opts && opts->hbm_budget) c->hbm_budget = opts->hbm_budget;
+    else {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess) c->hbm_budget = fr / 4 * 3;
+        else c->hbm_budget = 1ull << 34;
+    }
+    *out = c;
+    return CC_OK;
+}
+
+namespace ccm {
+int ctx_info(cc_ctx* ctx, int* device, uint64_t* budget, uint32_t* samples) {
+    if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    *device = ctx->device;
+    *budget = ctx->hbm_budget;
+    *samples = ctx->samples;
+    return CC_OK;
+}
+}  // namespace ccm
+
+extern "C" void cc_destroy(cc_ctx* ctx) {
+    if (!ctx) return;
+    slot_destroy(&ctx->slot);
+    delete ctx;
+}
+
+namespace {
+std::mutex g_default_mu;
+cc_ctx* g_default[64] = {};
+
+int default_ctx(cc_ctx** out) {
+    int dev = 0;
+    CCM_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(CC_EINVAL, "device ordinal out of range");
+    std::lock_guard<std::mutex> lk(g_default_mu);
+    if (!g_default[dev]) {
+        cc_ctx_opts o{};
+        o.device = dev;
+        int rc = cc_create(&g_default[dev], &o);
+        if (rc) return rc;
+    }
+    *out = g_default[dev];
+    return CC_OK;
+}
+
+int check_graph(uint64_t n, uint64_t m, const void* edges, const void* L) {
+    if (n > 0xFFFFFFFFull) return fail(CC_EINVAL, "n must be < 2^32");
+    if (m && !edges) return fail(CC_EINVAL, "edge_list is NULL with m > 0");
+    if (n && !L) return fail(CC_EINVAL, "L is NULL with n > 0");
+    if (n == 0 && m) return fail(CC_ERANGE, "entries given for an empty vertex set");
+    if (m > (1ull << 40)) return fail(CC_EINVAL, "m above 2^40");
+    return CC_OK;
+}
+
+int set_dev(cc_ctx* ctx) {
+    CCM_HIP(hipSetDevice(ctx->device));
+    return CC_OK;
+}
+
+}  // namespace
+
+// ---- single graph ---------------------------------------------------------------------------
+
+extern "C" int cc_solve(uint64_t n, uint64_t m, const uint32_t* edge_list, uint32_t* L) {
+    int rc = check_graph(n, m, edge_list, L);
+    if (rc) return rc;
+    if (n == 0) return CC_OK;
+    cc_ctx* ctx = nullptr;
+    if ((rc = default_ctx(&ctx))) return rc;
+    std::lock_guard<std::mutex> lk(g_default_mu);  // the default slot is shared
+    if ((rc = run_solve(&ctx->slot, n, m, edge_list, L, 0, 0, nullptr))) return rc;
+    return slot_sync(&ctx->slot, nullptr);
+}
+
+extern "C" int cc_solve_async(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edge_list,
+                              uint32_t* L, uint32_t flags, uint32_t zroot_hint, void* stream) {
+    if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    int rc = check_graph(n, m, edge_list, L);
+    if (rc) return rc;
+    if ((flags & CC_F_ZROOT_HINT) && n && zroot_hint >= n)
+        return fail(CC_EINVAL, "zroot_hint must be < n");
+    if ((rc = set_dev(ctx))) return rc;
+    return run_solve(&ctx->slot, n, m, edge_list, L, flags, zroot_hint, (hipStream_t)stream);
+}
+
+extern "C" int cc_sync(cc_ctx* ctx, void* stream) {
+    if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    int rc = set_dev(ctx);
+    if (rc) return rc;
+    return slot_sync(&ctx->slot, (hipStream_t)stream);
+}
+
+// ---- steps -------------------------------------------------------------------------------------
+
+extern "C" int cc_init(cc_ctx* ctx, uint64_t n, uint32_t* P, void* stream) {
+    if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    int rc = check_graph(n, 0, nullptr, P);
+    if (rc || n == 0) return rc;
+    if ((rc = set_dev(ctx))) return rc;
+    return run_init(&ctx->slot, n, P, (hipStream_t)stream);
+}
+
+extern "C" int cc_zroot(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edges,
+                        uint32_t flags, uint32_t zroot_hint, void* stream) {
+    if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    int rc = check_graph(n, m, edges, (const void*)1);
+    if (rc) return rc;
+    if (n == 0) return fail(CC_EINVAL, "zero root of an empty vertex set");
+    if ((flags & CC_F_ZROOT_HINT) && zroot_hint >= n)
+        return fail(CC_EINVAL, "zroot_hint must be < n");
+    if ((rc = set_dev(ctx))) return rc;
+    return run_zroot(&ctx->slot, n, m, edges, flags, zroot_hint, (hipStream_t)stream);
+}
+
+extern "C" int cc_push(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
+                       void* stream) {
+    if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    int rc = check_graph(n, m, edges, P);
+    if (rc || n == 0) return rc;
+    if ((rc = set_dev(ctx))) return rc;
+    return run_push(&ctx->slot, n, m, edges, P, (hipStream_t)stream);
+}
+
+extern "C" int cc_hook(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
+                       uint32_t flags, void* stream) {
+    if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    int rc = check_graph(n, m, edges, P);
+    if (rc || n == 0) return rc;
+    if ((rc = set_dev(ctx))) return rc;
+    return run_hook(&ctx->slot, n, m, edges, P, flags, (hipStream_t)stream);
+}
+
+extern "C" int cc_compress(cc_ctx* ctx, uint64_t n, uint32_t* P, uint32_t flags, void* stream) {
+    if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    int rc = check_graph(n, 0, nullptr, P);
+    if (rc || n == 0) return rc;
+    if ((rc = set_dev(ctx))) return rc;
+    return run_compress(&ctx->slot, n, P, flags, (hipStream_t)stream);
+}
+
+extern "C" int cc_canon(cc_ctx* ctx, uint64_t n, uint32_t* L, void* stream) {
+    if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    int rc = check_graph(n, 0, nullptr, L);
+    if (rc || n == 0) return rc;
+    if ((rc = set_dev(ctx))) return rc;
+    return run_canon(&ctx->slot, n, L, (hipStream_t)stream);
+}
+
+extern "C" int cc_get_zroot(cc_ctx* ctx, void* stream, uint32_t* zroot_out) {
+    if (!ctx || !zroot_out) return fail(CC_EINVAL, "NULL argument");
+    int rc = set_dev(ctx);
+    if (rc) return rc;
+    CCM_HIP(hipMemcpyAsync(ctx->slot.host_status, &ctx->slot.st->zroot, sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, (hipStream_t)stream));
+    CCM_HIP(hipStreamSynchronize((hipStream_t)stream));
+    *zroot_out = *ctx->slot.host_status;
+    *ctx->slot.host_status = 0;
+    return CC_OK;
+}
+
+// ---- batch -------------------------------------------------------------------------------------
+
+extern "C" int cc_batch(cc_ctx* ctx, uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,
+                        const int32_t* edges, int32_t* L, int32_t* status, void* stream) {
+    if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    if (G == 0) return CC_OK;
+    if (!vtx_off || !edge_off || !status) return fail(CC_EINVAL, "NULL offsets or status");
+    int rc = set_dev(ctx);
+    if (rc) return rc;
+    return run_batch(&ctx->slot, G, vtx_off, edge_off, edges, L, status, (hipStream_t)stream);
+}

@@ -1,0 +1,104 @@
+// cc_internal.h — declarations shared by the library's own translation units.
+// Not installed; the public interface is include/cc.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include <string>
+
+#include "cc.h"
+
+namespace ccm {
+
+// Device-resident state of one solve slot (a context has one; the server one per
+// slot). Lives in device memory; kernels read and update it, the host reads it
+// only through explicit copies.
+struct DevState {
+    uint32_t status;    // bit 0: an endpoint >= n was seen
+    uint32_t minz;      // smallest vertex whose root is the zero root (compress)
+    uint32_t zroot;     // the zero root chosen for the current solve
+    uint32_t pad0;
+    uint64_t zsel;      // packed argmax (count << 32) | (0xFFFFFFFF - id); 0 = none
+    uint64_t pad1[5];
+};
+static_assert(sizeof(DevState) == 64, "DevState is one 64-byte block");
+
+constexpr uint32_t kStatusRange = 1u;
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+
+// One graph of a batched launch: where its entries and labels live.
+struct GraphDesc {
+    const int32_t* edges;   // 2*m int32, local IDs
+    int32_t* L;             // n int32 labels (also the parent array when it is not in LDS)
+    int32_t* status;        // where the graph's status code goes
+    uint32_t n;
+    uint32_t pad;
+    int64_t m;
+};
+static_assert(sizeof(GraphDesc) == 40, "GraphDesc layout");
+
+// Scratch of the batched path: descriptors, largest-first order and the work
+// ticket, uploaded in one copy per launch.
+struct BatchScratch {
+    char* dev = nullptr;       // device: [ticket: 256 B][order: 4G][descs: 40G]
+    char* host = nullptr;      // pinned host staging of the same layout
+    uint64_t cap = 0;          // graphs
+};
+
+// Scratch owned by one slot.
+struct Slot {
+    int device = 0;
+    DevState* st = nullptr;        // device
+    uint32_t* hkeys = nullptr;     // device, zroot hash table keys   [table]
+    uint32_t* hcounts = nullptr;   // device, zroot hash table counts [table]
+    uint32_t table = 0;            // power of two >= 4 * samples
+    uint32_t samples = 0;          // K
+    uint32_t* deg = nullptr;       // device, exact-degree counts (grown on demand)
+    uint64_t deg_cap = 0;
+    uint32_t* host_status = nullptr;  // pinned host word
+    BatchScratch batch;
+};
+
+int slot_create(Slot* s, int device, uint32_t samples);
+void slot_destroy(Slot* s);
+
+// Enqueue steps (arguments already validated by the caller).
+int run_init(Slot* s, uint64_t n, uint32_t* P, hipStream_t stream);
+int run_zroot(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t flags,
+              uint32_t hint, hipStream_t stream);
+int run_push(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
+             hipStream_t stream);
+int run_hook(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
+             uint32_t flags, hipStream_t stream);
+int run_compress(Slot* s, uint64_t n, uint32_t* P, uint32_t flags, hipStream_t stream);
+int run_canon(Slot* s, uint64_t n, uint32_t* L, hipStream_t stream);
+int run_solve(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* L,
+              uint32_t flags, uint32_t hint, hipStream_t stream);
+// Copy the status word to the host, clear it, wait for the stream; CC_OK/CC_ERANGE.
+int slot_sync(Slot* s, hipStream_t stream);
+
+// Batched path (cc_batch.hip).
+// Enqueue one persistent launch over G graphs described on the host.
+int launch_batch(Slot* s, uint32_t G, const GraphDesc* descs, hipStream_t stream);
+// cc_batch: offsets in device memory; synchronous.
+int run_batch(Slot* s, uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,
+              const int32_t* edges, int32_t* L, int32_t* status, hipStream_t stream);
+void batch_scratch_free(BatchScratch* b);
+
+// Error reporting.
+int fail(int code, const std::string& detail);
+int hip_fail(hipError_t e, const char* what);
+#define CCM_HIP(call)                                             \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) return ::ccm::hip_fail(e_, #call);  \
+    } while (0)
+
+int device_cu_count(int device);
+
+// Device, memory budget and zero-root sample count of a context.
+int ctx_info(cc_ctx* ctx, int* device, uint64_t* budget, uint32_t* samples);
+
+}  // namespace ccm

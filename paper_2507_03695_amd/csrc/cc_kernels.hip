@@ -1,0 +1,408 @@
+// cc_kernels.hip — the single-graph path on gfx950: init, zero root, Initial
+// Push, hook, compress (pointer jumping) and the zero-component relabelling.
+//
+// Memory model. P is one uint32 array shared by every wave of the device
+// (Sec. I: one shared array per machine instead of per-core copies). Links
+// are made only by device-scope compare-and-swap on a root's own entry, so
+// two workers can never both hook the same root. Parent reads are ordinary
+// L2-cached loads: on a multi-XCD device another XCD's L2 may hold an older
+// value, but every value an entry ever holds is an ancestor of that vertex
+// (an entry changes from itself to a root of smaller key when hooked, and
+// afterwards only to further ancestors by path splitting), so a stale read
+// walks a shorter prefix of the true path. A stale "root" is caught by the
+// CAS, which fails and returns the current parent; the walk resumes there
+// (Sec. II: a failed CAS repeats the root search). Splitting stores go only
+// to non-roots, which no CAS can succeed on, so they never race with links.
+#include "cc_internal.h"
+
+namespace ccm {
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBlock = 256;
+
+// ---- keys: Formula 1's R used as an order while P stores vertex IDs ----------
+// key(x) = x on the plain path; with a zero root z, key(z) = 0 and key(x) = x+1.
+template <bool ZR>
+__device__ __forceinline__ bool key_less(uint32_t a, uint32_t b, uint32_t z) {
+    if (ZR) return (a == z) | ((b != z) & (a < b));
+    return a < b;
+}
+
+// ---- init --------------------------------------------------------------------
+// P_v = v (Algorithm 1 / 3 initialisation; with R the stored values stay vertex
+// IDs and only the order changes). 16-byte stores when P is 16-byte aligned.
+__global__ __launch_bounds__(kBlock) void k_init(uint32_t* __restrict__ P, uint64_t n,
+                                                 DevState* st, int vec) {
+    const uint64_t tid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    if (tid == 0) st->minz = kEmpty;
+    if (vec) {
+        const uint64_t n4 = n >> 2;
+        u32x4* P4 = reinterpret_cast<u32x4*>(P);
+        for (uint64_t i = tid; i < n4; i += stride) {
+            uint32_t b = (uint32_t)(i << 2);
+            u32x4 val = {b, b + 1, b + 2, b + 3};
+            __builtin_nontemporal_store(val, P4 + i);
+        }
+        for (uint64_t v = (n4 << 2) + tid; v < n; v += stride) P[v] = (uint32_t)v;
+    } else {
+        for (uint64_t v = tid; v < n; v += stride) P[v] = (uint32_t)v;
+    }
+}
+
+// ---- zero root: sampled endpoint counts in an open-addressing table ----------
+
+__device__ __forceinline__ uint64_t sample_index(uint64_t j, uint64_t m, uint64_t K) {
+    // floor(j*m/K) without 128-bit arithmetic: m = q*K + r
+    const uint64_t q = m / K, r = m % K;
+    return j * q + (j * r) / K;
+}
+
+__global__ __launch_bounds__(kBlock) void k_zfill(uint32_t* keys, uint32_t* counts, uint32_t T,
+                                                  DevState* st) {
+    uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i == 0) st->zsel = 0;
+    for (; i < T; i += gridDim.x * kBlock) { keys[i] = kEmpty; counts[i] = 0; }
+}
+
+__device__ __forceinline__ void table_add(uint32_t* keys, uint32_t* counts, uint32_t mask,
+                                          uint32_t x) {
+    uint32_t h = (x * 0x9E3779B1u) & mask;
+    while (true) {
+        uint32_t k = keys[h];
+        if (k == kEmpty) {
+            k = atomicCAS(&keys[h], kEmpty, x);
+            if (k == kEmpty) k = x;
+        }
+        if (k == x) { atomicAdd(&counts[h], 1u); return; }
+        h = (h + 1) & mask;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_zcount(const uint32_t* __restrict__ edges, uint64_t m,
+                                                   uint64_t K, uint64_t cnt, uint64_t n,
+                                                   uint32_t* keys, uint32_t* counts, uint32_t mask,
+                                                   DevState* st) {
+    for (uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < cnt;
+         j += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t i = (cnt == m) ? j : sample_index(j, m, K);
+        const uint32_t u = edges[2 * i], v = edges[2 * i + 1];
+        if (u >= n || v >= n) { atomicOr(&st->status, kStatusRange); continue; }
+        if (u == v) continue;
+        table_add(keys, counts, mask, u);
+        table_add(keys, counts, mask, v);
+    }
+}
+
+// Exact degree: dense counts over all entries.
+__global__ __launch_bounds__(kBlock) void k_degfill(uint32_t* deg, uint64_t n, DevState* st) {
+    uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i == 0) st->zsel = 0;
+    for (; i < n; i += (uint64_t)gridDim.x * kBlock) deg[i] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_degcount(const uint32_t* __restrict__ edges, uint64_t m,
+                                                     uint64_t n, uint32_t* deg, DevState* st) {
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
+         i += (uint64_t)gridDim.x * kBlock) {
+        const uint32_t u = edges[2 * i], v = edges[2 * i + 1];
+        if (u >= n || v >= n) { atomicOr(&st->status, kStatusRange); continue; }
+        if (u == v) continue;
+        atomicAdd(&deg[u], 1u);
+        atomicAdd(&deg[v], 1u);
+    }
+}
+
+__device__ __forceinline__ uint64_t pack_sel(uint32_t count, uint32_t id) {
+    return count ? ((uint64_t)count << 32) | (uint64_t)(0xFFFFFFFFu - id) : 0;
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t x) {
+    for (int off = 32; off > 0; off >>= 1) {
+        uint64_t y = __shfl_xor(x, off, 64);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+    for (int off = 32; off > 0; off >>= 1) {
+        uint32_t y = __shfl_xor(x, off, 64);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+// argmax over (count desc, id asc); ids come from a table (keys != nullptr) or
+// are the indices of a dense count array.
+__global__ __launch_bounds__(kBlock) void k_zargmax(const uint32_t* keys, const uint32_t* counts,
+                                                    uint64_t T, DevState* st) {
+    uint64_t best = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < T;
+         i += (uint64_t)gridDim.x * kBlock) {
+        uint32_t id = keys ? keys[i] : (uint32_t)i;
+        uint32_t c = counts[i];
+        if (id != kEmpty || !keys) {
+            uint64_t s = pack_sel(c, id);
+            best = s > best ? s : best;
+        }
+    }
+    best = wave_max_u64(best);
+    if ((threadIdx.x & 63) == 0 && best) atomicMax((unsigned long long*)&st->zsel,
+                                                   (unsigned long long)best);
+}
+
+__global__ void k_zfinish(DevState* st, int use_hint, uint32_t hint) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        uint32_t z;
+        if (use_hint) z = hint;
+        else {
+            uint64_t s = st->zsel;
+            z = s ? 0xFFFFFFFFu - (uint32_t)(s & 0xFFFFFFFFu) : 0u;
+        }
+        st->zroot = z;
+    }
+}
+
+// ---- Initial Push -------------------------------------------------------------
+// For sampled entries (x, z) / (z, x) with x != z: P_x = z. Every x is still a
+// root (run right after init), z has the smallest key, and all writers store
+// the same value, so plain stores suffice.
+__global__ __launch_bounds__(kBlock) void k_push(const uint32_t* __restrict__ edges, uint64_t m,
+                                                 uint64_t K, uint64_t cnt, uint64_t n,
+                                                 uint32_t* P, DevState* st) {
+    const uint32_t z = st->zroot;
+    for (uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < cnt;
+         j += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t i = (cnt == m) ? j : sample_index(j, m, K);
+        const uint32_t u = edges[2 * i], v = edges[2 * i + 1];
+        if (u >= n || v >= n || u == v) continue;
+        if (u == z) P[v] = z;
+        else if (v == z) P[u] = z;
+    }
+}
+
+// ---- hook ---------------------------------------------------------------------
+
+// Root of x, given px = a value read from P[x]. SPLIT = 1: path splitting (each
+// visited vertex takes its grandparent); SPLIT = 0: plain walk.
+template <int SPLIT>
+__device__ __forceinline__ uint32_t find_root(uint32_t* P, uint32_t x, uint32_t px) {
+    while (px != x) {
+        const uint32_t gp = P[px];
+        if (gp == px) return px;
+        if (SPLIT) P[x] = gp;
+        x = px;
+        px = gp;
+    }
+    return x;
+}
+
+// Algorithm 1 / 3 hooking of one entry whose endpoints u, v have parents pu, pv.
+template <bool ZR, int SPLIT>
+__device__ __forceinline__ void link(uint32_t* P, uint32_t u, uint32_t pu, uint32_t v,
+                                     uint32_t pv, uint32_t z) {
+    while (true) {
+        const uint32_t ru = find_root<SPLIT>(P, u, pu);
+        const uint32_t rv = find_root<SPLIT>(P, v, pv);
+        if (ru == rv) return;
+        const bool u_low = key_less<ZR>(ru, rv, z);
+        const uint32_t hi = u_low ? rv : ru;
+        const uint32_t lo = u_low ? ru : rv;
+        const uint32_t old = atomicCAS(&P[hi], hi, lo);
+        if (old == hi) return;
+        // hi was linked by someone else: its current parent is `old`
+        u = hi; pu = old;
+        v = lo; pv = lo;
+    }
+}
+
+constexpr int kEPT = 4;  // entries per thread per tile
+
+template <bool ZR, int SPLIT>
+__global__ __launch_bounds__(kBlock) void k_hook(const uint32_t* __restrict__ edges, uint64_t m,
+                                                 uint32_t n, uint32_t* P, DevState* st) {
+    const uint32_t z = ZR ? st->zroot : 0u;
+    const uint64_t tile = (uint64_t)blockIdx.x * (kBlock * kEPT);
+    const u32x2* E = reinterpret_cast<const u32x2*>(edges);
+    uint32_t u[kEPT], v[kEPT];
+#pragma unroll
+    for (int k = 0; k < kEPT; ++k) {
+        const uint64_t e = tile + (uint64_t)k * kBlock + threadIdx.x;
+        u32x2 uv = {0u, 0u};
+        if (e < m) uv = __builtin_nontemporal_load(E + e);
+        u[k] = uv.x;
+        v[k] = uv.y;
+    }
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < kEPT; ++k) {
+        if (u[k] >= n || v[k] >= n) { bad = true; u[k] = v[k] = 0; }
+    }
+    if (bad) atomicOr(&st->status, kStatusRange);
+    uint32_t pu[kEPT], pv[kEPT];
+#pragma unroll
+    for (int k = 0; k < kEPT; ++k) {
+        pu[k] = u[k] != v[k] ? P[u[k]] : 0u;
+        pv[k] = u[k] != v[k] ? P[v[k]] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kEPT; ++k) {
+        // a common parent, or one endpoint the parent of the other: same tree
+        if (u[k] == v[k] || pu[k] == pv[k] || pu[k] == v[k] || pv[k] == u[k]) continue;
+        link<ZR, SPLIT>(P, u[k], pu[k], v[k], pv[k], z);
+    }
+}
+
+// ---- compress (pointer jumping) ----------------------------------------------------
+// P_v <- root(v). Roots are fixed during this kernel, so every walk ends at the
+// true root. With a zero root, also the smallest v whose root is z.
+template <bool ZR>
+__global__ __launch_bounds__(kBlock) void k_compress(uint32_t* P, uint64_t n, DevState* st) {
+    const uint32_t z = ZR ? st->zroot : 0u;
+    uint32_t local_min = kEmpty;
+    for (uint64_t v = (uint64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
+         v += (uint64_t)gridDim.x * kBlock) {
+        const uint32_t p = P[v];
+        uint32_t r = (uint32_t)v;
+        if (p != (uint32_t)v) {
+            r = p;
+            uint32_t q = P[r];
+            while (q != r) { r = q; q = P[r]; }
+            if (r != p) P[v] = r;
+        }
+        if (ZR && r == z && (uint32_t)v < local_min) local_min = (uint32_t)v;
+    }
+    if (ZR) {
+        local_min = wave_min_u32(local_min);
+        if ((threadIdx.x & 63) == 0 && local_min != kEmpty) atomicMin(&st->minz, local_min);
+    }
+}
+
+// ---- relabel the zero root's component to its smallest ID ---------------------------
+__global__ __launch_bounds__(kBlock) void k_canon(uint32_t* L, uint64_t n, const DevState* st) {
+    const uint32_t z = st->zroot, mz = st->minz;
+    if (mz == z || mz == kEmpty) return;
+    for (uint64_t v = (uint64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
+         v += (uint64_t)gridDim.x * kBlock) {
+        if (L[v] == z) L[v] = mz;
+    }
+}
+
+// ---- host-side launchers ---------------------------------------------------------------
+
+static uint32_t grid_for(uint64_t work, uint64_t per_block, uint32_t cap) {
+    uint64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    return (uint32_t)(g < cap ? g : cap);
+}
+
+constexpr uint32_t kGridCap = 256 * 32;
+
+int run_init(Slot* s, uint64_t n, uint32_t* P, hipStream_t stream) {
+    int vec = ((uintptr_t)P & 15) == 0;
+    k_init<<<grid_for(n, kBlock * 4, kGridCap), kBlock, 0, stream>>>(P, n, s->st, vec);
+    CCM_HIP(hipGetLastError());
+    return CC_OK;
+}
+
+static uint64_t sample_count(uint64_t m, uint64_t K) { return m <= K ? m : K; }
+
+int run_zroot(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t flags,
+              uint32_t hint, hipStream_t stream) {
+    if (flags & CC_F_ZROOT_HINT) {
+        k_zfinish<<<1, 64, 0, stream>>>(s->st, 1, hint);
+        CCM_HIP(hipGetLastError());
+        return CC_OK;
+    }
+    if (flags & CC_F_ZROOT_EXACT) {
+        if (s->deg_cap < n) {
+            if (s->deg) CCM_HIP(hipFree(s->deg));
+            s->deg = nullptr;
+            s->deg_cap = 0;
+            if (hipMalloc(&s->deg, n * sizeof(uint32_t)) != hipSuccess) {
+                (void)hipGetLastError();
+                s->deg = nullptr;
+                return fail(CC_ENOMEM, "exact-degree scratch allocation failed");
+            }
+            s->deg_cap = n;
+        }
+        k_degfill<<<grid_for(n, kBlock, kGridCap), kBlock, 0, stream>>>(s->deg, n, s->st);
+        if (m) k_degcount<<<grid_for(m, kBlock, kGridCap), kBlock, 0, stream>>>(edges, m, n, s->deg, s->st);
+        k_zargmax<<<grid_for(n, kBlock, kGridCap), kBlock, 0, stream>>>(nullptr, s->deg, n, s->st);
+    } else {
+        const uint64_t K = s->samples;
+        const uint64_t cnt = sample_count(m, K);
+        k_zfill<<<grid_for(s->table, kBlock, 1024), kBlock, 0, stream>>>(s->hkeys, s->hcounts,
+                                                                          s->table, s->st);
+        if (cnt)
+            k_zcount<<<grid_for(cnt, kBlock, 1024), kBlock, 0, stream>>>(
+                edges, m, K, cnt, n, s->hkeys, s->hcounts, s->table - 1, s->st);
+        k_zargmax<<<grid_for(s->table, kBlock, 1024), kBlock, 0, stream>>>(s->hkeys, s->hcounts,
+                                                                            s->table, s->st);
+    }
+    k_zfinish<<<1, 64, 0, stream>>>(s->st, 0, 0);
+    CCM_HIP(hipGetLastError());
+    return CC_OK;
+}
+
+int run_push(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
+             hipStream_t stream) {
+    const uint64_t K = s->samples;
+    const uint64_t cnt = sample_count(m, K);
+    if (!cnt) return CC_OK;
+    k_push<<<grid_for(cnt, kBlock, 1024), kBlock, 0, stream>>>(edges, m, K, cnt, n, P, s->st);
+    CCM_HIP(hipGetLastError());
+    return CC_OK;
+}
+
+int run_hook(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
+             uint32_t flags, hipStream_t stream) {
+    if (!m) return CC_OK;
+    const uint64_t per = (uint64_t)kBlock * kEPT;
+    const uint64_t blocks = (m + per - 1) / per;
+    if (blocks > 0x7FFFFFFFull) return fail(CC_EINVAL, "edge count too large for one launch");
+    const bool zr = flags & CC_F_ZROOT;
+    const bool split = !(flags & CC_F_NO_SPLIT);
+    const uint32_t n32 = (uint32_t)n;
+    if (zr && split) k_hook<true, 1><<<(uint32_t)blocks, kBlock, 0, stream>>>(edges, m, n32, P, s->st);
+    else if (zr) k_hook<true, 0><<<(uint32_t)blocks, kBlock, 0, stream>>>(edges, m, n32, P, s->st);
+    else if (split) k_hook<false, 1><<<(uint32_t)blocks, kBlock, 0, stream>>>(edges, m, n32, P, s->st);
+    else k_hook<false, 0><<<(uint32_t)blocks, kBlock, 0, stream>>>(edges, m, n32, P, s->st);
+    CCM_HIP(hipGetLastError());
+    return CC_OK;
+}
+
+int run_compress(Slot* s, uint64_t n, uint32_t* P, uint32_t flags, hipStream_t stream) {
+    const uint32_t g = grid_for(n, kBlock, kGridCap);
+    if (flags & CC_F_ZROOT) k_compress<true><<<g, kBlock, 0, stream>>>(P, n, s->st);
+    else k_compress<false><<<g, kBlock, 0, stream>>>(P, n, s->st);
+    CCM_HIP(hipGetLastError());
+    return CC_OK;
+}
+
+int run_canon(Slot* s, uint64_t n, uint32_t* L, hipStream_t stream) {
+    k_canon<<<grid_for(n, kBlock, kGridCap), kBlock, 0, stream>>>(L, n, s->st);
+    CCM_HIP(hipGetLastError());
+    return CC_OK;
+}
+
+int run_solve(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* L,
+              uint32_t flags, uint32_t hint, hipStream_t stream) {
+    if (n == 0) return CC_OK;
+    int rc;
+    if ((rc = run_init(s, n, L, stream))) return rc;
+    if (flags & CC_F_ZROOT) {
+        if ((rc = run_zroot(s, n, m, edges, flags, hint, stream))) return rc;
+        if ((rc = run_push(s, n, m, edges, L, stream))) return rc;
+    }
+    if ((rc = run_hook(s, n, m, edges, L, flags, stream))) return rc;
+    if ((rc = run_compress(s, n, L, flags, stream))) return rc;
+    if (flags & CC_F_ZROOT)
+        if ((rc = run_canon(s, n, L, stream))) return rc;
+    return CC_OK;
+}
+
+}  // namespace ccm

@@ -1,0 +1,43 @@
+"""Helpers shared by the GPU tests: moving seeded inputs to the device and
+checking labels against the oracle and against properties that hold at any size."""
+import sys
+
+import numpy as np
+import torch
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(edges: np.ndarray) -> torch.Tensor:
+    """(m, 2) uint32 numpy -> (m, 2) int32 device tensor with the same bits."""
+    e = np.ascontiguousarray(edges.reshape(-1, 2))
+    if e.dtype == np.uint32:
+        e = e.view(np.int32)
+    return torch.from_numpy(e).cuda()
+
+
+def to_host_u32(L: torch.Tensor) -> np.ndarray:
+    return L.cpu().numpy().view(np.uint32)
+
+
+def assert_same_labels(got: np.ndarray, want: np.ndarray, what: str):
+    if not np.array_equal(got, want):
+        bad = np.flatnonzero(got != want)
+        raise AssertionError(f"{what}: {len(bad)} labels differ; first at v={bad[0]}: "
+                             f"got {got[bad[0]]}, want {want[bad[0]]}")
+
+
+def check_properties_on_device(edges_dev: torch.Tensor, L_dev: torch.Tensor, n: int):
+    """Every entry's endpoints share a label, L_v <= v, L_{L_v} = L_v (device-side)."""
+    L = L_dev.to(torch.int64) & 0xFFFFFFFF
+    E = edges_dev.to(torch.int64) & 0xFFFFFFFF
+    step = 1 << 26
+    for a in range(0, E.shape[0], step):
+        blk = E[a:a + step]
+        assert torch.equal(L[blk[:, 0]], L[blk[:, 1]]), "an entry's endpoints differ in label"
+    ar = torch.arange(n, device=L.device, dtype=torch.int64)
+    assert bool((L <= ar).all()), "a label exceeds its vertex"
+    assert torch.equal(L[L], L), "a label is not a fixed point"

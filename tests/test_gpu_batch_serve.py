@@ -1,0 +1,151 @@
+"""GPU parity of the batched launch (cc_batch) and the continuous-batching server
+(cc_serve_*): every graph's labels equal the oracle's and equal cc_solve on the
+graph alone, whatever the mix it ran in."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import graphgen
+import oracle
+from gpu_helpers import assert_same_labels, log, to_dev, to_host_u32
+
+pytestmark = pytest.mark.gpu
+
+cc = pytest.importorskip("paper_2507_03695_amd")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = cc.Context()
+    yield c
+    c.close()
+
+
+def batch_to_dev(b):
+    return (torch.from_numpy(b.vtx_off).cuda(), torch.from_numpy(b.edge_off).cuda(),
+            torch.from_numpy(np.ascontiguousarray(b.edges)).cuda())
+
+
+def test_batch_small_mix(ctx):
+    b = graphgen.batch(300, 17, lg_n_lo=0, lg_n_hi=13, deg_lo=0, deg_hi=20)
+    vo, eo, ed = batch_to_dev(b)
+    L, st = ctx.batch(vo, eo, ed)
+    want, wst = oracle.cc_labels_batch(b.vtx_off, b.edge_off, b.edges)
+    assert np.array_equal(st.cpu().numpy(), wst)
+    assert_same_labels(L.cpu().numpy().view(np.uint32), want.view(np.uint32), "batch small mix")
+
+
+def test_batch_handles_hbm_resident_graphs(ctx):
+    """Graphs above the LDS capacity keep their parent array in HBM."""
+    graphs = [(graphgen.rmat(17, 1 << 19, 3 + i) % (90_000 + i), 90_000 + i) for i in range(3)]
+    graphs += [(graphgen.er(200, 150, 9), 200), (np.zeros((0, 2), np.uint32), 5),
+               (graphgen.er(1 << 16, 1 << 18, 10), 1 << 16)]
+    b = graphgen.batch_from_graphs(graphs)
+    vo, eo, ed = batch_to_dev(b)
+    L, st = ctx.batch(vo, eo, ed)
+    want, _ = oracle.cc_labels_batch(b.vtx_off, b.edge_off, b.edges)
+    assert np.all(st.cpu().numpy() == 0)
+    assert_same_labels(L.cpu().numpy().view(np.uint32), want.view(np.uint32), "batch big graphs")
+
+
+def test_batch_per_graph_status(ctx):
+    graphs = [(np.array([[0, 1], [1, 2]], np.uint32), 3), (np.array([[0, 7]], np.uint32), 4),
+              (np.array([[3, 2]], np.uint32), 4)]
+    b = graphgen.batch_from_graphs(graphs)
+    vo, eo, ed = batch_to_dev(b)
+    L, st = ctx.batch(vo, eo, ed)
+    assert st.cpu().tolist() == [cc.CC_OK, cc.CC_ERANGE, cc.CC_OK]
+    Lh = L.cpu().numpy()
+    assert Lh[0:3].tolist() == [0, 0, 0]
+    assert Lh[7:11].tolist() == [0, 1, 2, 2]
+
+
+def test_batch_4096_full(ctx):
+    b = graphgen.batch_4096()
+    log(f"batch generated: G={b.G} sum n={b.vtx_off[-1]} sum m={b.edge_off[-1]}")
+    vo, eo, ed = batch_to_dev(b)
+    L, st = ctx.batch(vo, eo, ed)
+    want, wst = oracle.cc_labels_batch(b.vtx_off, b.edge_off, b.edges)
+    log("batch oracle done")
+    assert np.array_equal(st.cpu().numpy(), wst)
+    Lh = L.cpu().numpy().view(np.uint32)
+    assert_same_labels(Lh, want.view(np.uint32), "batch 4096")
+    # the same graphs alone through cc_solve
+    for g in list(range(0, b.G, 97)):
+        e, n = b.graph(g)
+        alone = to_host_u32(ctx.solve(to_dev(e.view(np.uint32)), n))
+        assert_same_labels(Lh[b.vtx_off[g]:b.vtx_off[g + 1]], alone, f"graph {g} alone")
+
+
+def _requests(count, seed, hi=2.0**17):
+    reqs = graphgen.serve_stream(count, seed, rate_per_s=1e9, hi=hi)
+    out = []
+    for r in reqs:
+        e = np.ascontiguousarray(r.edges().view(np.uint32).reshape(-1, 2))
+        out.append((e, r.n))
+    return out
+
+
+def test_serve_mix_equals_alone(ctx):
+    reqs = _requests(120, 5)
+    # two large ones that take the single-graph path
+    reqs.append((graphgen.rmat(18, 1 << 21, 1), 1 << 18))
+    reqs.append((graphgen.er(200_000, 400_000, 2), 200_000))
+    srv = cc.Server(ctx, streams=4, small_n=65536)
+    outs, tickets = [], []
+    for e, n in reqs:
+        L = np.zeros(n, np.uint32)
+        outs.append(L)
+        tickets.append(srv.submit(e, n, L))
+    stats = []
+    for t in tickets:
+        rc, st = srv.wait(t)
+        assert rc == cc.CC_OK
+        stats.append(st)
+    srv.close()
+    assert any(s.batched for s in stats) and any(not s.batched for s in stats)
+    for (e, n), L in zip(reqs, outs):
+        assert_same_labels(L, oracle.cc_labels(n, e), f"served n={n}")
+        alone = to_host_u32(ctx.solve(to_dev(e), n))
+        assert_same_labels(L, alone, f"served vs alone n={n}")
+
+
+def test_serve_budget_errors_and_cancel(ctx):
+    srv = cc.Server(ctx, streams=2, small_n=1024, hbm_budget=64 << 20)
+    e = graphgen.er(4_000_000, 8_000_000, 3)          # 64 MB edges + 16 MB labels > arena
+    L = np.zeros(4_000_000, np.uint32)
+    with pytest.raises(cc.CCError) as ei:
+        srv.submit(e, 4_000_000, L)
+    assert ei.value.code == cc.CC_ENOMEM
+    bad = np.array([[0, 5]], np.uint32)
+    Lb = np.zeros(3, np.uint32)
+    t = srv.submit(bad, 3, Lb)
+    rc, _ = srv.wait(t)
+    assert rc == cc.CC_ERANGE
+    # requests submitted after close are refused; queued ones are cancelled or done
+    ts = []
+    for i in range(50):
+        ee = graphgen.er(3000, 6000, 100 + i)
+        ts.append((srv.submit(ee, 3000, np.zeros(3000, np.uint32)), ee))
+    srv.close()
+
+
+def test_serve_overlap_and_timestamps(ctx):
+    reqs = _requests(300, 9, hi=2.0**15)
+    srv = cc.Server(ctx, streams=4)
+    outs, tickets = [], []
+    t0 = time.monotonic()
+    for e, n in reqs:
+        L = np.zeros(n, np.uint32)
+        outs.append(L)
+        tickets.append(srv.submit(e, n, L))
+    sts = [srv.wait(t)[1] for t in tickets]
+    srv.close()
+    log(f"300 requests in {time.monotonic() - t0:.3f} s")
+    for s in sts:
+        assert s.status == 0 and s.t_submit_ns <= s.t_admit_ns <= s.t_done_ns
+    for (e, n), L in zip(reqs[:40], outs[:40]):
+        assert_same_labels(L, oracle.cc_labels(n, e), f"served n={n}")

@@ -1,0 +1,226 @@
+"""GPU parity of the single-graph path (cc_solve / cc_solve_async and the step
+entry points) against the CPU oracle: bit-exact labels, on seeded inputs that
+span several tiles and ragged tails, edge cases, and both variants."""
+import numpy as np
+import pytest
+import torch
+
+import graphgen
+import oracle
+from gpu_helpers import assert_same_labels, check_properties_on_device, log, to_dev, to_host_u32
+
+pytestmark = pytest.mark.gpu
+
+cc = pytest.importorskip("paper_2507_03695_amd")
+
+FLAG_SETS = {
+    "plain": 0,
+    "nosplit": cc.F_NO_SPLIT,
+    "zroot": cc.F_ZROOT,
+    "zroot_exact": cc.F_ZROOT | cc.F_ZROOT_EXACT,
+    "zroot_nosplit": cc.F_ZROOT | cc.F_NO_SPLIT,
+}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = cc.Context(zroot_samples=4096)
+    yield c
+    c.close()
+
+
+def run_all_variants(ctx, e_np, n, want, what):
+    ed = to_dev(e_np)
+    for name, fl in FLAG_SETS.items():
+        L = ctx.solve(ed, n, flags=fl)
+        assert_same_labels(to_host_u32(L), want, f"{what} [{name}]")
+
+
+def test_cc_solve_default_context_small_random():
+    rng = np.random.default_rng(2024)
+    for i in range(150):
+        n = int(rng.integers(1, 3000))
+        m = int(rng.integers(0, 4 * n))
+        e = graphgen.er(n, m, 1000 + i)
+        L = cc.solve(to_dev(e), n)
+        assert_same_labels(to_host_u32(L), oracle.cc_labels(n, e), f"er n={n} m={m}")
+
+
+@pytest.mark.parametrize("m", [1, 255, 256, 1023, 1024, 1025, 4095, 4097, 100_003, 1_000_001])
+def test_tiles_and_ragged_tails(ctx, m):
+    n = 20_000
+    e = graphgen.er(n, m, 77 + m)
+    log(f"ragged m={m}")
+    run_all_variants(ctx, e, n, oracle.cc_labels(n, e), f"m={m}")
+
+
+def test_adversarial_orders(ctx):
+    n = 50_000
+    ids = np.arange(n, dtype=np.uint32)
+    chain_up = np.stack([ids[:-1], ids[1:]], 1)                     # (i, i+1)
+    chain_down = chain_up[::-1, ::-1].copy()                        # (i+1, i), high IDs first
+    rng = np.random.default_rng(5)
+    chain_rand = chain_up[rng.permutation(n - 1)]
+    star_hi = np.stack([np.full(n - 1, n - 1, np.uint32), ids[:-1]], 1)
+    perm = rng.permutation(n).astype(np.uint32)
+    perm_chain = np.stack([perm[:-1], perm[1:]], 1)
+    for name, e in [("chain_up", chain_up), ("chain_down", chain_down), ("chain_rand", chain_rand),
+                    ("star_hi", star_hi), ("perm_chain", perm_chain)]:
+        run_all_variants(ctx, e, n, oracle.cc_labels(n, e), name)
+
+
+def test_edge_cases(ctx):
+    # n = 1, self-loops only, m = 0, duplicates
+    for n, e in [(1, np.zeros((0, 2), np.uint32)), (1, np.zeros((5, 2), np.uint32)),
+                 (7, np.zeros((0, 2), np.uint32)), (3, np.array([[2, 2], [1, 1]], np.uint32)),
+                 (4, np.array([[3, 1]] * 1000, np.uint32))]:
+        run_all_variants(ctx, e, n, oracle.cc_labels(n, e), f"edge case n={n} m={len(e)}")
+    # n = 0 is a no-op
+    L = torch.empty(0, dtype=torch.int32, device="cuda")
+    ctx.solve_async(to_dev(np.zeros((0, 2), np.uint32)), 0, L)
+    assert ctx.sync() == cc.CC_OK
+
+
+def test_errors(ctx):
+    e = to_dev(np.array([[0, 1], [2, 9]], np.uint32))
+    L = torch.empty(4, dtype=torch.int32, device="cuda")
+    ctx.solve_async(e, 4, L)
+    assert ctx.sync() == cc.CC_ERANGE
+    assert ctx.sync() == cc.CC_OK            # cleared by the previous sync
+    with pytest.raises(cc.CCError) as ei:
+        cc.solve(e, 4)
+    assert ei.value.code == cc.CC_ERANGE
+    lib = cc.load()
+    assert lib.cc_solve(1 << 32, 0, None, None) == cc.CC_EINVAL
+    assert lib.cc_solve(5, 3, None, L.data_ptr()) == cc.CC_EINVAL
+    assert lib.cc_solve(5, 0, None, None) == cc.CC_EINVAL
+    assert lib.cc_solve_async(ctx.handle, 4, 0, None, L.data_ptr(), cc.F_ZROOT | cc.F_ZROOT_HINT,
+                              9, None) == cc.CC_EINVAL
+
+
+def test_metamorphic(ctx):
+    n = 30_000
+    e = graphgen.rmat(15, 3 * n, 31)[: 3 * n]
+    e = e % n
+    want = oracle.cc_labels(n, e)
+    rng = np.random.default_rng(0)
+    variants = {
+        "shuffled": e[rng.permutation(len(e))],
+        "swapped": e[:, ::-1].copy(),
+        "dups": np.concatenate([e, e[rng.integers(0, len(e), 5000)]]),
+        "loops": np.concatenate([e, np.stack([np.arange(0, n, 7)] * 2, 1).astype(np.uint32)]),
+    }
+    for name, ev in variants.items():
+        run_all_variants(ctx, ev, n, want, name)
+
+
+def test_repeat_stress(ctx):
+    """Same input, many runs: the schedule differs, the labels may not."""
+    n = 1 << 16
+    e = graphgen.rmat(16, 16 << 16, 12)
+    want = oracle.cc_labels(n, e)
+    ed = to_dev(e)
+    L = torch.empty(n, dtype=torch.int32, device="cuda")
+    for rep in range(40):
+        fl = [0, cc.F_ZROOT][rep % 2]
+        ctx.solve_async(ed, n, L, flags=fl)
+        assert ctx.sync() == cc.CC_OK
+        assert_same_labels(to_host_u32(L), want, f"rep {rep}")
+
+
+# ---- the step entry points ----------------------------------------------------------
+
+def test_zroot_step(ctx):
+    for seed, n, m in [(1, 1000, 3000), (2, 1 << 16, 1 << 20), (3, 5, 2)]:
+        e = graphgen.rmat(max(1, (n - 1).bit_length()), m, seed) % n
+        ed = to_dev(e)
+        ctx.zroot(ed, n)
+        assert ctx.get_zroot() == oracle.zroot(n, e, 4096), f"sampled zroot n={n}"
+        ctx.zroot(ed, n, flags=cc.F_ZROOT_EXACT)
+        assert ctx.get_zroot() == oracle.zroot(n, e, 0), f"exact zroot n={n}"
+        ctx.zroot(ed, n, flags=cc.F_ZROOT_HINT, zroot_hint=n - 1)
+        assert ctx.get_zroot() == n - 1
+
+
+def test_push_step(ctx):
+    n, m = 1 << 14, 1 << 18
+    e = graphgen.rmat(14, m, 8)
+    ed = to_dev(e)
+    P = torch.empty(n, dtype=torch.int32, device="cuda")
+    ctx.init(n, P)
+    ctx.zroot(ed, n)
+    z = ctx.get_zroot()
+    ctx.push(ed, n, P)
+    torch.cuda.synchronize()
+    assert_same_labels(to_host_u32(P), oracle.push(n, e, 4096, z), "push")
+
+
+@pytest.mark.parametrize("flags", [0, 1, 8, 9])
+def test_hook_leaves_a_key_monotone_forest(ctx, flags):
+    n, m = 1 << 17, 1 << 20
+    e = graphgen.rmat(17, m, 44)
+    ed = to_dev(e)
+    want = oracle.cc_labels(n, e)
+    P = torch.empty(n, dtype=torch.int32, device="cuda")
+    ctx.init(n, P)
+    z = 0
+    if flags & cc.F_ZROOT:
+        ctx.zroot(ed, n)
+        z = ctx.get_zroot()
+        ctx.push(ed, n, P)
+    ctx.hook(ed, n, P, flags=flags)
+    torch.cuda.synchronize()
+    Ph = to_host_u32(P)
+    roots = oracle.check_forest(Ph, bool(flags & cc.F_ZROOT), z)
+    assert roots == oracle.count_components(want)
+    ctx.compress(n, P, flags=flags)
+    if flags & cc.F_ZROOT:
+        ctx.canon(n, P)
+    assert ctx.sync() == cc.CC_OK
+    assert_same_labels(to_host_u32(P), want, "steps")
+
+
+# ---- the named workloads at full size ---------------------------------------------------
+
+def test_er_65k_full():
+    e, n = graphgen.er_65k()
+    want = oracle.cc_labels(n, e)
+    with cc.Context() as c:
+        run_all_variants(c, e, n, want, "ER n=65536 m=2^20")
+
+
+def test_rmat22_sym_full():
+    e, n = graphgen.rmat22_sym()
+    log("rmat22 generated")
+    want = oracle.cc_labels(n, e)
+    log("rmat22 oracle done")
+    with cc.Context() as c:
+        ed = to_dev(e)
+        for name, fl in [("plain", 0), ("zroot", cc.F_ZROOT)]:
+            L = c.solve(ed, n, flags=fl)
+            assert_same_labels(to_host_u32(L), want, f"rmat22 [{name}]")
+            check_properties_on_device(ed, L, n)
+
+
+def test_rmat26_extras_full():
+    """The RMAT-26 + isolated + paths workload in the bench's launch configuration."""
+    g = graphgen.rmat26_extras()
+    log(f"rmat26 generated: n={g.n} m={len(g.edges)}")
+    ed = to_dev(g.edges)
+    with cc.Context() as c:
+        Lz = c.solve(ed, g.n, flags=cc.F_ZROOT)
+        Lp = c.solve(ed, g.n, flags=0)
+        torch.cuda.synchronize()
+        log("rmat26 GPU done")
+        check_properties_on_device(ed, Lz, g.n)
+        assert torch.equal(Lz, Lp), "plain and zero-root paths disagree"
+        Lh = to_host_u32(Lz)
+    del ed
+    lo, hi = g.isolated
+    assert np.array_equal(Lh[lo:hi], np.arange(lo, hi, dtype=np.uint32))
+    for s, ln in zip(g.path_starts[:2000], g.path_lens[:2000]):
+        assert np.all(Lh[int(s):int(s) + int(ln)] == s)
+    want = oracle.cc_labels(g.n, g.edges)
+    log("rmat26 oracle done")
+    assert_same_labels(Lh, want, "rmat26 extras")
