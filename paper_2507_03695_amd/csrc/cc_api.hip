@@ -77,6 +77,7 @@ void slot_destroy(Slot* s) {
     (void)hipDeviceSynchronize();
     if (s->st) (void)hipFree(s->st);
     if (s->deg) (void)hipFree(s->deg);
+    if (s->zbits) (void)hipFree(s->zbits);
     batch_scratch_free(&s->batch);
     if (s->host_status) (void)hipHostFree(s->host_status);
     *s = Slot{};

@@ -59,6 +59,13 @@ struct Slot {
     uint64_t deg_cap = 0;
     uint32_t* host_status = nullptr;  // pinned host word
     BatchScratch batch;
+    // Zero-root membership bitmap: bit x set => x is in the zero root's tree.
+    uint32_t* zbits = nullptr;     // device, ceil(n/32) words (grown on demand)
+    uint64_t zbits_cap = 0;        // words
+    // Host-side order of the steps: a CC_F_ZROOT hook needs cc_zroot after the
+    // latest cc_init on the same n (the bitmap describes that solve).
+    uint64_t cur_n = 0;
+    bool zr_ready = false;
 };
 
 int slot_create(Slot* s, int device, uint32_t samples);

@@ -172,16 +172,31 @@ __global__ void k_zfinish(DevState* st, int use_hint, uint32_t hint) {
 // the same value, so plain stores suffice.
 __global__ __launch_bounds__(kBlock) void k_push(const uint32_t* __restrict__ edges, uint64_t m,
                                                  uint64_t K, uint64_t cnt, uint64_t n,
-                                                 uint32_t* P, DevState* st) {
+                                                 uint32_t* P, uint32_t* zbits, DevState* st) {
     const uint32_t z = st->zroot;
     for (uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < cnt;
          j += (uint64_t)gridDim.x * kBlock) {
         const uint64_t i = (cnt == m) ? j : sample_index(j, m, K);
         const uint32_t u = edges[2 * i], v = edges[2 * i + 1];
         if (u >= n || v >= n || u == v) continue;
-        if (u == z) P[v] = z;
-        else if (v == z) P[u] = z;
+        uint32_t x = kEmpty;
+        if (u == z) x = v;
+        else if (v == z) x = u;
+        if (x != kEmpty) {
+            P[x] = z;
+            atomicOr(&zbits[x >> 5], 1u << (x & 31));
+        }
     }
+}
+
+// Membership bitmap of the zero root's tree: cleared, with only z itself set.
+__global__ __launch_bounds__(kBlock) void k_zbits_clear(uint32_t* zbits, uint64_t words,
+                                                        const DevState* st) {
+    const uint32_t z = st->zroot;
+    const uint64_t zw = z >> 5;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < words;
+         i += (uint64_t)gridDim.x * kBlock)
+        zbits[i] = (i == zw) ? (1u << (z & 31)) : 0u;
 }
 
 // ---- hook ---------------------------------------------------------------------
@@ -201,29 +216,50 @@ __device__ __forceinline__ uint32_t find_root(uint32_t* P, uint32_t x, uint32_t 
 }
 
 // Algorithm 1 / 3 hooking of one entry whose endpoints u, v have parents pu, pv.
+// Returns the root under which both endpoints ended up (the surviving root of
+// the link, or the common root found). When it is the zero root z, both
+// endpoints are certainly in z's tree: z has the smallest key and is never
+// linked under anything.
 template <bool ZR, int SPLIT>
-__device__ __forceinline__ void link(uint32_t* P, uint32_t u, uint32_t pu, uint32_t v,
-                                     uint32_t pv, uint32_t z) {
+__device__ __forceinline__ uint32_t link(uint32_t* P, uint32_t u, uint32_t pu, uint32_t v,
+                                         uint32_t pv, uint32_t z) {
     while (true) {
         const uint32_t ru = find_root<SPLIT>(P, u, pu);
         const uint32_t rv = find_root<SPLIT>(P, v, pv);
-        if (ru == rv) return;
+        if (ru == rv) return ru;
         const bool u_low = key_less<ZR>(ru, rv, z);
         const uint32_t hi = u_low ? rv : ru;
         const uint32_t lo = u_low ? ru : rv;
         const uint32_t old = atomicCAS(&P[hi], hi, lo);
-        if (old == hi) return;
+        if (old == hi) return lo;
         // hi was linked by someone else: its current parent is `old`
         u = hi; pu = old;
         v = lo; pv = lo;
     }
 }
 
+__device__ __forceinline__ bool zbit(const uint32_t* zbits, uint32_t x) {
+    return (zbits[x >> 5] >> (x & 31)) & 1u;
+}
+
+__device__ __forceinline__ void zbit_set(uint32_t* zbits, uint32_t x) {
+    atomicOr(&zbits[x >> 5], 1u << (x & 31));
+}
+
 constexpr int kEPT = 4;  // entries per thread per tile
 
+// One tile of kBlock*kEPT entries per workgroup; each thread loads its kEPT
+// entries (coalesced, non-temporal: the edge stream must not evict P) and
+// issues all their parent reads before walking any of them.
+// With a zero root (ZR) the membership bitmap is consulted first: an entry
+// whose endpoints are both known to be in z's tree is dropped without reading P
+// (the single-GPU form of treating zero-converged vertices specially, Sec. IV).
+// Bits only go from 0 to 1 and only for vertices in z's tree, so a stale or
+// missing bit just sends the entry down the ordinary path.
 template <bool ZR, int SPLIT>
 __global__ __launch_bounds__(kBlock) void k_hook(const uint32_t* __restrict__ edges, uint64_t m,
-                                                 uint32_t n, uint32_t* P, DevState* st) {
+                                                 uint32_t n, uint32_t* P, uint32_t* zbits,
+                                                 DevState* st) {
     const uint32_t z = ZR ? st->zroot : 0u;
     const uint64_t tile = (uint64_t)blockIdx.x * (kBlock * kEPT);
     const u32x2* E = reinterpret_cast<const u32x2*>(edges);
@@ -242,17 +278,43 @@ __global__ __launch_bounds__(kBlock) void k_hook(const uint32_t* __restrict__ ed
         if (u[k] >= n || v[k] >= n) { bad = true; u[k] = v[k] = 0; }
     }
     if (bad) atomicOr(&st->status, kStatusRange);
+    bool live[kEPT];
+#pragma unroll
+    for (int k = 0; k < kEPT; ++k) live[k] = u[k] != v[k];
+    bool inu[kEPT] = {}, inv[kEPT] = {};
+    if (ZR) {
+        uint32_t bu[kEPT], bv[kEPT];
+#pragma unroll
+        for (int k = 0; k < kEPT; ++k) {
+            bu[k] = live[k] ? zbits[u[k] >> 5] : 0u;
+            bv[k] = live[k] ? zbits[v[k] >> 5] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kEPT; ++k) {
+            inu[k] = (bu[k] >> (u[k] & 31)) & 1u;
+            inv[k] = (bv[k] >> (v[k] & 31)) & 1u;
+            live[k] = live[k] && !(inu[k] && inv[k]);
+        }
+    }
     uint32_t pu[kEPT], pv[kEPT];
 #pragma unroll
     for (int k = 0; k < kEPT; ++k) {
-        pu[k] = u[k] != v[k] ? P[u[k]] : 0u;
-        pv[k] = u[k] != v[k] ? P[v[k]] : 0u;
+        pu[k] = live[k] ? P[u[k]] : 0u;
+        pv[k] = live[k] ? P[v[k]] : 0u;
     }
 #pragma unroll
     for (int k = 0; k < kEPT; ++k) {
+        if (!live[k]) continue;
         // a common parent, or one endpoint the parent of the other: same tree
-        if (u[k] == v[k] || pu[k] == pv[k] || pu[k] == v[k] || pv[k] == u[k]) continue;
-        link<ZR, SPLIT>(P, u[k], pu[k], v[k], pv[k], z);
+        uint32_t r;
+        if (pu[k] == pv[k]) r = pu[k];
+        else if (pu[k] == v[k]) r = v[k];
+        else if (pv[k] == u[k]) r = u[k];
+        else r = link<ZR, SPLIT>(P, u[k], pu[k], v[k], pv[k], z);
+        if (ZR && r == z) {
+            if (!inu[k]) zbit_set(zbits, u[k]);
+            if (!inv[k]) zbit_set(zbits, v[k]);
+        }
     }
 }
 
@@ -302,6 +364,8 @@ static uint32_t grid_for(uint64_t work, uint64_t per_block, uint32_t cap) {
 constexpr uint32_t kGridCap = 256 * 32;
 
 int run_init(Slot* s, uint64_t n, uint32_t* P, hipStream_t stream) {
+    s->cur_n = n;
+    s->zr_ready = false;
     int vec = ((uintptr_t)P & 15) == 0;
     k_init<<<grid_for(n, kBlock * 4, kGridCap), kBlock, 0, stream>>>(P, n, s->st, vec);
     CCM_HIP(hipGetLastError());
@@ -310,12 +374,34 @@ int run_init(Slot* s, uint64_t n, uint32_t* P, hipStream_t stream) {
 
 static uint64_t sample_count(uint64_t m, uint64_t K) { return m <= K ? m : K; }
 
+// Size the membership bitmap for n vertices and clear it (only z set). Marks the
+// slot ready for a zero-root hook when n is the current solve's.
+static int zbits_reset(Slot* s, uint64_t n, hipStream_t stream) {
+    const uint64_t words = (n + 31) / 32;
+    if (s->zbits_cap < words) {
+        CCM_HIP(hipStreamSynchronize(stream));
+        if (s->zbits) CCM_HIP(hipFree(s->zbits));
+        s->zbits = nullptr;
+        s->zbits_cap = 0;
+        if (hipMalloc(&s->zbits, words * sizeof(uint32_t)) != hipSuccess) {
+            (void)hipGetLastError();
+            s->zbits = nullptr;
+            return fail(CC_ENOMEM, "zero-root bitmap allocation failed");
+        }
+        s->zbits_cap = words;
+    }
+    k_zbits_clear<<<grid_for(words, kBlock, kGridCap), kBlock, 0, stream>>>(s->zbits, words, s->st);
+    CCM_HIP(hipGetLastError());
+    s->zr_ready = (n == s->cur_n);
+    return CC_OK;
+}
+
 int run_zroot(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t flags,
               uint32_t hint, hipStream_t stream) {
     if (flags & CC_F_ZROOT_HINT) {
         k_zfinish<<<1, 64, 0, stream>>>(s->st, 1, hint);
         CCM_HIP(hipGetLastError());
-        return CC_OK;
+        return zbits_reset(s, n, stream);
     }
     if (flags & CC_F_ZROOT_EXACT) {
         if (s->deg_cap < n) {
@@ -345,15 +431,18 @@ int run_zroot(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t f
     }
     k_zfinish<<<1, 64, 0, stream>>>(s->st, 0, 0);
     CCM_HIP(hipGetLastError());
-    return CC_OK;
+    return zbits_reset(s, n, stream);
 }
 
 int run_push(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
              hipStream_t stream) {
+    if (!s->zr_ready || s->cur_n != n)
+        return fail(CC_EINVAL, "cc_push needs cc_init then cc_zroot on the same n");
     const uint64_t K = s->samples;
     const uint64_t cnt = sample_count(m, K);
     if (!cnt) return CC_OK;
-    k_push<<<grid_for(cnt, kBlock, 1024), kBlock, 0, stream>>>(edges, m, K, cnt, n, P, s->st);
+    k_push<<<grid_for(cnt, kBlock, 1024), kBlock, 0, stream>>>(edges, m, K, cnt, n, P, s->zbits,
+                                                               s->st);
     CCM_HIP(hipGetLastError());
     return CC_OK;
 }
@@ -366,11 +455,15 @@ int run_hook(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P
     if (blocks > 0x7FFFFFFFull) return fail(CC_EINVAL, "edge count too large for one launch");
     const bool zr = flags & CC_F_ZROOT;
     const bool split = !(flags & CC_F_NO_SPLIT);
+    if (zr && (!s->zr_ready || s->cur_n != n))
+        return fail(CC_EINVAL, "a CC_F_ZROOT hook needs cc_init then cc_zroot on the same n");
     const uint32_t n32 = (uint32_t)n;
-    if (zr && split) k_hook<true, 1><<<(uint32_t)blocks, kBlock, 0, stream>>>(edges, m, n32, P, s->st);
-    else if (zr) k_hook<true, 0><<<(uint32_t)blocks, kBlock, 0, stream>>>(edges, m, n32, P, s->st);
-    else if (split) k_hook<false, 1><<<(uint32_t)blocks, kBlock, 0, stream>>>(edges, m, n32, P, s->st);
-    else k_hook<false, 0><<<(uint32_t)blocks, kBlock, 0, stream>>>(edges, m, n32, P, s->st);
+    uint32_t* zb = s->zbits;
+    const uint32_t g = (uint32_t)blocks;
+    if (zr && split) k_hook<true, 1><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st);
+    else if (zr) k_hook<true, 0><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st);
+    else if (split) k_hook<false, 1><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st);
+    else k_hook<false, 0><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st);
     CCM_HIP(hipGetLastError());
     return CC_OK;
 }

@@ -97,6 +97,16 @@ def test_errors(ctx):
     assert lib.cc_solve(5, 0, None, None) == cc.CC_EINVAL
     assert lib.cc_solve_async(ctx.handle, 4, 0, None, L.data_ptr(), cc.F_ZROOT | cc.F_ZROOT_HINT,
                               9, None) == cc.CC_EINVAL
+    # a zero-root hook needs cc_zroot after the latest cc_init
+    ctx.init(4, L)
+    with pytest.raises(cc.CCError) as ei:
+        ctx.hook(e, 4, L, flags=cc.F_ZROOT)
+    assert ei.value.code == cc.CC_EINVAL
+    ctx.zroot(e[:1], 4)
+    ctx.init(4, L)
+    with pytest.raises(cc.CCError):
+        ctx.push(e[:1], 4, L)
+    assert ctx.sync() == cc.CC_OK
 
 
 def test_metamorphic(ctx):
