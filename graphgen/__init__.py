@@ -162,7 +162,8 @@ def rmat_share(scale: int, edgefactor: int, seed: int, shares: int, k: int) -> t
     """Share k of `shares` equal vertex ranges of a permuted R-MAT graph.
 
     Returns (edges, n) where n = 2^scale (the parent array stays global-size):
-    the generated entries whose first endpoint lies in the share's range.
+    the generated entries whose first endpoint lies in the share's range, in
+    generation order.
     """
     lib = _load()
     t1, t2, t3 = rmat_thresholds()
@@ -171,12 +172,23 @@ def rmat_share(scale: int, edgefactor: int, seed: int, shares: int, k: int) -> t
     span = n // shares
     lo, hi = k * span, (k + 1) * span
     perm_seed = subseed(seed, 0x5045524D) | 1
-    cnt = lib.gg_rmat_share(scale, m_total, t1, t2, t3, seed, perm_seed, lo, hi, None, 0)
-    out = np.empty((cnt, 2), dtype=np.uint32)
-    got = lib.gg_rmat_share(scale, m_total, t1, t2, t3, seed, perm_seed, lo, hi, _ptr(out), cnt)
-    if got != cnt:
-        raise RuntimeError("share generation count mismatch")
-    return out, n
+    cap = int(m_total / shares * 1.03) + (1 << 20)
+    out = np.empty((cap, 2), dtype=np.uint32)
+    cnt = lib.gg_rmat_share(scale, m_total, t1, t2, t3, seed, perm_seed, lo, hi, _ptr(out), cap)
+    if cnt == 2**64 - 1:
+        raise MemoryError("share staging allocation failed")
+    if cnt > cap:
+        out = np.empty((cnt, 2), dtype=np.uint32)
+        got = lib.gg_rmat_share(scale, m_total, t1, t2, t3, seed, perm_seed, lo, hi, _ptr(out), cnt)
+        if got != cnt:
+            raise RuntimeError("share generation count mismatch")
+        return out, n
+    return out[:cnt], n
+
+
+def rmat30_share() -> tuple:
+    """Share 0 of 16 of R-MAT scale 30, edgefactor 16 (n = 2^30, about 2^30 entries)."""
+    return rmat_share(30, 16, config_seed(5), 16, 0)
 
 
 @dataclass
@@ -322,3 +334,83 @@ def serve_stream(count: int, seed: int, rate_per_s: float, lo=2.0**10, hi=2.0**2
         kind = int((r[2] >> 32) & 1)
         reqs.append(Request(n, ef, kind, r[3], t))
     return reqs
+
+
+# ---- device twin (graphgen_dev.hip): the same entries, generated on the GPU ----
+
+_DEV_SRC = os.path.join(_HERE, "graphgen_dev.hip")
+_DEV_LIB_PATH = os.path.join(_HERE, "libgraphgen_dev.so")
+_dev_lib = None
+
+
+def build_dev() -> str:
+    """Compile libgraphgen_dev.so for gfx950 with hipcc."""
+    tmp = _DEV_LIB_PATH + ".tmp"
+    subprocess.check_call(["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O3", "-fPIC", "-shared",
+                           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                           "-Wno-unused-command-line-argument", "-o", tmp, _DEV_SRC],
+                          stderr=subprocess.DEVNULL)
+    os.replace(tmp, _DEV_LIB_PATH)
+    return _DEV_LIB_PATH
+
+
+def _load_dev():
+    global _dev_lib
+    if _dev_lib is None:
+        if not os.path.exists(_DEV_LIB_PATH):
+            raise ImportError(f"{_DEV_LIB_PATH} is missing: run graphgen.build_dev()")
+        lib = ctypes.CDLL(_DEV_LIB_PATH)
+        u64, u32, p = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p
+        lib.gg_dev_rmat.argtypes = [u32, u64, u32, u32, u32, u64, u64, p]
+        lib.gg_dev_rmat.restype = ctypes.c_int
+        lib.gg_dev_share_count.argtypes = [u32, u64, u32, u32, u32, u64, u64, u64, u64, u64, p]
+        lib.gg_dev_share_count.restype = ctypes.c_int
+        lib.gg_dev_share_write.argtypes = [u32, u64, u32, u32, u32, u64, u64, u64, u64, u64, p, p]
+        lib.gg_dev_share_write.restype = ctypes.c_int
+        _dev_lib = lib
+    return _dev_lib
+
+
+def rmat_dev(scale: int, m: int, seed: int, permute: bool = True):
+    """rmat() generated on the current GPU: an (m, 2) int32 torch tensor, same bits."""
+    import torch
+    lib = _load_dev()
+    t1, t2, t3 = rmat_thresholds()
+    out = torch.empty((m, 2), dtype=torch.int32, device="cuda")
+    perm_seed = subseed(seed, 0x5045524D) | 1 if permute else 0
+    if m and lib.gg_dev_rmat(scale, m, t1, t2, t3, seed, perm_seed, out.data_ptr()) != 0:
+        raise RuntimeError("gg_dev_rmat failed")
+    return out
+
+
+def rmat_share_dev(scale: int, edgefactor: int, seed: int, shares: int, k: int,
+                   span: int = 1 << 20):
+    """rmat_share() generated on the current GPU: ((cnt, 2) int32 tensor, n)."""
+    import torch
+    lib = _load_dev()
+    t1, t2, t3 = rmat_thresholds()
+    n = 1 << scale
+    m_total = edgefactor * n
+    width = n // shares
+    lo, hi = k * width, (k + 1) * width
+    perm_seed = subseed(seed, 0x5045524D) | 1
+    blocks = (m_total + span - 1) // span
+    counts = torch.empty(blocks, dtype=torch.int32, device="cuda")
+    if lib.gg_dev_share_count(scale, m_total, t1, t2, t3, seed, perm_seed, lo, hi, span,
+                              counts.data_ptr()) != 0:
+        raise RuntimeError("gg_dev_share_count failed")
+    c64 = counts.to(torch.int64)
+    offs = torch.zeros(blocks, dtype=torch.int64, device="cuda")
+    if blocks > 1:
+        offs[1:] = torch.cumsum(c64, 0)[:-1]
+    total = int(c64.sum().item())
+    out = torch.empty((total, 2), dtype=torch.int32, device="cuda")
+    if total and lib.gg_dev_share_write(scale, m_total, t1, t2, t3, seed, perm_seed, lo, hi, span,
+                                        offs.data_ptr(), out.data_ptr()) != 0:
+        raise RuntimeError("gg_dev_share_write failed")
+    return out, n
+
+
+def rmat30_share_dev():
+    """rmat30_share() generated on the GPU."""
+    return rmat_share_dev(30, 16, config_seed(5), 16, 0)

@@ -25,6 +25,7 @@
  */
 #include <stdint.h>
 #include <stddef.h>
+#include <stdlib.h>
 #include <string.h>
 
 #define GG_GAMMA 0x9E3779B97F4A7C15ull
@@ -112,18 +113,18 @@ void gg_er(uint64_t n, uint64_t m, uint64_t seed, uint32_t* out) {
 static inline void rmat_entry(uint64_t seed, uint64_t i, uint32_t scale,
                               uint32_t t1, uint32_t t2, uint32_t t3,
                               uint64_t* uo, uint64_t* vo) {
-    uint64_t u = 0, v = 0, r = 0;
-    for (uint32_t l = 0; l < scale; ++l) {
-        uint32_t r32;
-        if ((l & 1) == 0) { r = draw(seed, i * 16 + (l >> 1)); r32 = (uint32_t)r; }
-        else r32 = (uint32_t)(r >> 32);
-        uint64_t ub, vb;
-        if (r32 < t1)      { ub = 0; vb = 0; }
-        else if (r32 < t2) { ub = 0; vb = 1; }
-        else if (r32 < t3) { ub = 1; vb = 0; }
-        else               { ub = 1; vb = 1; }
-        u = (u << 1) | ub;
-        v = (v << 1) | vb;
+    uint64_t u = 0, v = 0;
+    for (uint32_t l = 0; l < scale; l += 2) {
+        const uint64_t r = draw(seed, i * 16 + (l >> 1));
+        const uint32_t lo = (uint32_t)r, hi = (uint32_t)(r >> 32);
+        /* quadrant 0: r < t1; 1: t1 <= r < t2; 2: t2 <= r < t3; 3: r >= t3.
+           u's bit is set in quadrants 2 and 3, v's in quadrants 1 and 3. */
+        u = (u << 1) | (uint64_t)(lo >= t2);
+        v = (v << 1) | (uint64_t)(((lo >= t1) & (lo < t2)) | (lo >= t3));
+        if (l + 1 < scale) {
+            u = (u << 1) | (uint64_t)(hi >= t2);
+            v = (v << 1) | (uint64_t)(((hi >= t1) & (hi < t2)) | (hi >= t3));
+        }
     }
     *uo = u; *vo = v;
 }
@@ -148,56 +149,49 @@ void gg_rmat(uint32_t scale, uint64_t m, uint32_t t1, uint32_t t2, uint32_t t3,
 /*
  * One share of a vertex-range partition of a permuted R-MAT graph: of the
  * m_total generated entries keep those whose first endpoint lies in
- * [lo, hi), in generation order. Pass out == NULL to count only.
- * Returns the number of kept entries.
+ * [lo, hi), in generation order. Entries are generated once: each round of
+ * chunks is filtered into per-chunk staging, then copied out at prefix
+ * offsets. Writes at most out_cap entries; returns the number of kept
+ * entries (when that exceeds out_cap, only the count is meaningful).
  */
 uint64_t gg_rmat_share(uint32_t scale, uint64_t m_total, uint32_t t1, uint32_t t2, uint32_t t3,
                        uint64_t seed, uint64_t perm_seed, uint64_t lo, uint64_t hi,
                        uint32_t* out, uint64_t out_cap) {
     perm_t p; perm_init(&p, scale, perm_seed);
-    const int64_t CHUNK = 1 << 20;
-    int64_t nchunks = (int64_t)((m_total + CHUNK - 1) / CHUNK);
+    const int64_t CHUNK = 1 << 18, ROUND = 256;
+    const int64_t nchunks = (int64_t)((m_total + CHUNK - 1) / CHUNK);
+    uint32_t* stage = (uint32_t*)malloc((size_t)ROUND * CHUNK * 2 * sizeof(uint32_t));
+    if (!stage) return ~0ull;
     uint64_t total = 0;
-    /* chunked two-pass: count per chunk, prefix, then write, to keep order */
-    for (int64_t c0 = 0; c0 < nchunks; c0 += 4096) {
-        int64_t c1 = c0 + 4096 < nchunks ? c0 + 4096 : nchunks;
-        uint64_t counts[4096];
+    for (int64_t c0 = 0; c0 < nchunks; c0 += ROUND) {
+        const int64_t c1 = c0 + ROUND < nchunks ? c0 + ROUND : nchunks;
+        uint64_t counts[256];
         #pragma omp parallel for schedule(dynamic, 1)
         for (int64_t c = c0; c < c1; ++c) {
-            uint64_t b = (uint64_t)c * CHUNK, e = b + CHUNK < m_total ? b + CHUNK : m_total;
+            const uint64_t b = (uint64_t)c * CHUNK;
+            const uint64_t e = b + CHUNK < m_total ? b + CHUNK : m_total;
+            uint32_t* st = stage + (size_t)(c - c0) * CHUNK * 2;
             uint64_t k = 0;
             for (uint64_t i = b; i < e; ++i) {
                 uint64_t u, v;
                 rmat_entry(seed, i, scale, t1, t2, t3, &u, &v);
                 u = perm_apply(&p, u);
-                if (u >= lo && u < hi) ++k;
+                if (u >= lo && u < hi) {
+                    st[2 * k] = (uint32_t)u;
+                    st[2 * k + 1] = (uint32_t)perm_apply(&p, v);
+                    ++k;
+                }
             }
             counts[c - c0] = k;
         }
-        if (out) {
-            uint64_t offs[4096];
-            uint64_t run = total;
-            for (int64_t c = c0; c < c1; ++c) { offs[c - c0] = run; run += counts[c - c0]; }
-            if (run > out_cap) return ~0ull;
-            #pragma omp parallel for schedule(dynamic, 1)
-            for (int64_t c = c0; c < c1; ++c) {
-                uint64_t b = (uint64_t)c * CHUNK, e = b + CHUNK < m_total ? b + CHUNK : m_total;
-                uint64_t k = offs[c - c0];
-                for (uint64_t i = b; i < e; ++i) {
-                    uint64_t u, v;
-                    rmat_entry(seed, i, scale, t1, t2, t3, &u, &v);
-                    u = perm_apply(&p, u);
-                    if (u >= lo && u < hi) {
-                        v = perm_apply(&p, v);
-                        out[2 * k] = (uint32_t)u;
-                        out[2 * k + 1] = (uint32_t)v;
-                        ++k;
-                    }
-                }
-            }
+        for (int64_t c = c0; c < c1; ++c) {
+            const uint64_t k = counts[c - c0];
+            if (out && total + k <= out_cap)
+                memcpy(out + 2 * total, stage + (size_t)(c - c0) * CHUNK * 2, k * 2 * sizeof(uint32_t));
+            total += k;
         }
-        for (int64_t c = c0; c < c1; ++c) total += counts[c - c0];
     }
+    free(stage);
     return total;
 }
 
