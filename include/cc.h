@@ -72,6 +72,11 @@ int cc_version(void);
 #define CC_F_ZROOT_HINT   0x4u
 /* Plain root walks without path splitting (Algorithm 1's finds as printed). */
 #define CC_F_NO_SPLIT     0x8u
+/* With CC_F_ZROOT: keep the direct hook (bitmap tests in L2) even where the
+   tiled hook applies (2 <= ceil(n / 2^19) <= 256 and 2^24 <= m < 2^32), which
+   first regroups the entries by the vertex ranges of both endpoints so that
+   both membership tests read LDS. Labels are identical either way. */
+#define CC_F_NO_TILE      0x10u
 
 /* ---- context ----------------------------------------------------------- */
 typedef struct cc_ctx cc_ctx;

@@ -78,6 +78,7 @@ void slot_destroy(Slot* s) {
     if (s->st) (void)hipFree(s->st);
     if (s->deg) (void)hipFree(s->deg);
     if (s->zbits) (void)hipFree(s->zbits);
+    tiled_free(&s->tiled);
     batch_scratch_free(&s->batch);
     if (s->host_status) (void)hipHostFree(s->host_status);
     *s = Slot{};
@@ -85,8 +86,9 @@ void slot_destroy(Slot* s) {
 
 __global__ void k_status_take(DevState* st, uint32_t* out) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        *out = st->status;
-        st->status = 0;
+        const uint32_t w = __hip_atomic_exchange(&st->status, 0u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(out, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
@@ -240,7 +242,9 @@ extern "C" int cc_init(cc_ctx* ctx, uint64_t n, uint32_t* P, void* stream) {
     int rc = check_graph(n, 0, nullptr, P);
     if (rc || n == 0) return rc;
     if ((rc = set_dev(ctx))) return rc;
-    return run_init(&ctx->slot, n, P, (hipStream_t)stream);
+    if ((rc = cohere((hipStream_t)stream))) return rc;
+    if ((rc = run_init(&ctx->slot, n, P, (hipStream_t)stream))) return rc;
+    return cohere((hipStream_t)stream);
 }
 
 extern "C" int cc_zroot(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edges,
@@ -252,7 +256,9 @@ extern "C" int cc_zroot(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edg
     if ((flags & CC_F_ZROOT_HINT) && zroot_hint >= n)
         return fail(CC_EINVAL, "zroot_hint must be < n");
     if ((rc = set_dev(ctx))) return rc;
-    return run_zroot(&ctx->slot, n, m, edges, flags, zroot_hint, (hipStream_t)stream);
+    if ((rc = cohere((hipStream_t)stream))) return rc;
+    if ((rc = run_zroot(&ctx->slot, n, m, edges, flags, zroot_hint, (hipStream_t)stream))) return rc;
+    return cohere((hipStream_t)stream);
 }
 
 extern "C" int cc_push(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
@@ -261,7 +267,9 @@ extern "C" int cc_push(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edge
     int rc = check_graph(n, m, edges, P);
     if (rc || n == 0) return rc;
     if ((rc = set_dev(ctx))) return rc;
-    return run_push(&ctx->slot, n, m, edges, P, (hipStream_t)stream);
+    if ((rc = cohere((hipStream_t)stream))) return rc;
+    if ((rc = run_push(&ctx->slot, n, m, edges, P, (hipStream_t)stream))) return rc;
+    return cohere((hipStream_t)stream);
 }
 
 extern "C" int cc_hook(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
@@ -270,7 +278,9 @@ extern "C" int cc_hook(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edge
     int rc = check_graph(n, m, edges, P);
     if (rc || n == 0) return rc;
     if ((rc = set_dev(ctx))) return rc;
-    return run_hook(&ctx->slot, n, m, edges, P, flags, (hipStream_t)stream);
+    if ((rc = cohere((hipStream_t)stream))) return rc;
+    if ((rc = run_hook(&ctx->slot, n, m, edges, P, flags, (hipStream_t)stream))) return rc;
+    return cohere((hipStream_t)stream);
 }
 
 extern "C" int cc_compress(cc_ctx* ctx, uint64_t n, uint32_t* P, uint32_t flags, void* stream) {
@@ -278,7 +288,9 @@ extern "C" int cc_compress(cc_ctx* ctx, uint64_t n, uint32_t* P, uint32_t flags,
     int rc = check_graph(n, 0, nullptr, P);
     if (rc || n == 0) return rc;
     if ((rc = set_dev(ctx))) return rc;
-    return run_compress(&ctx->slot, n, P, flags, (hipStream_t)stream);
+    if ((rc = cohere((hipStream_t)stream))) return rc;
+    if ((rc = run_compress(&ctx->slot, n, P, flags, (hipStream_t)stream))) return rc;
+    return cohere((hipStream_t)stream);
 }
 
 extern "C" int cc_canon(cc_ctx* ctx, uint64_t n, uint32_t* L, void* stream) {
@@ -286,13 +298,16 @@ extern "C" int cc_canon(cc_ctx* ctx, uint64_t n, uint32_t* L, void* stream) {
     int rc = check_graph(n, 0, nullptr, L);
     if (rc || n == 0) return rc;
     if ((rc = set_dev(ctx))) return rc;
-    return run_canon(&ctx->slot, n, L, (hipStream_t)stream);
+    if ((rc = cohere((hipStream_t)stream))) return rc;
+    if ((rc = run_canon(&ctx->slot, n, L, (hipStream_t)stream))) return rc;
+    return cohere((hipStream_t)stream);
 }
 
 extern "C" int cc_get_zroot(cc_ctx* ctx, void* stream, uint32_t* zroot_out) {
     if (!ctx || !zroot_out) return fail(CC_EINVAL, "NULL argument");
     int rc = set_dev(ctx);
     if (rc) return rc;
+    if ((rc = cohere((hipStream_t)stream))) return rc;
     CCM_HIP(hipMemcpyAsync(ctx->slot.host_status, &ctx->slot.st->zroot, sizeof(uint32_t),
                            hipMemcpyDeviceToHost, (hipStream_t)stream));
     CCM_HIP(hipStreamSynchronize((hipStream_t)stream));

@@ -162,11 +162,13 @@ int launch_batch(Slot* s, uint32_t G, const GraphDesc* descs, hipStream_t stream
     const int cus = device_cu_count(s->device);
     const uint32_t grid = (uint32_t)std::min<int64_t>((int64_t)cus, (int64_t)G);
     char* d = bs.dev;
+    rc = cohere(stream);
+    if (rc) return rc;
     k_batch<<<grid, kBatchBlock, lds_bytes, stream>>>(
         G, reinterpret_cast<const GraphDesc*>(d + ((char*)h_desc - h)),
         reinterpret_cast<const uint32_t*>(d + kTicketBytes), reinterpret_cast<uint32_t*>(d), lds_cap);
     CCM_HIP(hipGetLastError());
-    return CC_OK;
+    return cohere(stream);
 }
 
 int run_batch(Slot* s, uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,

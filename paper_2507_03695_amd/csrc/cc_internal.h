@@ -47,6 +47,12 @@ struct BatchScratch {
     uint64_t cap = 0;          // graphs
 };
 
+// Scratch of the tiled zero-root hook (one block, grown on demand).
+struct TiledScratch {
+    char* buf = nullptr;
+    uint64_t cap = 0;
+};
+
 // Scratch owned by one slot.
 struct Slot {
     int device = 0;
@@ -66,6 +72,7 @@ struct Slot {
     // latest cc_init on the same n (the bitmap describes that solve).
     uint64_t cur_n = 0;
     bool zr_ready = false;
+    TiledScratch tiled;
 };
 
 int slot_create(Slot* s, int device, uint32_t samples);
@@ -86,6 +93,12 @@ int run_solve(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* 
 // Copy the status word to the host, clear it, wait for the stream; CC_OK/CC_ERANGE.
 int slot_sync(Slot* s, hipStream_t stream);
 
+// Tiled zero-root hook (cc_tiled.hip): both membership tests in LDS.
+bool tiled_eligible(uint64_t n, uint64_t m);
+int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
+                   hipStream_t stream);
+void tiled_free(TiledScratch* t);
+
 // Batched path (cc_batch.hip).
 // Enqueue one persistent launch over G graphs described on the host.
 int launch_batch(Slot* s, uint32_t G, const GraphDesc* descs, hipStream_t stream);
@@ -104,6 +117,29 @@ int hip_fail(hipError_t e, const char* what);
     } while (0)
 
 int device_cu_count(int device);
+
+// Coherence point between dependent kernels on one stream. Each XCD of the
+// device has its own L2; a clean line cached on one XCD is not invalidated when
+// another XCD (or an atomic performed beyond the L2) changes the data, and the
+// kernel boundary alone has been observed not to drop such lines. This launch
+// runs workgroups on every XCD, each writing back and invalidating its L2
+// (agent-scope acquire-release fence), so the next kernel on the stream reads
+// what the previous ones wrote.
+int cohere(hipStream_t stream);
+
+// Coherent (agent-scope) accesses to the small shared words of DevState.
+__device__ __forceinline__ uint32_t ld_agent(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_agent64(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent64(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Device, memory budget and zero-root sample count of a context.
 int ctx_info(cc_ctx* ctx, int* device, uint64_t* budget, uint32_t* samples);

@@ -37,7 +37,7 @@ __global__ __launch_bounds__(kBlock) void k_init(uint32_t* __restrict__ P, uint6
                                                  DevState* st, int vec) {
     const uint64_t tid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    if (tid == 0) st->minz = kEmpty;
+    if (tid == 0) st_agent(&st->minz, kEmpty);
     if (vec) {
         const uint64_t n4 = n >> 2;
         u32x4* P4 = reinterpret_cast<u32x4*>(P);
@@ -63,7 +63,7 @@ __device__ __forceinline__ uint64_t sample_index(uint64_t j, uint64_t m, uint64_
 __global__ __launch_bounds__(kBlock) void k_zfill(uint32_t* keys, uint32_t* counts, uint32_t T,
                                                   DevState* st) {
     uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i == 0) st->zsel = 0;
+    if (i == 0) st_agent64(&st->zsel, 0);
     for (; i < T; i += gridDim.x * kBlock) { keys[i] = kEmpty; counts[i] = 0; }
 }
 
@@ -71,7 +71,7 @@ __device__ __forceinline__ void table_add(uint32_t* keys, uint32_t* counts, uint
                                           uint32_t x) {
     uint32_t h = (x * 0x9E3779B1u) & mask;
     while (true) {
-        uint32_t k = keys[h];
+        uint32_t k = ld_agent(&keys[h]);
         if (k == kEmpty) {
             k = atomicCAS(&keys[h], kEmpty, x);
             if (k == kEmpty) k = x;
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kBlock) void k_zcount(const uint32_t* __restrict__ 
 // Exact degree: dense counts over all entries.
 __global__ __launch_bounds__(kBlock) void k_degfill(uint32_t* deg, uint64_t n, DevState* st) {
     uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i == 0) st->zsel = 0;
+    if (i == 0) st_agent64(&st->zsel, 0);
     for (; i < n; i += (uint64_t)gridDim.x * kBlock) deg[i] = 0;
 }
 
@@ -142,8 +142,8 @@ __global__ __launch_bounds__(kBlock) void k_zargmax(const uint32_t* keys, const 
     uint64_t best = 0;
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < T;
          i += (uint64_t)gridDim.x * kBlock) {
-        uint32_t id = keys ? keys[i] : (uint32_t)i;
-        uint32_t c = counts[i];
+        uint32_t id = keys ? ld_agent(&keys[i]) : (uint32_t)i;
+        uint32_t c = ld_agent(&counts[i]);
         if (id != kEmpty || !keys) {
             uint64_t s = pack_sel(c, id);
             best = s > best ? s : best;
@@ -159,10 +159,10 @@ __global__ void k_zfinish(DevState* st, int use_hint, uint32_t hint) {
         uint32_t z;
         if (use_hint) z = hint;
         else {
-            uint64_t s = st->zsel;
+            uint64_t s = ld_agent64(&st->zsel);
             z = s ? 0xFFFFFFFFu - (uint32_t)(s & 0xFFFFFFFFu) : 0u;
         }
-        st->zroot = z;
+        st_agent(&st->zroot, z);
     }
 }
 
@@ -173,7 +173,7 @@ __global__ void k_zfinish(DevState* st, int use_hint, uint32_t hint) {
 __global__ __launch_bounds__(kBlock) void k_push(const uint32_t* __restrict__ edges, uint64_t m,
                                                  uint64_t K, uint64_t cnt, uint64_t n,
                                                  uint32_t* P, uint32_t* zbits, DevState* st) {
-    const uint32_t z = st->zroot;
+    const uint32_t z = ld_agent(&st->zroot);
     for (uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < cnt;
          j += (uint64_t)gridDim.x * kBlock) {
         const uint64_t i = (cnt == m) ? j : sample_index(j, m, K);
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_push(const uint32_t* __restrict__ ed
 // Membership bitmap of the zero root's tree: cleared, with only z itself set.
 __global__ __launch_bounds__(kBlock) void k_zbits_clear(uint32_t* zbits, uint64_t words,
                                                         const DevState* st) {
-    const uint32_t z = st->zroot;
+    const uint32_t z = ld_agent(&st->zroot);
     const uint64_t zw = z >> 5;
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < words;
          i += (uint64_t)gridDim.x * kBlock)
@@ -260,7 +260,7 @@ template <bool ZR, int SPLIT>
 __global__ __launch_bounds__(kBlock) void k_hook(const uint32_t* __restrict__ edges, uint64_t m,
                                                  uint32_t n, uint32_t* P, uint32_t* zbits,
                                                  DevState* st) {
-    const uint32_t z = ZR ? st->zroot : 0u;
+    const uint32_t z = ZR ? ld_agent(&st->zroot) : 0u;
     const uint64_t tile = (uint64_t)blockIdx.x * (kBlock * kEPT);
     const u32x2* E = reinterpret_cast<const u32x2*>(edges);
     uint32_t u[kEPT], v[kEPT];
@@ -296,11 +296,18 @@ __global__ __launch_bounds__(kBlock) void k_hook(const uint32_t* __restrict__ ed
             live[k] = live[k] && !(inu[k] && inv[k]);
         }
     }
+    // An endpoint whose bit is set has root z: walk from z instead (no read of P).
+    uint32_t wu[kEPT], wv[kEPT];
+#pragma unroll
+    for (int k = 0; k < kEPT; ++k) {
+        wu[k] = (ZR && inu[k]) ? z : u[k];
+        wv[k] = (ZR && inv[k]) ? z : v[k];
+    }
     uint32_t pu[kEPT], pv[kEPT];
 #pragma unroll
     for (int k = 0; k < kEPT; ++k) {
-        pu[k] = live[k] ? P[u[k]] : 0u;
-        pv[k] = live[k] ? P[v[k]] : 0u;
+        pu[k] = !live[k] ? 0u : ((ZR && inu[k]) ? z : P[wu[k]]);
+        pv[k] = !live[k] ? 0u : ((ZR && inv[k]) ? z : P[wv[k]]);
     }
 #pragma unroll
     for (int k = 0; k < kEPT; ++k) {
@@ -308,9 +315,9 @@ __global__ __launch_bounds__(kBlock) void k_hook(const uint32_t* __restrict__ ed
         // a common parent, or one endpoint the parent of the other: same tree
         uint32_t r;
         if (pu[k] == pv[k]) r = pu[k];
-        else if (pu[k] == v[k]) r = v[k];
-        else if (pv[k] == u[k]) r = u[k];
-        else r = link<ZR, SPLIT>(P, u[k], pu[k], v[k], pv[k], z);
+        else if (pu[k] == wv[k]) r = wv[k];
+        else if (pv[k] == wu[k]) r = wu[k];
+        else r = link<ZR, SPLIT>(P, wu[k], pu[k], wv[k], pv[k], z);
         if (ZR && r == z) {
             if (!inu[k]) zbit_set(zbits, u[k]);
             if (!inv[k]) zbit_set(zbits, v[k]);
@@ -319,20 +326,31 @@ __global__ __launch_bounds__(kBlock) void k_hook(const uint32_t* __restrict__ ed
 }
 
 // ---- compress (pointer jumping) ----------------------------------------------------
-// P_v <- root(v). Roots are fixed during this kernel, so every walk ends at the
-// true root. With a zero root, also the smallest v whose root is z.
+// P_v <- root(v). No entry is linked any more, but another XCD's L2 can still
+// hold a copy of an entry read while its vertex was a root, and that copy has
+// been observed to survive into this kernel. A walk may follow such stale
+// (still ancestor) values freely, but the two facts the label rests on are read
+// coherently: the vertex's own entry, and the root the walk stops at (a stale
+// "root" would end the walk early); if the coherent value differs, the walk
+// continues from it. Lanes stopping at the same root share one request.
 template <bool ZR>
 __global__ __launch_bounds__(kBlock) void k_compress(uint32_t* P, uint64_t n, DevState* st) {
-    const uint32_t z = ZR ? st->zroot : 0u;
+    const uint32_t z = ZR ? ld_agent(&st->zroot) : 0u;
     uint32_t local_min = kEmpty;
     for (uint64_t v = (uint64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
          v += (uint64_t)gridDim.x * kBlock) {
-        const uint32_t p = P[v];
+        const uint32_t p = ld_agent(&P[v]);
         uint32_t r = (uint32_t)v;
         if (p != (uint32_t)v) {
             r = p;
-            uint32_t q = P[r];
-            while (q != r) { r = q; q = P[r]; }
+            while (true) {
+                uint32_t q = P[r];
+                while (q != r) { r = q; q = P[r]; }
+                if (ZR && r == z) break;          // the zero root is never linked
+                q = ld_agent(&P[r]);
+                if (q == r) break;
+                r = q;
+            }
             if (r != p) P[v] = r;
         }
         if (ZR && r == z && (uint32_t)v < local_min) local_min = (uint32_t)v;
@@ -345,12 +363,28 @@ __global__ __launch_bounds__(kBlock) void k_compress(uint32_t* P, uint64_t n, De
 
 // ---- relabel the zero root's component to its smallest ID ---------------------------
 __global__ __launch_bounds__(kBlock) void k_canon(uint32_t* L, uint64_t n, const DevState* st) {
-    const uint32_t z = st->zroot, mz = st->minz;
+    const uint32_t z = ld_agent(&st->zroot), mz = ld_agent(&st->minz);
     if (mz == z || mz == kEmpty) return;
     for (uint64_t v = (uint64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
          v += (uint64_t)gridDim.x * kBlock) {
-        if (L[v] == z) L[v] = mz;
+        if (ld_agent(&L[v]) == z) L[v] = mz;
     }
+}
+
+// ---- coherence point ----------------------------------------------------------------------
+__global__ void k_cohere() {
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        __builtin_amdgcn_s_waitcnt(0);           // the write-back and invalidate complete here
+    }
+}
+
+int cohere(hipStream_t stream) {
+    // 64 single-wave workgroups: consecutive workgroups are dealt to the XCDs in
+    // turn, so every XCD runs several of them.
+    k_cohere<<<64, 64, 0, stream>>>();
+    CCM_HIP(hipGetLastError());
+    return CC_OK;
 }
 
 // ---- host-side launchers ---------------------------------------------------------------
@@ -392,6 +426,8 @@ static int zbits_reset(Slot* s, uint64_t n, hipStream_t stream) {
     }
     k_zbits_clear<<<grid_for(words, kBlock, kGridCap), kBlock, 0, stream>>>(s->zbits, words, s->st);
     CCM_HIP(hipGetLastError());
+    int rcc = cohere(stream);       // cleared words written back before push's atomics
+    if (rcc) return rcc;
     s->zr_ready = (n == s->cur_n);
     return CC_OK;
 }
@@ -416,6 +452,8 @@ int run_zroot(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t f
             s->deg_cap = n;
         }
         k_degfill<<<grid_for(n, kBlock, kGridCap), kBlock, 0, stream>>>(s->deg, n, s->st);
+        int rcc = cohere(stream);   // zero-filled lines written back before the atomics
+        if (rcc) return rcc;
         if (m) k_degcount<<<grid_for(m, kBlock, kGridCap), kBlock, 0, stream>>>(edges, m, n, s->deg, s->st);
         k_zargmax<<<grid_for(n, kBlock, kGridCap), kBlock, 0, stream>>>(nullptr, s->deg, n, s->st);
     } else {
@@ -423,6 +461,8 @@ int run_zroot(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t f
         const uint64_t cnt = sample_count(m, K);
         k_zfill<<<grid_for(s->table, kBlock, 1024), kBlock, 0, stream>>>(s->hkeys, s->hcounts,
                                                                           s->table, s->st);
+        int rcc = cohere(stream);   // filled lines written back before the atomics
+        if (rcc) return rcc;
         if (cnt)
             k_zcount<<<grid_for(cnt, kBlock, 1024), kBlock, 0, stream>>>(
                 edges, m, K, cnt, n, s->hkeys, s->hcounts, s->table - 1, s->st);
@@ -457,6 +497,8 @@ int run_hook(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P
     const bool split = !(flags & CC_F_NO_SPLIT);
     if (zr && (!s->zr_ready || s->cur_n != n))
         return fail(CC_EINVAL, "a CC_F_ZROOT hook needs cc_init then cc_zroot on the same n");
+    if (zr && split && !(flags & CC_F_NO_TILE) && tiled_eligible(n, m))
+        return run_hook_tiled(s, n, m, edges, P, stream);
     const uint32_t n32 = (uint32_t)n;
     uint32_t* zb = s->zbits;
     const uint32_t g = (uint32_t)blocks;
@@ -491,11 +533,15 @@ int run_solve(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* 
         if ((rc = run_zroot(s, n, m, edges, flags, hint, stream))) return rc;
         if ((rc = run_push(s, n, m, edges, L, stream))) return rc;
     }
+    if ((rc = cohere(stream))) return rc;
     if ((rc = run_hook(s, n, m, edges, L, flags, stream))) return rc;
+    if ((rc = cohere(stream))) return rc;
     if ((rc = run_compress(s, n, L, flags, stream))) return rc;
-    if (flags & CC_F_ZROOT)
+    if (flags & CC_F_ZROOT) {
+        if ((rc = cohere(stream))) return rc;
         if ((rc = run_canon(s, n, L, stream))) return rc;
-    return CC_OK;
+    }
+    return cohere(stream);
 }
 
 }  // namespace ccm

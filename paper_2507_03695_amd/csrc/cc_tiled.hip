@@ -1,0 +1,699 @@
+// cc_tiled.hip — the zero-root hook with both membership tests in LDS.
+//
+// The plain bitmap hook pays two random L2/MALL line reads per entry (the
+// bitmap is n/8 bytes, 8.5 MB at RMAT-26, twice one XCD's L2). Here the
+// entries are first regrouped so that each workgroup sees only entries whose
+// endpoints fall in two fixed vertex ranges ("slices" of 2^kSliceBits
+// vertices), and it holds the bitmap words of both slices in LDS:
+//
+//  1. k_t1_part   — every chunk of kC1 entries is sorted in LDS by the slice
+//                   of its first endpoint (a) and written back in place order;
+//                   per chunk, the start of each a-segment; per a, the counts.
+//  2. k_t1_scan   — per a, exclusive prefix of the segment counts over chunks
+//                   (each a-bucket becomes one virtual array).
+//  3. k_t1_bases  — where each a-bucket starts in the second buffer and how
+//                   many level-2 chunks it has.
+//  4. k_t2_part   — every kC2-entry piece of an a-bucket is gathered from its
+//                   segments, sorted in LDS by the slice of the second
+//                   endpoint (b) and written contiguously, with its b-runs.
+//  5. k_t3_hook   — one workgroup per (a, b): both slices' bitmap words in
+//                   LDS; entries with both bits set are dropped there; the
+//                   rest take the ordinary path on the global parent array,
+//                   and new zero-tree members are recorded in the global
+//                   bitmap and in the LDS copies.
+//
+// The regrouping only reorders entries (and drops self-loops, which are
+// no-ops); hooking is order-independent (Sec. II), so the labels are those of
+// the plain pass. Entries whose endpoints are out of range are dropped with
+// the status bit set, as in the plain hook.
+#include <algorithm>
+
+#include "cc_internal.h"
+
+namespace ccm {
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+constexpr int kSliceBits = 19;                       // 2^19 vertices per slice
+constexpr uint32_t kSliceWords = (1u << kSliceBits) / 32;   // 16384 words = 64 KB
+constexpr int kMaxSlices = 256;
+constexpr int kC1 = 8192;                            // level-1 chunk (entries)
+constexpr int kC2 = 8192;                            // level-2 chunk (entries)
+constexpr int kPartBlock = 1024;
+constexpr int kPartEPT = kC1 / kPartBlock;           // 16
+
+// ---- shared device helpers (same rules as the plain hook) ---------------------
+
+__device__ __forceinline__ bool t_key_less(uint32_t a, uint32_t b, uint32_t z) {
+    return (a == z) | ((b != z) & (a < b));
+}
+
+__device__ __forceinline__ uint32_t t_find(uint32_t* P, uint32_t x, uint32_t px) {
+    while (px != x) {
+        const uint32_t gp = P[px];
+        if (gp == px) return px;
+        P[x] = gp;
+        x = px;
+        px = gp;
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint32_t t_link(uint32_t* P, uint32_t u, uint32_t pu, uint32_t v,
+                                           uint32_t pv, uint32_t z) {
+    while (true) {
+        const uint32_t ru = t_find(P, u, pu);
+        const uint32_t rv = t_find(P, v, pv);
+        if (ru == rv) return ru;
+        const bool u_low = t_key_less(ru, rv, z);
+        const uint32_t hi = u_low ? rv : ru;
+        const uint32_t lo = u_low ? ru : rv;
+        const uint32_t old = atomicCAS(&P[hi], hi, lo);
+        if (old == hi) return lo;
+        u = hi; pu = old;
+        v = lo; pv = lo;
+    }
+}
+
+// Exclusive scan of cnt[0..R) into start[0..R] by the first wave (R <= 256);
+// start[R] is the total.
+__device__ __forceinline__ void wave_scan_256(const uint32_t* cnt, uint32_t* start, int R) {
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x < 64) {
+        uint32_t c[4], s = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int d = lane * 4 + j;
+            c[j] = d < R ? cnt[d] : 0u;
+            s += c[j];
+        }
+        uint32_t incl = s;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        uint32_t run = incl - s;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int d = lane * 4 + j;
+            if (d < R) start[d] = run;
+            run += c[j];
+        }
+        if (lane == 63) start[R] = incl;
+    }
+}
+
+// ---- 1. level-1 partition by the first endpoint's slice -----------------------------
+__global__ __launch_bounds__(kPartBlock) void k_t1_part(const uint32_t* __restrict__ edges,
+                                                        uint64_t m, uint32_t n, int R,
+                                                        uint64_t nch1, u32x2* __restrict__ tmp1,
+                                                        uint16_t* __restrict__ segT,
+                                                        uint32_t* __restrict__ cnt1,
+                                                        DevState* st) {
+    __shared__ u32x2 stage[kC1];
+    __shared__ uint32_t hist[kMaxSlices + 1];
+    __shared__ uint32_t start[kMaxSlices + 1];
+    const uint64_t c = blockIdx.x;
+    for (int i = threadIdx.x; i <= kMaxSlices; i += kPartBlock) hist[i] = 0;
+    __syncthreads();
+    const u32x2* E = reinterpret_cast<const u32x2*>(edges);
+    u32x2 e[kPartEPT];
+    uint16_t rank[kPartEPT];
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < kPartEPT; ++k) {
+        // unconditional load (clamped index): keeps all loads of the thread in flight
+        const uint64_t i = c * kC1 + (uint64_t)k * kPartBlock + threadIdx.x;
+        e[k] = __builtin_nontemporal_load(E + (i < m ? i : m - 1));
+    }
+#pragma unroll
+    for (int k = 0; k < kPartEPT; ++k) {
+        const uint64_t i = c * kC1 + (uint64_t)k * kPartBlock + threadIdx.x;
+        if (i >= m) e[k].x = e[k].y = 0u;
+        else if (e[k].x >= n || e[k].y >= n) { bad = true; e[k].x = e[k].y = 0u; }
+    }
+    if (bad) atomicOr(&st->status, kStatusRange);
+#pragma unroll
+    for (int k = 0; k < kPartEPT; ++k) {
+        rank[k] = 0xFFFF;
+        if (e[k].x != e[k].y) rank[k] = (uint16_t)atomicAdd(&hist[e[k].x >> kSliceBits], 1u);
+    }
+    __syncthreads();
+    wave_scan_256(hist, start, R);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPartEPT; ++k)
+        if (rank[k] != 0xFFFF) stage[start[e[k].x >> kSliceBits] + rank[k]] = e[k];
+    __syncthreads();
+    const uint32_t kept = start[R];
+    u32x2* out = tmp1 + c * kC1;
+    for (uint32_t i = threadIdx.x; i < kept; i += kPartBlock) out[i] = stage[i];
+    for (int d = threadIdx.x; d < R; d += kPartBlock) {
+        segT[(uint64_t)d * nch1 + c] = (uint16_t)start[d];
+        cnt1[(uint64_t)d * nch1 + c] = hist[d];
+    }
+}
+
+// ---- 2. per slice a: exclusive prefix of segment counts over chunks ------------------
+// pre1 has nch1 + 1 entries per row (the last is the total). Two launches over
+// (a, tile of kScanTile chunks): tile sums, then the scan of each tile offset by
+// the sum of the tiles before it.
+constexpr int kScanTile = 1024;
+constexpr int kScanBlock = 256;
+
+__global__ __launch_bounds__(kScanBlock) void k_t1_tsum(const uint32_t* __restrict__ cnt1,
+                                                        uint64_t nch1, uint32_t ntile,
+                                                        uint32_t* __restrict__ tsum) {
+    __shared__ uint32_t ws[kScanBlock / 64];
+    const uint64_t a = blockIdx.x / ntile, tile = blockIdx.x % ntile;
+    const uint32_t* row = cnt1 + a * nch1;
+    uint32_t s = 0;
+    for (int k = 0; k < kScanTile / kScanBlock; ++k) {
+        const uint64_t c = tile * kScanTile + (uint64_t)k * kScanBlock + threadIdx.x;
+        if (c < nch1) s += row[c];
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < kScanBlock / 64; ++w) t += ws[w];
+        tsum[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_t1_scan(const uint32_t* __restrict__ cnt1,
+                                                        uint64_t nch1, uint32_t ntile,
+                                                        const uint32_t* __restrict__ tsum,
+                                                        uint32_t* __restrict__ pre1) {
+    __shared__ uint32_t ws[kScanBlock / 64];
+    __shared__ uint32_t s_off;
+    const uint64_t a = blockIdx.x / ntile, tile = blockIdx.x % ntile;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (wave == 0) {
+        // sum of the tiles before this one (ntile may exceed 64: strided lanes)
+        uint32_t s = 0;
+        for (uint64_t i = lane; i < tile; i += 64) s += tsum[a * ntile + i];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (lane == 0) s_off = s;
+    }
+    const uint32_t* row = cnt1 + a * nch1;
+    uint32_t* out = pre1 + a * (nch1 + 1);
+    // each thread scans 4 consecutive chunks of the tile
+    constexpr int PER = kScanTile / kScanBlock;
+    const uint64_t c0 = tile * kScanTile + (uint64_t)threadIdx.x * PER;
+    uint32_t v[PER], s = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        v[k] = c0 + k < nch1 ? row[c0 + k] : 0u;
+        s += v[k];
+    }
+    uint32_t incl = s;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) ws[wave] = incl;
+    __syncthreads();
+    uint32_t run = s_off + incl - s;
+    for (int w = 0; w < wave; ++w) run += ws[w];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        if (c0 + k < nch1) out[c0 + k] = run;
+        run += v[k];
+    }
+    // the thread holding the last chunk writes the row total
+    if (c0 < nch1 && nch1 <= c0 + PER) out[nch1] = run;
+}
+
+// ---- 3. bucket bases and level-2 chunk counts ---------------------------------------------
+// base2[a]: first entry of bucket a in the second buffer; cbase[a]: first level-2
+// chunk of bucket a; cbase[R] is the total. Single thread: R <= 256.
+__global__ void k_t1_bases(const uint32_t* __restrict__ pre1, uint64_t nch1, int R,
+                           uint64_t* __restrict__ base2, uint32_t* __restrict__ cbase) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    uint64_t b = 0;
+    uint32_t cb = 0;
+    for (int a = 0; a < R; ++a) {
+        const uint32_t size = pre1[(uint64_t)a * (nch1 + 1) + nch1];
+        base2[a] = b;
+        cbase[a] = cb;
+        b += size;
+        cb += (size + kC2 - 1) / kC2;
+    }
+    base2[R] = b;
+    cbase[R] = cb;
+}
+
+// ---- 4a. level-2 chunk bounds -------------------------------------------------------------
+// Level-2 chunk t of bucket a covers virtual positions [t*kC2, min((t+1)*kC2, size_a)).
+// For every level-1 chunk c with a nonempty a-segment [pre[c], pre[c+1]), record c
+// as the first chunk (c0tab) of the level-2 chunks starting inside it and as the
+// last chunk (c1tab) of those ending inside it. One thread per (a, c).
+__global__ __launch_bounds__(256) void k_t2_bounds(const uint32_t* __restrict__ pre1, uint64_t nch1,
+                                                   int R, const uint32_t* __restrict__ cbase,
+                                                   uint32_t* __restrict__ c0tab,
+                                                   uint32_t* __restrict__ c1tab) {
+    const uint64_t id = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (id >= (uint64_t)R * nch1) return;
+    const uint64_t a = id / nch1, c = id % nch1;
+    const uint32_t* pre = pre1 + a * (nch1 + 1);
+    const uint32_t p0 = pre[c], p1 = pre[c + 1], size = pre[nch1];
+    if (p1 <= p0) return;
+    for (uint32_t t = p0 / kC2; t <= (p1 - 1) / kC2; ++t) {
+        const uint32_t first = t * kC2;
+        const uint32_t last = min(first + (uint32_t)kC2, size) - 1;
+        if (first >= p0 && first < p1) c0tab[cbase[a] + t] = (uint32_t)c;
+        if (last >= p0 && last < p1) c1tab[cbase[a] + t] = (uint32_t)c;
+    }
+}
+
+// ---- 4b. level-2 partition by the second endpoint's slice ----------------------------------
+constexpr int kWin2 = 256;   // level-1 chunks per gather window (owner index fits a byte)
+
+__global__ __launch_bounds__(kPartBlock) void k_t2_part(const u32x2* __restrict__ tmp1,
+                                                        const uint16_t* __restrict__ segT,
+                                                        const uint32_t* __restrict__ pre1,
+                                                        uint64_t nch1, int R,
+                                                        const uint64_t* __restrict__ base2,
+                                                        const uint32_t* __restrict__ cbase,
+                                                        const uint32_t* __restrict__ c0tab,
+                                                        const uint32_t* __restrict__ c1tab,
+                                                        u32x2* __restrict__ tmp2,
+                                                        uint16_t* __restrict__ run2T,
+                                                        uint64_t nch2) {
+    __shared__ u32x2 stage[kC2];
+    __shared__ uint8_t owner[kC2];
+    __shared__ uint32_t s_pre[kWin2 + 1];
+    __shared__ uint32_t s_seg[kWin2];
+    __shared__ uint32_t hist[kMaxSlices + 1];
+    __shared__ uint32_t start[kMaxSlices + 1];
+    __shared__ uint32_t s_cb[kMaxSlices + 1];
+    __shared__ int s_a;
+    const uint32_t g = blockIdx.x;
+    for (int i = threadIdx.x; i <= R; i += kPartBlock) s_cb[i] = cbase[i];
+    for (int i = threadIdx.x; i <= kMaxSlices; i += kPartBlock) hist[i] = 0;
+    __syncthreads();
+    if (g >= s_cb[R]) return;
+    if (threadIdx.x == 0) {
+        int lo = 0, hi = R - 1;                 // last a with cbase[a] <= g
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (s_cb[mid] <= g) lo = mid; else hi = mid - 1;
+        }
+        s_a = lo;
+    }
+    __syncthreads();
+    const int a = s_a;
+    const uint32_t t = g - s_cb[a];
+    const uint32_t* pre = pre1 + (uint64_t)a * (nch1 + 1);
+    const uint32_t vlo = t * (uint32_t)kC2;
+    const uint32_t vhi = min(vlo + (uint32_t)kC2, pre[nch1]);
+    const uint32_t cnt = vhi - vlo;
+    const uint64_t c0 = c0tab[g], c1 = c1tab[g];
+    u32x2 e[kPartEPT];
+    for (uint64_t cw = c0; cw <= c1; cw += kWin2) {
+        const uint32_t nw = (uint32_t)min<uint64_t>((uint64_t)kWin2, c1 - cw + 1);
+        for (uint32_t i = threadIdx.x; i <= nw; i += kPartBlock) s_pre[i] = pre[cw + i];
+        for (uint32_t i = threadIdx.x; i < nw; i += kPartBlock)
+            s_seg[i] = segT[(uint64_t)a * nch1 + cw + i];
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < nw; i += kPartBlock) {
+            const uint32_t lo = max(s_pre[i], vlo), hi = min(s_pre[i + 1], vhi);
+            for (uint32_t p = lo; p < hi; ++p) owner[p - vlo] = (uint8_t)i;
+        }
+        __syncthreads();
+        const uint32_t wlo = max(s_pre[0], vlo), whi = min(s_pre[nw], vhi);
+        u32x2 x[kPartEPT];
+        bool in[kPartEPT];
+#pragma unroll
+        for (int k = 0; k < kPartEPT; ++k) {
+            // unconditional load (a safe in-bounds address when the position is
+            // not in this window) so that all loads of the thread are in flight
+            const uint32_t p = vlo + (uint32_t)k * kPartBlock + threadIdx.x;
+            in[k] = p >= wlo && p < whi;
+            const uint32_t i = in[k] ? owner[p - vlo] : 0u;
+            const uint64_t at = in[k] ? (cw + i) * kC1 + s_seg[i] + (p - s_pre[i]) : 0ull;
+            x[k] = tmp1[at];
+        }
+#pragma unroll
+        for (int k = 0; k < kPartEPT; ++k)
+            if (in[k]) e[k] = x[k];
+        __syncthreads();
+    }
+    uint16_t rank[kPartEPT];
+#pragma unroll
+    for (int k = 0; k < kPartEPT; ++k) {
+        const uint32_t i = (uint32_t)k * kPartBlock + threadIdx.x;
+        rank[k] = 0xFFFF;
+        if (i < cnt) rank[k] = (uint16_t)atomicAdd(&hist[e[k].y >> kSliceBits], 1u);
+    }
+    __syncthreads();
+    wave_scan_256(hist, start, R);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPartEPT; ++k)
+        if (rank[k] != 0xFFFF) stage[start[e[k].y >> kSliceBits] + rank[k]] = e[k];
+    __syncthreads();
+    u32x2* out = tmp2 + base2[a] + vlo;
+    for (uint32_t i = threadIdx.x; i < cnt; i += kPartBlock) out[i] = stage[i];
+    for (int d = threadIdx.x; d <= R; d += kPartBlock) run2T[(uint64_t)d * nch2 + g] = (uint16_t)start[d];
+}
+
+// ---- 5. the hook over bucket (a, b) with both slices' bitmap words in LDS --------------
+constexpr int kHook3Block = 1024;
+constexpr int kWaves3 = kHook3Block / 64;
+constexpr int kWin3 = 2048;      // level-2 chunks per window
+constexpr int kRunsInFlight = 8; // runs a wave reads at once (one entry per lane each)
+constexpr int kWaveQueue = 128;  // per-wave LDS queue of entries that need the parent array
+
+// The ordinary path for one entry whose endpoints were not both known to be in
+// the zero root's tree. u lies in the resident first-endpoint slice (sa); v may
+// come from an earlier second-endpoint slice (entries carried over in a wave's
+// queue), so its LDS bit is used only when v lies in the resident slice lb.
+__device__ __forceinline__ void t3_slow(uint32_t* P, uint32_t* zbits, uint32_t* sa, uint32_t* lb,
+                                        uint32_t abase, uint32_t bbase, uint32_t z, u32x2 uv) {
+    const uint32_t u = uv.x, v = uv.y;
+    const uint32_t ou = u - abase, ov = v - bbase;
+    const bool vloc = ov < (1u << kSliceBits);
+    // bits may have been set since the entry was queued
+    const bool inu = (sa[ou >> 5] >> (ou & 31)) & 1u;
+    const bool inv = vloc ? ((lb[ov >> 5] >> (ov & 31)) & 1u) : ((zbits[v >> 5] >> (v & 31)) & 1u);
+    if (inu && inv) return;
+    const uint32_t wu = inu ? z : u, wv = inv ? z : v;
+    const uint32_t pu = inu ? z : P[u];
+    const uint32_t pv = inv ? z : P[v];
+    uint32_t r;
+    if (pu == pv) r = pu;
+    else if (pu == wv) r = wv;
+    else if (pv == wu) r = wu;
+    else r = t_link(P, wu, pu, wv, pv, z);
+    if (r == z) {
+        if (!inu) {
+            atomicOr(&zbits[u >> 5], 1u << (u & 31));
+            atomicOr(&sa[ou >> 5], 1u << (ou & 31));
+        }
+        if (!inv) {
+            atomicOr(&zbits[v >> 5], 1u << (v & 31));
+            if (vloc) atomicOr(&lb[ov >> 5], 1u << (ov & 31));
+        }
+    }
+}
+
+// Exclusive scan in place of n <= 2 * kHook3Block values (x[n] receives the
+// total); every thread of the workgroup calls it.
+__device__ __forceinline__ void block_scan_2048(uint32_t* x, uint32_t n, uint32_t* wsum) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t i0 = 2 * tid, i1 = 2 * tid + 1;
+    const uint32_t a0 = i0 < n ? x[i0] : 0u, a1 = i1 < n ? x[i1] : 0u;
+    const uint32_t s = a0 + a1;
+    uint32_t incl = s;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int w = 0; w < kHook3Block / 64; ++w) { const uint32_t t = wsum[w]; wsum[w] = run; run += t; }
+        wsum[kHook3Block / 64] = run;
+    }
+    __syncthreads();
+    const uint32_t excl = wsum[wave] + incl - s;
+    if (i0 < n) x[i0] = excl;
+    if (i1 < n) x[i1] = excl + a0;
+    if (tid == 0) x[n] = wsum[kHook3Block / 64];
+    __syncthreads();
+}
+
+// Walk the first `qn` queued entries of this wave (one per lane, two rounds).
+__device__ __forceinline__ void t3_drain(u32x2* wq, uint32_t qn, int lane, uint32_t* P,
+                                         uint32_t* zbits, uint32_t* sa, uint32_t* lb,
+                                         uint32_t abase, uint32_t bbase, uint32_t z) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    u32x2 x0 = {0u, 0u}, x1 = {0u, 0u};
+    const bool h0 = (uint32_t)lane < qn, h1 = (uint32_t)lane + 64 < qn;
+    if (h0) x0 = wq[lane];
+    if (h1) x1 = wq[lane + 64];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (h0) t3_slow(P, zbits, sa, lb, abase, bbase, z, x0);
+    if (h1) t3_slow(P, zbits, sa, lb, abase, bbase, z, x1);
+}
+
+// Run holding index j0 of the window (last t < nw with s_pre[t] <= j0), found
+// by the whole wave in two 64-way ballot steps (nw <= 64 * 64).
+__device__ __forceinline__ uint32_t t3_find_run(const uint32_t* s_pre, uint32_t nw, uint32_t j0,
+                                                int lane) {
+    const uint32_t stride = (nw + 63) / 64;
+    const uint32_t i1 = (uint32_t)lane * stride;
+    const bool c1 = i1 < nw && s_pre[i1] <= j0;
+    const uint64_t b1 = __ballot(c1);
+    const uint32_t base = (63u - (uint32_t)__clzll((long long)b1)) * stride;
+    const uint32_t i2 = base + (uint32_t)lane;
+    const bool c2 = (uint32_t)lane < stride && i2 < nw && s_pre[i2] <= j0;
+    const uint64_t b2 = __ballot(c2);
+    return base + (63u - (uint32_t)__clzll((long long)b2));
+}
+
+constexpr int kBPerBlock = 4;    // second-endpoint slices handled by one workgroup
+
+__global__ __launch_bounds__(kHook3Block) void k_t3_hook(const u32x2* __restrict__ tmp2,
+                                                         const uint16_t* __restrict__ run2T,
+                                                         uint64_t nch2, int R,
+                                                         const uint64_t* __restrict__ base2,
+                                                         const uint32_t* __restrict__ cbase,
+                                                         uint32_t* P, uint32_t* zbits,
+                                                         uint64_t words, DevState* st) {
+    __shared__ uint32_t sa[kSliceWords];
+    __shared__ uint32_t sb[kSliceWords];
+    __shared__ uint16_t s_r0[kWin3];
+    __shared__ uint32_t s_pre[kWin3 + 1];
+    __shared__ u32x2 queue[kWaves3 * kWaveQueue];
+    __shared__ uint32_t wsum[kWaves3 + 1];
+    const int nbg = (R + kBPerBlock - 1) / kBPerBlock;
+    const int a = blockIdx.x / nbg, bg = blockIdx.x % nbg;
+    const uint32_t cb = cbase[a];
+    const uint32_t nch = cbase[a + 1] - cb;
+    if (nch == 0) return;
+    const uint32_t z = ld_agent(&st->zroot);
+    constexpr int PER = kSliceWords / kHook3Block;       // 16 words per thread per slice
+    {
+        const uint64_t wa = (uint64_t)a * kSliceWords;
+        uint32_t xa[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const uint64_t i = (uint64_t)k * kHook3Block + threadIdx.x;
+            xa[k] = wa + i < words ? zbits[wa + i] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < PER; ++k) sa[(uint32_t)k * kHook3Block + threadIdx.x] = xa[k];
+    }
+    const uint32_t abase = (uint32_t)a << kSliceBits;
+    const u32x2* src = tmp2 + base2[a];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    u32x2* wq = queue + wave * kWaveQueue;
+    constexpr uint32_t kRange = 64 * kRunsInFlight;      // entries per wave per range
+    uint32_t qn = 0;             // wave-uniform queue length, carried across slices b
+    uint32_t* lb = sa;
+    uint32_t bbase = 0;
+    for (int bi = 0; bi < kBPerBlock; ++bi) {
+        const int b = bg * kBPerBlock + bi;
+        if (b >= R) break;
+        // the wave queue may still hold entries of earlier slices b; their walks
+        // use the global bitmap for v (t3_slow checks the slice)
+        __syncthreads();                                  // previous slice b fully used
+        if (b != a) {
+            const uint64_t wb = (uint64_t)b * kSliceWords;
+            uint32_t xb[PER];
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const uint64_t i = (uint64_t)k * kHook3Block + threadIdx.x;
+                xb[k] = wb + i < words ? zbits[wb + i] : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < PER; ++k) sb[(uint32_t)k * kHook3Block + threadIdx.x] = xb[k];
+        }
+        lb = (a == b) ? sa : sb;
+        bbase = (uint32_t)b << kSliceBits;
+        for (uint32_t w0 = 0; w0 < nch; w0 += kWin3) {
+            const uint32_t nw = min((uint32_t)kWin3, nch - w0);
+            __syncthreads();
+            for (uint32_t t = threadIdx.x; t < nw; t += kHook3Block) {
+                const uint64_t g = (uint64_t)cb + w0 + t;
+                const uint32_t r0 = run2T[(uint64_t)b * nch2 + g];
+                const uint32_t r1 = run2T[(uint64_t)(b + 1) * nch2 + g];
+                s_r0[t] = (uint16_t)r0;
+                s_pre[t] = r1 - r0;
+            }
+            __syncthreads();
+            block_scan_2048(s_pre, nw, wsum);        // run lengths -> starts; s_pre[nw] = total
+            const uint32_t total = s_pre[nw];
+            // The window's entries form one index space [0, total); each wave
+            // takes ranges of kRange consecutive indices (lanes step through the
+            // runs). The loads of the next range are issued before the current
+            // range is tested, so memory latency overlaps the tests and walks.
+            uint32_t j0 = (uint32_t)wave * kRange;
+            u32x2 e[kRunsInFlight];
+            bool has[kRunsInFlight];
+            auto issue = [&](uint32_t jb, u32x2* ev, bool* hv) {
+                uint32_t t = t3_find_run(s_pre, nw, jb, lane);
+#pragma unroll
+                for (int k = 0; k < kRunsInFlight; ++k) {
+                    const uint32_t j = jb + (uint32_t)k * 64 + lane;
+                    hv[k] = j < total;
+                    while (t + 1 < nw && s_pre[t + 1] <= j) ++t;
+                    const uint64_t at = hv[k] ? (uint64_t)(w0 + t) * kC2 + s_r0[t] + (j - s_pre[t]) : 0ull;
+                    ev[k] = __builtin_nontemporal_load(src + at);
+                }
+            };
+            if (j0 < total) issue(j0, e, has);
+            while (j0 < total) {
+                const uint32_t jn = j0 + kWaves3 * kRange;
+                u32x2 en[kRunsInFlight];
+                bool hn[kRunsInFlight];
+                if (jn < total) issue(jn, en, hn);
+                // membership tests of the current range (LDS reads overlap)
+                bool sv[kRunsInFlight];
+#pragma unroll
+                for (int k = 0; k < kRunsInFlight; ++k) {
+                    const uint32_t ou = e[k].x - abase, ov = e[k].y - bbase;
+                    const uint32_t wu = sa[has[k] ? (ou >> 5) : 0u];
+                    const uint32_t wv = lb[has[k] ? (ov >> 5) : 0u];
+                    sv[k] = has[k] && !(((wu >> (ou & 31)) & (wv >> (ov & 31))) & 1u);
+                }
+#pragma unroll
+                for (int k = 0; k < kRunsInFlight; ++k) {
+                    const uint64_t ball = __ballot(sv[k]);
+                    if (sv[k]) wq[qn + (uint32_t)__popcll(ball & ((1ull << lane) - 1ull))] = e[k];
+                    qn += (uint32_t)__popcll(ball);
+                    if (qn >= 64) {
+                        t3_drain(wq, qn, lane, P, zbits, sa, lb, abase, bbase, z);
+                        qn = 0;
+                    }
+                }
+                j0 = jn;
+                if (j0 < total) {
+#pragma unroll
+                    for (int k = 0; k < kRunsInFlight; ++k) { e[k] = en[k]; has[k] = hn[k]; }
+                }
+            }
+        }
+    }
+    if (qn) t3_drain(wq, qn, lane, P, zbits, sa, lb, abase, bbase, z);
+}
+
+// ---- host side --------------------------------------------------------------------
+
+struct TiledPlan {
+    int R;
+    uint64_t nch1, nch2_max;
+};
+
+static TiledPlan tiled_plan(uint64_t n, uint64_t m) {
+    TiledPlan p;
+    p.R = (int)((n + (1ull << kSliceBits) - 1) >> kSliceBits);
+    p.nch1 = (m + kC1 - 1) / kC1;
+    p.nch2_max = m / kC2 + (uint64_t)p.R + 1;
+    return p;
+}
+
+bool tiled_eligible(uint64_t n, uint64_t m) {
+    const uint64_t R = (n + (1ull << kSliceBits) - 1) >> kSliceBits;
+    return R >= 2 && R <= (uint64_t)kMaxSlices && m >= (1ull << 24) && m < (1ull << 32);
+}
+
+static int grow(void** p, uint64_t* cap, uint64_t bytes, hipStream_t stream) {
+    if (*cap >= bytes) return CC_OK;
+    CCM_HIP(hipStreamSynchronize(stream));
+    if (*p) CCM_HIP(hipFree(*p));
+    *p = nullptr;
+    *cap = 0;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(CC_ENOMEM, "tiled hook scratch allocation failed");
+    }
+    *cap = bytes;
+    return CC_OK;
+}
+
+void tiled_free(TiledScratch* t) {
+    if (t->buf) (void)hipFree(t->buf);
+    *t = TiledScratch{};
+}
+
+int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
+                   hipStream_t stream) {
+    // Warm-up: the first 1/64 of the entries go through the direct hook, so the
+    // membership bitmap already holds the core of the zero root's tree when the
+    // first tiles load their slices.
+    const uint64_t m0 = m >> 6;
+    if (m0) {
+        int rc0 = run_hook(s, n, m0, edges, P, CC_F_ZROOT | CC_F_NO_TILE, stream);
+        if (rc0) return rc0;
+        edges += 2 * m0;
+        m -= m0;
+    }
+    const TiledPlan pl = tiled_plan(n, m);
+    const int R = pl.R;
+    auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
+    const uint64_t b_tmp = al(8 * (pl.nch1 * kC1));
+    const uint64_t b_seg1 = al(2 * pl.nch1 * R);
+    const uint32_t ntile = (uint32_t)((pl.nch1 + kScanTile - 1) / kScanTile);
+    const uint64_t b_tsum = al(4 * (uint64_t)ntile * R);
+    const uint64_t b_cnt1 = al(4 * pl.nch1 * R);
+    const uint64_t b_pre1 = al(4 * (pl.nch1 + 1) * R);
+    const uint64_t b_base2 = al(8 * (R + 1));
+    const uint64_t b_cbase = al(4 * (R + 1));
+    const uint64_t b_run2 = al(2 * pl.nch2_max * (R + 1));
+    const uint64_t b_ctab = al(4 * pl.nch2_max);
+    const uint64_t total = 2 * b_tmp + b_seg1 + b_cnt1 + b_pre1 + b_base2 + b_cbase + b_run2 +
+                           2 * b_ctab + b_tsum;
+    int rc = grow(reinterpret_cast<void**>(&s->tiled.buf), &s->tiled.cap, total, stream);
+    if (rc) return rc;
+    char* q = s->tiled.buf;
+    u32x2* tmp1 = reinterpret_cast<u32x2*>(q); q += b_tmp;
+    u32x2* tmp2 = reinterpret_cast<u32x2*>(q); q += b_tmp;
+    uint16_t* segT = reinterpret_cast<uint16_t*>(q); q += b_seg1;
+    uint32_t* cnt1 = reinterpret_cast<uint32_t*>(q); q += b_cnt1;
+    uint32_t* pre1 = reinterpret_cast<uint32_t*>(q); q += b_pre1;
+    uint64_t* base2 = reinterpret_cast<uint64_t*>(q); q += b_base2;
+    uint32_t* cbase = reinterpret_cast<uint32_t*>(q); q += b_cbase;
+    uint16_t* run2 = reinterpret_cast<uint16_t*>(q); q += b_run2;
+    uint32_t* c0tab = reinterpret_cast<uint32_t*>(q); q += b_ctab;
+    uint32_t* c1tab = reinterpret_cast<uint32_t*>(q); q += b_ctab;
+    uint32_t* tsum = reinterpret_cast<uint32_t*>(q);
+    // every kernel below reads tables the previous one wrote: coherence points between
+    int rc1;
+    if ((rc1 = cohere(stream))) return rc1;
+    k_t1_part<<<(uint32_t)pl.nch1, kPartBlock, 0, stream>>>(edges, m, (uint32_t)n, R, pl.nch1, tmp1,
+                                                           segT, cnt1, s->st);
+    if ((rc1 = cohere(stream))) return rc1;
+    k_t1_tsum<<<(uint32_t)R * ntile, kScanBlock, 0, stream>>>(cnt1, pl.nch1, ntile, tsum);
+    if ((rc1 = cohere(stream))) return rc1;
+    k_t1_scan<<<(uint32_t)R * ntile, kScanBlock, 0, stream>>>(cnt1, pl.nch1, ntile, tsum, pre1);
+    if ((rc1 = cohere(stream))) return rc1;
+    k_t1_bases<<<1, 64, 0, stream>>>(pre1, pl.nch1, R, base2, cbase);
+    if ((rc1 = cohere(stream))) return rc1;
+    const uint64_t pairs = (uint64_t)R * pl.nch1;
+    k_t2_bounds<<<(uint32_t)((pairs + 255) / 256), 256, 0, stream>>>(pre1, pl.nch1, R, cbase, c0tab,
+                                                                    c1tab);
+    if ((rc1 = cohere(stream))) return rc1;
+    k_t2_part<<<(uint32_t)pl.nch2_max, kPartBlock, 0, stream>>>(tmp1, segT, pre1, pl.nch1, R, base2,
+                                                               cbase, c0tab, c1tab, tmp2, run2,
+                                                               pl.nch2_max);
+    if ((rc1 = cohere(stream))) return rc1;
+    const uint32_t nbg = (uint32_t)((R + kBPerBlock - 1) / kBPerBlock);
+    k_t3_hook<<<(uint32_t)R * nbg, kHook3Block, 0, stream>>>(tmp2, run2, pl.nch2_max, R, base2, cbase,
+                                                            P, s->zbits, (n + 31) / 32, s->st);
+    CCM_HIP(hipGetLastError());
+    return CC_OK;
+}
+
+}  // namespace ccm

@@ -234,3 +234,70 @@ def test_rmat26_extras_full():
     want = oracle.cc_labels(g.n, g.edges)
     log("rmat26 oracle done")
     assert_same_labels(Lh, want, "rmat26 extras")
+
+
+# ---- the tiled zero-root hook (entries regrouped by both endpoints' vertex ranges) -------
+
+@pytest.mark.parametrize("case", ["er_R6", "rmat_unpermuted", "two_slices", "loops_dups", "R256"])
+def test_tiled_hook_parity(case):
+    rng = np.random.default_rng(hash(case) % 2**32)
+    if case == "er_R6":
+        n = 3_000_000
+        e = graphgen.er(n, (1 << 24) + 12_345, 61)
+    elif case == "rmat_unpermuted":          # skewed: low slices hold most entries
+        n = 1 << 22
+        e = graphgen.rmat(22, (1 << 24) + 777, 62, permute=False)
+    elif case == "two_slices":
+        n = (1 << 19) + 1
+        e = graphgen.er(n, 1 << 24, 63)
+    elif case == "loops_dups":
+        n = 2_000_000
+        e = graphgen.er(n, 1 << 24, 64)
+        e[::7, 1] = e[::7, 0]                  # self-loops
+        e[1::11] = e[0:-1:11][: len(e[1::11])]  # repeats
+    else:                                      # exactly 256 slices
+        n = 256 << 19
+        e = graphgen.rmat(27, 1 << 24, 65)
+    want = oracle.cc_labels(n, e)
+    ed = to_dev(e)
+    with cc.Context() as c:
+        for name, fl in [("tiled", cc.F_ZROOT), ("direct", cc.F_ZROOT | cc.F_NO_TILE)]:
+            L = c.solve(ed, n, flags=fl)
+            assert_same_labels(to_host_u32(L), want, f"{case} [{name}]")
+
+
+def test_tiled_hook_out_of_range():
+    n = 1 << 21
+    e = graphgen.er(n, 1 << 24, 66)
+    e[12345] = (n + 5, 3)
+    with cc.Context() as c:
+        L = torch.empty(n, dtype=torch.int32, device="cuda")
+        c.solve_async(to_dev(e), n, L, flags=cc.F_ZROOT)
+        assert c.sync() == cc.CC_ERANGE
+
+
+def test_compress_never_trusts_a_stale_root():
+    """Regression: a compress thread once stopped at a vertex whose entry it read as
+    a root from a copy cached on another XCD while the vertex was still a root,
+    although the hook had linked it. Repeated step-wise solves of a skewed graph
+    (hook, host check of P, compress) must all give the oracle's labels."""
+    n = 1 << 22
+    e = graphgen.rmat(22, (1 << 24) + 777, 62, permute=False)
+    want = oracle.cc_labels(n, e)
+    ed = to_dev(e)
+    with cc.Context() as c:
+        P = torch.empty(n, dtype=torch.int32, device="cuda")
+        for rep in range(24):
+            fl = 0 if rep % 2 == 0 else cc.F_ZROOT | cc.F_NO_TILE
+            c.init(n, P)
+            if fl:
+                c.zroot(ed, n)
+                c.push(ed, n, P)
+            c.hook(ed, n, P, flags=fl)
+            torch.cuda.synchronize()
+            _ = P.cpu()                      # the host read between the kernels, as before
+            c.compress(n, P, flags=fl)
+            if fl:
+                c.canon(n, P)
+            assert c.sync() == cc.CC_OK
+            assert_same_labels(to_host_u32(P), want, f"rep {rep} flags {fl}")
