@@ -5,8 +5,10 @@ A step is one pass of the whole single-graph path over the workload, with the
 edge list already resident in HBM: init, zero root (sampled), Initial Push,
 hook, compress and the zero-component relabelling (flags CC_F_ZROOT), i.e.
 cc_init / cc_zroot / cc_push / cc_hook / cc_compress / cc_canon enqueued on one
-stream. The hook kernel is bracketed by its own HIP events on that stream
-inside the timed region (the roofline figure).
+stream. The hook step (one cc_hook call: on the zero-root path a short direct
+hook over 1/64 of the entries, two partition passes and the tiled hook kernel)
+is bracketed by its own HIP events on that stream inside the timed region; the
+roofline figure is its algorithmic bytes (8 per entry) over that duration.
 
 Prints one JSON line. Default workload: R-MAT scale 26, edgefactor 16, permuted
 IDs, plus 1 % isolated vertices and 10,000 paths of 2..64 vertices.
@@ -25,6 +27,39 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 PEAK_HBM_GBS = 8000.0
+
+# HBM bytes per launch of the cc_hook step, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, WRITE_SIZE) of this script with --steps 1 --warmup 0 --calibrate,
+# each counter scaled by what it reads for a 4 GiB device copy. Keyed by
+# (workload, variant); valid only for the kernel sources they were taken on.
+TRAFFIC = {
+    ("rmat26", "zroot"): {"bytes": 64191536646,
+                          "src_sha256": "41bdb7b975f6f6d2c914008d7ca99ec66c43823271a913dd4099f3c8e2794520"},
+}
+
+HOOK_KERNELS = {
+    "zroot": "cc_hook step: k_hook<ZR> on 1/64 of the entries, k_t1_part, k_t1_tsum, k_t1_scan, "
+             "k_t1_bases, k_t2_bounds, k_t2_part, k_t3_hook",
+    "plain": "cc_hook step: k_hook<plain>",
+}
+
+
+def kernel_sources_sha256():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(HERE, "paper_2507_03695_amd", "csrc", "*"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, variant):
+    t = TRAFFIC.get((workload, variant))
+    if t is None or t["src_sha256"] != kernel_sources_sha256():
+        return None
+    return t["bytes"]
 
 
 def log(msg):
@@ -52,15 +87,15 @@ def cpu_baseline(edges, n, target_s=15.0):
     import oracle
     m = len(edges)
     k = min(m, 1 << 22)
-    t0 = time.perf_counter()
-    oracle.cc_labels(n, edges[:k])
-    t1 = time.perf_counter() - t0
-    k2 = int(min(m, max(k, k * target_s / max(t1, 1e-3))))
-    if k2 > k:
+    while True:
         t0 = time.perf_counter()
-        oracle.cc_labels(n, edges[:k2])
+        oracle.cc_labels(n, edges[:k])
         t1 = time.perf_counter() - t0
-        k = k2
+        if t1 >= 0.6 * target_s or k == m:
+            break
+        # the time per entry grows with the prefix (the touched part of the
+        # parent array outgrows the caches), so grow the sample in steps
+        k = int(min(m, k * min(4.0, max(1.5, target_s / max(t1, 1e-3)))))
     return {"value": round(k / t1 / 1e9, 6), "unit": "GTEPS", "cores": 1, "kind": "oracle",
             "sample": f"first {k} of {m} entries with all {n} vertices; union-find + min-ID pass, "
                       f"{t1:.2f} s on one host thread"}
@@ -208,6 +243,8 @@ def main():
     ap.add_argument("--variant", default="zroot", choices=["zroot", "plain"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batch and serve lines")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="also run a plain 4 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -225,6 +262,16 @@ def main():
     log(f"workload {cfg['workload']}: n={n} m={m} generated in {time.time() - t0:.1f} s")
     ed = torch.from_numpy(edges.view(np.int32)).cuda()
     torch.cuda.synchronize()
+
+    if args.calibrate:
+        # a plain copy of known size: 4 GiB read + 4 GiB written, for scaling the
+        # FETCH_SIZE / WRITE_SIZE counters of the profiled kernels
+        src = torch.ones(1 << 30, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
 
     flags = cc.F_ZROOT if args.variant == "zroot" else 0
     ms, hook_ms, L = bench_single(cc, torch, ed, n, m, args.steps, args.warmup, flags)
@@ -253,9 +300,11 @@ def main():
         "data": "synthetic",
         "config": dict(cfg, variant=args.variant, parallelism="single_gpu"),
         "hbm_roofline_frac_whole_path": round(alg_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
-        "roofline": {"bound": "hbm", "kernel": "k_hook", "achieved": round(hook_gbs, 1),
+        "roofline": {"bound": "hbm", "achieved": round(hook_gbs, 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(hook_gbs / PEAK_HBM_GBS, 4), "traffic": None,
+                     "frac": round(hook_gbs / PEAK_HBM_GBS, 4),
+                     "traffic": measured_traffic(args.workload, args.variant),
+                     "kernel": HOOK_KERNELS[args.variant],
                      "algorithmic_bytes_per_launch": 8 * m, "avg_launch_ms": round(hook_ms, 4)},
         other: {"ms_per_step": round(ms_o, 4), "hook_ms": round(hook_o, 4),
                 "GTEPS": round(m / (ms_o * 1e-3) / 1e9, 3)},
