@@ -62,7 +62,7 @@ int slot_create(Slot* s, int device, uint32_t samples) {
     e = hipHostMalloc(&s->host_status, sizeof(uint32_t), hipHostMallocDefault);
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        hipFree(base);
+        (void)hipFree(base);
         s->st = nullptr;
         return fail(CC_ENOMEM, "pinned host status allocation failed");
     }
@@ -98,6 +98,7 @@ int slot_sync(Slot* s, hipStream_t stream) {
     CCM_HIP(hipGetLastError());
     CCM_HIP(hipStreamSynchronize(stream));
     const uint32_t w = __atomic_load_n(s->host_status, __ATOMIC_ACQUIRE);
+    if (w & kStatusInternal) return fail(CC_EDEVICE, "internal scratch bound exceeded");
     if (w & kStatusRange) return fail(CC_ERANGE, "an endpoint is >= n");
     return CC_OK;
 }

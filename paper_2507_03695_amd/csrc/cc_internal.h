@@ -26,6 +26,7 @@ struct DevState {
 static_assert(sizeof(DevState) == 64, "DevState is one 64-byte block");
 
 constexpr uint32_t kStatusRange = 1u;
+constexpr uint32_t kStatusInternal = 2u;   // a scratch bound check failed (a bug)
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 
 // One graph of a batched launch: where its entries and labels live.

@@ -18,7 +18,6 @@
 namespace ccm {
 
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kBlock = 256;
 
@@ -32,24 +31,14 @@ __device__ __forceinline__ bool key_less(uint32_t a, uint32_t b, uint32_t z) {
 
 // ---- init --------------------------------------------------------------------
 // P_v = v (Algorithm 1 / 3 initialisation; with R the stored values stay vertex
-// IDs and only the order changes). 16-byte stores when P is 16-byte aligned.
+// IDs and only the order changes). Like every store to P, a device-coherent one
+// (see find_root); lanes write consecutive words, so each wave writes whole lines.
 __global__ __launch_bounds__(kBlock) void k_init(uint32_t* __restrict__ P, uint64_t n,
-                                                 DevState* st, int vec) {
+                                                 DevState* st) {
     const uint64_t tid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     if (tid == 0) st_agent(&st->minz, kEmpty);
-    if (vec) {
-        const uint64_t n4 = n >> 2;
-        u32x4* P4 = reinterpret_cast<u32x4*>(P);
-        for (uint64_t i = tid; i < n4; i += stride) {
-            uint32_t b = (uint32_t)(i << 2);
-            u32x4 val = {b, b + 1, b + 2, b + 3};
-            __builtin_nontemporal_store(val, P4 + i);
-        }
-        for (uint64_t v = (n4 << 2) + tid; v < n; v += stride) P[v] = (uint32_t)v;
-    } else {
-        for (uint64_t v = tid; v < n; v += stride) P[v] = (uint32_t)v;
-    }
+    for (uint64_t v = tid; v < n; v += stride) st_agent(&P[v], (uint32_t)v);
 }
 
 // ---- zero root: sampled endpoint counts in an open-addressing table ----------
@@ -183,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_push(const uint32_t* __restrict__ ed
         if (u == z) x = v;
         else if (v == z) x = u;
         if (x != kEmpty) {
-            P[x] = z;
+            st_agent(&P[x], z);
             atomicOr(&zbits[x >> 5], 1u << (x & 31));
         }
     }
@@ -203,16 +192,23 @@ __global__ __launch_bounds__(kBlock) void k_zbits_clear(uint32_t* zbits, uint64_
 
 // Root of x, given px = a value read from P[x]. SPLIT = 1: path splitting (each
 // visited vertex takes its grandparent); SPLIT = 0: plain walk.
+// The splitting writes are device-coherent stores: a plain store leaves the line
+// in the writing XCD's L2, and such a copy has been observed to outlive later
+// kernels' writes from other XCDs (a reader on that XCD then sees the old
+// parent). Each one is issued after the next step's load, so that its latency
+// overlaps the walk instead of adding to it.
 template <int SPLIT>
 __device__ __forceinline__ uint32_t find_root(uint32_t* P, uint32_t x, uint32_t px) {
-    while (px != x) {
-        const uint32_t gp = P[px];
-        if (gp == px) return px;
-        if (SPLIT) P[x] = gp;
+    if (px == x) return x;
+    uint32_t gp = P[px];
+    while (gp != px) {
+        const uint32_t ggp = P[gp];
+        if (SPLIT) st_agent(&P[x], gp);
         x = px;
         px = gp;
+        gp = ggp;
     }
-    return x;
+    return px;
 }
 
 // Algorithm 1 / 3 hooking of one entry whose endpoints u, v have parents pu, pv.
@@ -351,7 +347,7 @@ __global__ __launch_bounds__(kBlock) void k_compress(uint32_t* P, uint64_t n, De
                 if (q == r) break;
                 r = q;
             }
-            if (r != p) P[v] = r;
+            if (r != p) st_agent(&P[v], r);
         }
         if (ZR && r == z && (uint32_t)v < local_min) local_min = (uint32_t)v;
     }
@@ -367,7 +363,7 @@ __global__ __launch_bounds__(kBlock) void k_canon(uint32_t* L, uint64_t n, const
     if (mz == z || mz == kEmpty) return;
     for (uint64_t v = (uint64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
          v += (uint64_t)gridDim.x * kBlock) {
-        if (ld_agent(&L[v]) == z) L[v] = mz;
+        if (ld_agent(&L[v]) == z) st_agent(&L[v], mz);
     }
 }
 
@@ -400,8 +396,7 @@ constexpr uint32_t kGridCap = 256 * 32;
 int run_init(Slot* s, uint64_t n, uint32_t* P, hipStream_t stream) {
     s->cur_n = n;
     s->zr_ready = false;
-    int vec = ((uintptr_t)P & 15) == 0;
-    k_init<<<grid_for(n, kBlock * 4, kGridCap), kBlock, 0, stream>>>(P, n, s->st, vec);
+    k_init<<<grid_for(n, kBlock * 4, kGridCap), kBlock, 0, stream>>>(P, n, s->st);
     CCM_HIP(hipGetLastError());
     return CC_OK;
 }

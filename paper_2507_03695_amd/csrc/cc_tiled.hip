@@ -16,15 +16,16 @@
 //  4. k_t2_part   — every kC2-entry piece of an a-bucket is gathered from its
 //                   segments, sorted in LDS by the slice of the second
 //                   endpoint (b) and written contiguously, with its b-runs.
-//  5. k_t3_hook   — one workgroup per (a, b): both slices' bitmap words in
-//                   LDS; entries with both bits set are dropped there; the
-//                   rest take the ordinary path on the global parent array,
-//                   and new zero-tree members are recorded in the global
-//                   bitmap and in the LDS copies.
+//  5. k_t3_filter — one workgroup per (a, b): both slices' bitmap words in
+//                   LDS; entries with both endpoints marked are dropped there,
+//                   the rest are appended to a survivor list, and an entry
+//                   with one marked endpoint marks the other (LDS and global).
+//  6. k_t4_hook   — the ordinary hook over the survivor list.
 //
 // The regrouping only reorders entries (and drops self-loops, which are
-// no-ops); hooking is order-independent (Sec. II), so the labels are those of
-// the plain pass. Entries whose endpoints are out of range are dropped with
+// no-ops); hooking is order-independent (Sec. II), and dropped entries join
+// vertices the kept ones connect anyway, so the labels are those of the plain
+// pass. Entries whose endpoints are out of range are dropped with
 // the status bit set, as in the plain hook.
 #include <algorithm>
 
@@ -48,15 +49,19 @@ __device__ __forceinline__ bool t_key_less(uint32_t a, uint32_t b, uint32_t z) {
     return (a == z) | ((b != z) & (a < b));
 }
 
+// Root of x with path splitting; device-coherent splitting stores, each issued
+// after the next step's load (as in the plain hook).
 __device__ __forceinline__ uint32_t t_find(uint32_t* P, uint32_t x, uint32_t px) {
-    while (px != x) {
-        const uint32_t gp = P[px];
-        if (gp == px) return px;
-        P[x] = gp;
+    if (px == x) return x;
+    uint32_t gp = P[px];
+    while (gp != px) {
+        const uint32_t ggp = P[gp];
+        st_agent(&P[x], gp);
         x = px;
         px = gp;
+        gp = ggp;
     }
-    return x;
+    return px;
 }
 
 __device__ __forceinline__ uint32_t t_link(uint32_t* P, uint32_t u, uint32_t pu, uint32_t v,
@@ -362,45 +367,24 @@ __global__ __launch_bounds__(kPartBlock) void k_t2_part(const u32x2* __restrict_
     for (int d = threadIdx.x; d <= R; d += kPartBlock) run2T[(uint64_t)d * nch2 + g] = (uint16_t)start[d];
 }
 
-// ---- 5. the hook over bucket (a, b) with both slices' bitmap words in LDS --------------
+// ---- 5. the filter over bucket (a, b) with both slices' bitmap words in LDS ---------------
+//
+// While this kernel runs, a set bit means "connected to the zero root through
+// the entries hooked by the end of the step" (the warm-up's bits are stronger:
+// in z's tree already). An entry with both endpoints marked is dropped: it joins
+// two vertices that the kept entries connect anyway. Every other entry is kept
+// for the survivor hook, and when exactly one endpoint is marked the other is
+// marked at once (in LDS and in the global bitmap): once that kept entry is
+// hooked it is connected to z as well. Such an entry is kept as (x, z), x the
+// newly marked endpoint, which has the same effect on the components and
+// spares the hook the walk up the marked endpoint's path. Each mark thus rests on a kept entry and
+// an earlier mark, so no dropped entry is ever needed. Because marks are claims
+// about the end of the step, the survivor hook does not consult them.
 constexpr int kHook3Block = 1024;
 constexpr int kWaves3 = kHook3Block / 64;
 constexpr int kWin3 = 2048;      // level-2 chunks per window
-constexpr int kRunsInFlight = 8; // runs a wave reads at once (one entry per lane each)
-constexpr int kWaveQueue = 128;  // per-wave LDS queue of entries that need the parent array
-
-// The ordinary path for one entry whose endpoints were not both known to be in
-// the zero root's tree. u lies in the resident first-endpoint slice (sa); v may
-// come from an earlier second-endpoint slice (entries carried over in a wave's
-// queue), so its LDS bit is used only when v lies in the resident slice lb.
-__device__ __forceinline__ void t3_slow(uint32_t* P, uint32_t* zbits, uint32_t* sa, uint32_t* lb,
-                                        uint32_t abase, uint32_t bbase, uint32_t z, u32x2 uv) {
-    const uint32_t u = uv.x, v = uv.y;
-    const uint32_t ou = u - abase, ov = v - bbase;
-    const bool vloc = ov < (1u << kSliceBits);
-    // bits may have been set since the entry was queued
-    const bool inu = (sa[ou >> 5] >> (ou & 31)) & 1u;
-    const bool inv = vloc ? ((lb[ov >> 5] >> (ov & 31)) & 1u) : ((zbits[v >> 5] >> (v & 31)) & 1u);
-    if (inu && inv) return;
-    const uint32_t wu = inu ? z : u, wv = inv ? z : v;
-    const uint32_t pu = inu ? z : P[u];
-    const uint32_t pv = inv ? z : P[v];
-    uint32_t r;
-    if (pu == pv) r = pu;
-    else if (pu == wv) r = wv;
-    else if (pv == wu) r = wu;
-    else r = t_link(P, wu, pu, wv, pv, z);
-    if (r == z) {
-        if (!inu) {
-            atomicOr(&zbits[u >> 5], 1u << (u & 31));
-            atomicOr(&sa[ou >> 5], 1u << (ou & 31));
-        }
-        if (!inv) {
-            atomicOr(&zbits[v >> 5], 1u << (v & 31));
-            if (vloc) atomicOr(&lb[ov >> 5], 1u << (ov & 31));
-        }
-    }
-}
+constexpr int kRunsInFlight = 16; // entries a lane loads at once (a wave: 16 x 64 consecutive)
+constexpr int kWaveQueue = 128;  // per-wave LDS staging of kept entries
 
 // Exclusive scan in place of n <= 2 * kHook3Block values (x[n] receives the
 // total); every thread of the workgroup calls it.
@@ -430,20 +414,58 @@ __device__ __forceinline__ void block_scan_2048(uint32_t* x, uint32_t n, uint32_
     __syncthreads();
 }
 
-// Walk the first `qn` queued entries of this wave (one per lane, two rounds).
-__device__ __forceinline__ void t3_drain(u32x2* wq, uint32_t qn, int lane, uint32_t* P,
-                                         uint32_t* zbits, uint32_t* sa, uint32_t* lb,
-                                         uint32_t abase, uint32_t bbase, uint32_t z) {
+// Append the first `qn` staged entries of this wave (qn < 128) to the
+// workgroup's survivor region: the place comes from an LDS counter, so no
+// global atomic is involved; one entry per lane per round.
+__device__ __forceinline__ void t3_flush(const u32x2* wq, uint32_t qn, int lane, u32x2* out,
+                                         uint32_t cap, uint32_t* s_used, DevState* st) {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    u32x2 x0 = {0u, 0u}, x1 = {0u, 0u};
-    const bool h0 = (uint32_t)lane < qn, h1 = (uint32_t)lane + 64 < qn;
-    if (h0) x0 = wq[lane];
-    if (h1) x1 = wq[lane + 64];
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(s_used, qn);
+    base = __shfl(base, 0, 64);
+    if (base + qn > cap) {
+        // cannot happen (the region holds all of the workgroup's entries); never
+        // write past it
+        if (lane == 0) atomicOr(&st->status, kStatusInternal);
+        qn = 0;
+    }
+    if ((uint32_t)lane < qn) out[base + lane] = wq[lane];
+    if ((uint32_t)lane + 64 < qn) out[base + lane + 64] = wq[lane + 64];
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    if (h0) t3_slow(P, zbits, sa, lb, abase, bbase, z, x0);
-    if (h1) t3_slow(P, zbits, sa, lb, abase, bbase, z, x1);
+}
+
+constexpr int kBPerBlock = 4;    // second-endpoint slices handled by one workgroup
+
+// Survivor regions: workgroup (a, bg) of the filter reads exactly the entries of
+// tiles (a, b), b in [4 bg, 4 bg + 4); its kept entries go to a region of that
+// size inside [base2[a], base2[a+1]) of the survivor buffer; regions are
+// consecutive, so wgoff[w + 1] ends region w (wgoff has R * nbg + 1 entries).
+// One block per a.
+__global__ __launch_bounds__(256) void k_t3_regions(const uint16_t* __restrict__ run2T,
+                                                    uint64_t nch2, int R,
+                                                    const uint64_t* __restrict__ base2,
+                                                    const uint32_t* __restrict__ cbase,
+                                                    uint64_t* __restrict__ wgoff) {
+    __shared__ uint32_t ws[4];
+    const int a = blockIdx.x;
+    const int nbg = (R + kBPerBlock - 1) / kBPerBlock;
+    const uint32_t g0 = cbase[a], g1 = cbase[a + 1];
+    uint64_t run = base2[a];
+    for (int bg = 0; bg < nbg; ++bg) {
+        const int blo = bg * kBPerBlock, bhi = min(R, blo + kBPerBlock);
+        uint32_t t = 0;
+        for (uint32_t g = g0 + threadIdx.x; g < g1; g += 256)
+            t += (uint32_t)run2T[(uint64_t)bhi * nch2 + g] - (uint32_t)run2T[(uint64_t)blo * nch2 + g];
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+        __syncthreads();                       // ws of the previous group consumed
+        if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = t;
+        __syncthreads();
+        if (threadIdx.x == 0) wgoff[(uint64_t)a * nbg + bg] = run;
+        run += (uint64_t)ws[0] + ws[1] + ws[2] + ws[3];
+    }
+    if (a == R - 1 && threadIdx.x == 0) wgoff[(uint64_t)R * nbg] = run;   // end of the last region
 }
 
 // Run holding index j0 of the window (last t < nw with s_pre[t] <= j0), found
@@ -461,26 +483,34 @@ __device__ __forceinline__ uint32_t t3_find_run(const uint32_t* s_pre, uint32_t 
     return base + (63u - (uint32_t)__clzll((long long)b2));
 }
 
-constexpr int kBPerBlock = 4;    // second-endpoint slices handled by one workgroup
-
-__global__ __launch_bounds__(kHook3Block) void k_t3_hook(const u32x2* __restrict__ tmp2,
-                                                         const uint16_t* __restrict__ run2T,
-                                                         uint64_t nch2, int R,
-                                                         const uint64_t* __restrict__ base2,
-                                                         const uint32_t* __restrict__ cbase,
-                                                         uint32_t* P, uint32_t* zbits,
-                                                         uint64_t words, DevState* st) {
+__global__ __launch_bounds__(kHook3Block) void k_t3_filter(const u32x2* __restrict__ tmp2,
+                                                           const uint16_t* __restrict__ run2T,
+                                                           uint64_t nch2, int R,
+                                                           const uint64_t* __restrict__ base2,
+                                                           const uint32_t* __restrict__ cbase,
+                                                           uint32_t* zbits, uint64_t words,
+                                                           u32x2* __restrict__ surv,
+                                                           const uint64_t* __restrict__ wgoff,
+                                                           uint32_t* __restrict__ wgcnt,
+                                                           DevState* st) {
     __shared__ uint32_t sa[kSliceWords];
     __shared__ uint32_t sb[kSliceWords];
     __shared__ uint16_t s_r0[kWin3];
     __shared__ uint32_t s_pre[kWin3 + 1];
     __shared__ u32x2 queue[kWaves3 * kWaveQueue];
     __shared__ uint32_t wsum[kWaves3 + 1];
+    __shared__ uint32_t s_used;
     const int nbg = (R + kBPerBlock - 1) / kBPerBlock;
     const int a = blockIdx.x / nbg, bg = blockIdx.x % nbg;
     const uint32_t cb = cbase[a];
     const uint32_t nch = cbase[a + 1] - cb;
-    if (nch == 0) return;
+    if (nch == 0) {
+        if (threadIdx.x == 0) wgcnt[blockIdx.x] = 0;
+        return;
+    }
+    if (threadIdx.x == 0) s_used = 0;
+    u32x2* out = surv + wgoff[blockIdx.x];
+    const uint32_t cap = (uint32_t)(wgoff[blockIdx.x + 1] - wgoff[blockIdx.x]);
     const uint32_t z = ld_agent(&st->zroot);
     constexpr int PER = kSliceWords / kHook3Block;       // 16 words per thread per slice
     {
@@ -499,14 +529,10 @@ __global__ __launch_bounds__(kHook3Block) void k_t3_hook(const u32x2* __restrict
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     u32x2* wq = queue + wave * kWaveQueue;
     constexpr uint32_t kRange = 64 * kRunsInFlight;      // entries per wave per range
-    uint32_t qn = 0;             // wave-uniform queue length, carried across slices b
-    uint32_t* lb = sa;
-    uint32_t bbase = 0;
+    uint32_t qn = 0;             // wave-uniform staging length, carried across slices b
     for (int bi = 0; bi < kBPerBlock; ++bi) {
         const int b = bg * kBPerBlock + bi;
         if (b >= R) break;
-        // the wave queue may still hold entries of earlier slices b; their walks
-        // use the global bitmap for v (t3_slow checks the slice)
         __syncthreads();                                  // previous slice b fully used
         if (b != a) {
             const uint64_t wb = (uint64_t)b * kSliceWords;
@@ -519,8 +545,8 @@ __global__ __launch_bounds__(kHook3Block) void k_t3_hook(const u32x2* __restrict
 #pragma unroll
             for (int k = 0; k < PER; ++k) sb[(uint32_t)k * kHook3Block + threadIdx.x] = xb[k];
         }
-        lb = (a == b) ? sa : sb;
-        bbase = (uint32_t)b << kSliceBits;
+        uint32_t* lb = (a == b) ? sa : sb;
+        const uint32_t bbase = (uint32_t)b << kSliceBits;
         for (uint32_t w0 = 0; w0 < nch; w0 += kWin3) {
             const uint32_t nw = min((uint32_t)kWin3, nch - w0);
             __syncthreads();
@@ -536,56 +562,176 @@ __global__ __launch_bounds__(kHook3Block) void k_t3_hook(const u32x2* __restrict
             const uint32_t total = s_pre[nw];
             // The window's entries form one index space [0, total); each wave
             // takes ranges of kRange consecutive indices (lanes step through the
-            // runs). The loads of the next range are issued before the current
-            // range is tested, so memory latency overlaps the tests and walks.
+            // runs).
             uint32_t j0 = (uint32_t)wave * kRange;
-            u32x2 e[kRunsInFlight];
-            bool has[kRunsInFlight];
+            // Addresses first (LDS only), then the loads back to back: no loop
+            // sits between loads, so none forces an early wait on the loads in
+            // flight.
             auto issue = [&](uint32_t jb, u32x2* ev, bool* hv) {
                 uint32_t t = t3_find_run(s_pre, nw, jb, lane);
+                uint64_t at[kRunsInFlight];
 #pragma unroll
                 for (int k = 0; k < kRunsInFlight; ++k) {
                     const uint32_t j = jb + (uint32_t)k * 64 + lane;
                     hv[k] = j < total;
                     while (t + 1 < nw && s_pre[t + 1] <= j) ++t;
-                    const uint64_t at = hv[k] ? (uint64_t)(w0 + t) * kC2 + s_r0[t] + (j - s_pre[t]) : 0ull;
-                    ev[k] = __builtin_nontemporal_load(src + at);
+                    at[k] = hv[k] ? (uint64_t)(w0 + t) * kC2 + s_r0[t] + (j - s_pre[t]) : 0ull;
                 }
+#pragma unroll
+                for (int k = 0; k < kRunsInFlight; ++k) ev[k] = __builtin_nontemporal_load(src + at[k]);
             };
-            if (j0 < total) issue(j0, e, has);
-            while (j0 < total) {
-                const uint32_t jn = j0 + kWaves3 * kRange;
-                u32x2 en[kRunsInFlight];
-                bool hn[kRunsInFlight];
-                if (jn < total) issue(jn, en, hn);
-                // membership tests of the current range (LDS reads overlap)
-                bool sv[kRunsInFlight];
+            // Membership tests of one range; kept entries are staged in the
+            // wave's queue (marks as described above).
+            auto test = [&](u32x2* ev, const bool* hv) {
+                bool keep[kRunsInFlight];
 #pragma unroll
                 for (int k = 0; k < kRunsInFlight; ++k) {
-                    const uint32_t ou = e[k].x - abase, ov = e[k].y - bbase;
-                    const uint32_t wu = sa[has[k] ? (ou >> 5) : 0u];
-                    const uint32_t wv = lb[has[k] ? (ov >> 5) : 0u];
-                    sv[k] = has[k] && !(((wu >> (ou & 31)) & (wv >> (ov & 31))) & 1u);
+                    const uint32_t ou = ev[k].x - abase, ov = ev[k].y - bbase;
+                    const uint32_t iu = hv[k] ? (ou >> 5) : 0u, iv = hv[k] ? (ov >> 5) : 0u;
+                    const uint32_t bu = 1u << (ou & 31), bv = 1u << (ov & 31);
+                    const bool mu = (sa[iu] & bu) != 0u, mv = (lb[iv] & bv) != 0u;
+                    keep[k] = hv[k] && !(mu && mv);
+                    if (hv[k] && mu != mv) {
+                        // mark the unmarked endpoint; the global word only once per workgroup
+                        uint32_t* w = mu ? &lb[iv] : &sa[iu];
+                        const uint32_t bit = mu ? bv : bu;
+                        const uint32_t x = mu ? ev[k].y : ev[k].x;
+                        if (!(atomicOr(w, bit) & bit)) atomicOr(&zbits[x >> 5], 1u << (x & 31));
+                        // the marked endpoint ends up connected to z: keep (x, z),
+                        // whose hook walks only x's path
+                        ev[k].x = x;
+                        ev[k].y = z;
+                    }
                 }
 #pragma unroll
                 for (int k = 0; k < kRunsInFlight; ++k) {
-                    const uint64_t ball = __ballot(sv[k]);
-                    if (sv[k]) wq[qn + (uint32_t)__popcll(ball & ((1ull << lane) - 1ull))] = e[k];
+                    const uint64_t ball = __ballot(keep[k]);
+                    if (keep[k]) wq[qn + (uint32_t)__popcll(ball & ((1ull << lane) - 1ull))] = ev[k];
                     qn += (uint32_t)__popcll(ball);
                     if (qn >= 64) {
-                        t3_drain(wq, qn, lane, P, zbits, sa, lb, abase, bbase, z);
+                        t3_flush(wq, qn, lane, out, cap, &s_used, st);
                         qn = 0;
                     }
                 }
-                j0 = jn;
-                if (j0 < total) {
-#pragma unroll
-                    for (int k = 0; k < kRunsInFlight; ++k) { e[k] = en[k]; has[k] = hn[k]; }
-                }
+            };
+            // Each wave loads a whole range (kRunsInFlight entries per lane, all
+            // in flight at once) and then tests it; the other waves of the
+            // workgroup keep the memory system busy meanwhile.
+            constexpr uint32_t kStep = kWaves3 * kRange;
+            u32x2 e[kRunsInFlight];
+            bool h[kRunsInFlight];
+            for (; j0 < total; j0 += kStep) {
+                issue(j0, e, h);
+                test(e, h);
             }
         }
     }
-    if (qn) t3_drain(wq, qn, lane, P, zbits, sa, lb, abase, bbase, z);
+    if (qn) t3_flush(wq, qn, lane, out, cap, &s_used, st);
+    __syncthreads();
+    if (threadIdx.x == 0) wgcnt[blockIdx.x] = min(s_used, cap);
+}
+
+// ---- 6. the survivor hook -------------------------------------------------------------------
+// The regions are first packed into one dense list (exclusive prefix of the
+// region counts, then one block per region copies its entries), so that the
+// hook can spread the list evenly over the whole chip.
+constexpr int kPackBlock = 1024;
+
+// Exclusive prefix of cnt[0..nw) into pref[0..nw], pref[nw] = total; one block.
+__global__ __launch_bounds__(kPackBlock) void k_t4_scan(const uint32_t* __restrict__ cnt,
+                                                        uint32_t nw, uint32_t* __restrict__ pref) {
+    __shared__ uint32_t ws[kPackBlock / 64 + 1];
+    __shared__ uint32_t s_carry;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) s_carry = 0;
+    for (uint32_t base = 0; base < nw; base += kPackBlock) {
+        const uint32_t i = base + threadIdx.x;
+        const uint32_t x = i < nw ? cnt[i] : 0u;
+        uint32_t incl = x;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) ws[wave] = incl;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t run = s_carry;
+            for (int w = 0; w < kPackBlock / 64; ++w) { const uint32_t t = ws[w]; ws[w] = run; run += t; }
+            ws[kPackBlock / 64] = run;
+        }
+        __syncthreads();
+        if (i < nw) pref[i] = ws[wave] + incl - x;
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry = ws[kPackBlock / 64];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) pref[nw] = s_carry;
+}
+
+// Region w's entries to dense[pref[w] ..); one block per region, eight loads
+// per thread in flight.
+constexpr int kPackEPT = 8;
+
+__global__ __launch_bounds__(256) void k_t4_pack(const u32x2* __restrict__ surv,
+                                                 const uint64_t* __restrict__ wgoff,
+                                                 const uint32_t* __restrict__ cnt,
+                                                 const uint32_t* __restrict__ pref,
+                                                 u32x2* __restrict__ dense) {
+    const uint32_t w = blockIdx.x;
+    const uint32_t c = cnt[w];
+    const u32x2* src = surv + wgoff[w];
+    u32x2* dst = dense + pref[w];
+    for (uint32_t i0 = 0; i0 < c; i0 += 256 * kPackEPT) {
+        u32x2 x[kPackEPT];
+#pragma unroll
+        for (int k = 0; k < kPackEPT; ++k) {
+            const uint32_t i = i0 + (uint32_t)k * 256 + threadIdx.x;
+            x[k] = src[i < c ? i : 0u];
+        }
+#pragma unroll
+        for (int k = 0; k < kPackEPT; ++k) {
+            const uint32_t i = i0 + (uint32_t)k * 256 + threadIdx.x;
+            if (i < c) dst[i] = x[k];
+        }
+    }
+}
+
+// Algorithm 3's hooking loop (keys of Formula 1 as an order, path splitting)
+// over the kept entries, with no bitmap: the marks may describe links that
+// this kernel has not made yet. Grid-stride over the dense list.
+constexpr int kHook4Block = 256;
+constexpr int kHook4EPT = 4;
+constexpr int kHook4Grid = 2048;     // 8 workgroups per CU
+
+__global__ __launch_bounds__(kHook4Block) void k_t4_hook(const u32x2* __restrict__ list,
+                                                         const uint32_t* __restrict__ count,
+                                                         uint32_t* P, DevState* st) {
+    const uint32_t z = ld_agent(&st->zroot);
+    const uint64_t S = ld_agent(count);
+    constexpr uint64_t per = (uint64_t)kHook4Block * kHook4EPT;
+    for (uint64_t t0 = (uint64_t)blockIdx.x * per; t0 < S; t0 += (uint64_t)gridDim.x * per) {
+        u32x2 e[kHook4EPT];
+        bool h[kHook4EPT];
+#pragma unroll
+        for (int k = 0; k < kHook4EPT; ++k) {
+            const uint64_t i = t0 + (uint64_t)k * kHook4Block + threadIdx.x;
+            h[k] = i < S;
+            e[k] = list[h[k] ? i : 0];
+        }
+        uint32_t pu[kHook4EPT], pv[kHook4EPT];
+#pragma unroll
+        for (int k = 0; k < kHook4EPT; ++k) {
+            pu[k] = P[e[k].x];
+            pv[k] = P[e[k].y];
+        }
+#pragma unroll
+        for (int k = 0; k < kHook4EPT; ++k) {
+            if (!h[k]) continue;
+            if (pu[k] == pv[k] || pu[k] == e[k].y || pv[k] == e[k].x) continue;
+            (void)t_link(P, e[k].x, pu[k], e[k].y, pv[k], z);
+        }
+    }
 }
 
 // ---- host side --------------------------------------------------------------------
@@ -653,8 +799,12 @@ int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint3
     const uint64_t b_cbase = al(4 * (R + 1));
     const uint64_t b_run2 = al(2 * pl.nch2_max * (R + 1));
     const uint64_t b_ctab = al(4 * pl.nch2_max);
+    const uint32_t nbg = (uint32_t)((R + kBPerBlock - 1) / kBPerBlock);
+    const uint32_t nwg = (uint32_t)R * nbg;
+    const uint64_t b_wgoff = al(8 * ((uint64_t)nwg + 1)), b_wgcnt = al(4 * (uint64_t)nwg);
+    const uint64_t b_spref = al(4 * ((uint64_t)nwg + 1));
     const uint64_t total = 2 * b_tmp + b_seg1 + b_cnt1 + b_pre1 + b_base2 + b_cbase + b_run2 +
-                           2 * b_ctab + b_tsum;
+                           2 * b_ctab + b_tsum + b_wgoff + b_wgcnt + b_spref;
     int rc = grow(reinterpret_cast<void**>(&s->tiled.buf), &s->tiled.cap, total, stream);
     if (rc) return rc;
     char* q = s->tiled.buf;
@@ -668,7 +818,12 @@ int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint3
     uint16_t* run2 = reinterpret_cast<uint16_t*>(q); q += b_run2;
     uint32_t* c0tab = reinterpret_cast<uint32_t*>(q); q += b_ctab;
     uint32_t* c1tab = reinterpret_cast<uint32_t*>(q); q += b_ctab;
-    uint32_t* tsum = reinterpret_cast<uint32_t*>(q);
+    uint32_t* tsum = reinterpret_cast<uint32_t*>(q); q += b_tsum;
+    uint64_t* wgoff = reinterpret_cast<uint64_t*>(q); q += b_wgoff;
+    uint32_t* wgcnt = reinterpret_cast<uint32_t*>(q); q += b_wgcnt;
+    uint32_t* spref = reinterpret_cast<uint32_t*>(q);
+    u32x2* surv = tmp1;      // free once the level-2 partition has read it
+    u32x2* dense = tmp2;     // free once the filter has read it
     // every kernel below reads tables the previous one wrote: coherence points between
     int rc1;
     if ((rc1 = cohere(stream))) return rc1;
@@ -689,9 +844,16 @@ int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint3
                                                                cbase, c0tab, c1tab, tmp2, run2,
                                                                pl.nch2_max);
     if ((rc1 = cohere(stream))) return rc1;
-    const uint32_t nbg = (uint32_t)((R + kBPerBlock - 1) / kBPerBlock);
-    k_t3_hook<<<(uint32_t)R * nbg, kHook3Block, 0, stream>>>(tmp2, run2, pl.nch2_max, R, base2, cbase,
-                                                            P, s->zbits, (n + 31) / 32, s->st);
+    k_t3_regions<<<(uint32_t)R, 256, 0, stream>>>(run2, pl.nch2_max, R, base2, cbase, wgoff);
+    if ((rc1 = cohere(stream))) return rc1;
+    k_t3_filter<<<nwg, kHook3Block, 0, stream>>>(tmp2, run2, pl.nch2_max, R, base2, cbase, s->zbits,
+                                                (n + 31) / 32, surv, wgoff, wgcnt, s->st);
+    if ((rc1 = cohere(stream))) return rc1;
+    k_t4_scan<<<1, kPackBlock, 0, stream>>>(wgcnt, nwg, spref);
+    if ((rc1 = cohere(stream))) return rc1;
+    k_t4_pack<<<nwg, 256, 0, stream>>>(surv, wgoff, wgcnt, spref, dense);
+    if ((rc1 = cohere(stream))) return rc1;
+    k_t4_hook<<<kHook4Grid, kHook4Block, 0, stream>>>(dense, spref + nwg, P, s->st);
     CCM_HIP(hipGetLastError());
     return CC_OK;
 }
