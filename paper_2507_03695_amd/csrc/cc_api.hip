@@ -48,7 +48,7 @@ int slot_create(Slot* s, int device, uint32_t samples) {
     s->table = next_pow2(4ull * samples);
     if (s->table < 1024) s->table = 1024;
     CCM_HIP(hipSetDevice(device));
-    size_t bytes = sizeof(DevState) + 2ull * s->table * sizeof(uint32_t);
+    size_t bytes = sizeof(DevState) + (2ull * s->table + kGridCap) * sizeof(uint32_t);
     char* base = nullptr;
     hipError_t e = hipMalloc(&base, bytes);
     if (e != hipSuccess) {
@@ -58,6 +58,7 @@ int slot_create(Slot* s, int device, uint32_t samples) {
     s->st = reinterpret_cast<DevState*>(base);
     s->hkeys = reinterpret_cast<uint32_t*>(base + sizeof(DevState));
     s->hcounts = s->hkeys + s->table;
+    s->bmin = s->hcounts + s->table;
     CCM_HIP(hipMemset(s->st, 0, sizeof(DevState)));
     e = hipHostMalloc(&s->host_status, sizeof(uint32_t), hipHostMallocDefault);
     if (e != hipSuccess) {

@@ -28,6 +28,7 @@ static_assert(sizeof(DevState) == 64, "DevState is one 64-byte block");
 constexpr uint32_t kStatusRange = 1u;
 constexpr uint32_t kStatusInternal = 2u;   // a scratch bound check failed (a bug)
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+constexpr uint32_t kGridCap = 256 * 32;   // blocks of a grid-stride launch over n
 
 // One graph of a batched launch: where its entries and labels live.
 struct GraphDesc {
@@ -60,6 +61,7 @@ struct Slot {
     DevState* st = nullptr;        // device
     uint32_t* hkeys = nullptr;     // device, zroot hash table keys   [table]
     uint32_t* hcounts = nullptr;   // device, zroot hash table counts [table]
+    uint32_t* bmin = nullptr;      // device, per-block minima of compress [kGridCap]
     uint32_t table = 0;            // power of two >= 4 * samples
     uint32_t samples = 0;          // K
     uint32_t* deg = nullptr;       // device, exact-degree counts (grown on demand)

@@ -13,6 +13,9 @@
 // CAS, which fails and returns the current parent; the walk resumes there
 // (Sec. II: a failed CAS repeats the root search). Splitting stores go only
 // to non-roots, which no CAS can succeed on, so they never race with links.
+// Every store to P is an agent-scope atomic store: plain stores have been
+// observed to leave copies in the writing XCD's L2 that outlive later kernels'
+// writes from other XCDs, so that a later reader on that XCD sees an old value.
 #include "cc_internal.h"
 
 namespace ccm {
@@ -330,7 +333,9 @@ __global__ __launch_bounds__(kBlock) void k_hook(const uint32_t* __restrict__ ed
 // "root" would end the walk early); if the coherent value differs, the walk
 // continues from it. Lanes stopping at the same root share one request.
 template <bool ZR>
-__global__ __launch_bounds__(kBlock) void k_compress(uint32_t* P, uint64_t n, DevState* st) {
+__global__ __launch_bounds__(kBlock) void k_compress(uint32_t* P, uint64_t n, DevState* st,
+                                                     uint32_t* bmin) {
+    __shared__ uint32_t s_min[kBlock / 64];
     const uint32_t z = ZR ? ld_agent(&st->zroot) : 0u;
     uint32_t local_min = kEmpty;
     for (uint64_t v = (uint64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
@@ -352,8 +357,31 @@ __global__ __launch_bounds__(kBlock) void k_compress(uint32_t* P, uint64_t n, De
         if (ZR && r == z && (uint32_t)v < local_min) local_min = (uint32_t)v;
     }
     if (ZR) {
+        // the block's smallest member of z's tree; k_minz reduces over blocks
+        // (one atomic per block on a single word would serialise)
         local_min = wave_min_u32(local_min);
-        if ((threadIdx.x & 63) == 0 && local_min != kEmpty) atomicMin(&st->minz, local_min);
+        if ((threadIdx.x & 63) == 0) s_min[threadIdx.x >> 6] = local_min;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t b = s_min[0];
+            for (int w = 1; w < kBlock / 64; ++w) b = min(b, s_min[w]);
+            bmin[blockIdx.x] = b;
+        }
+    }
+}
+
+// minz = the smallest of the per-block minima (one block).
+__global__ __launch_bounds__(1024) void k_minz(const uint32_t* __restrict__ bmin, uint32_t nb,
+                                               DevState* st) {
+    __shared__ uint32_t s_min[1024 / 64];
+    uint32_t x = kEmpty;
+    for (uint32_t i = threadIdx.x; i < nb; i += 1024) x = min(x, bmin[i]);
+    x = wave_min_u32(x);
+    if ((threadIdx.x & 63) == 0) s_min[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 1024 / 64; ++w) x = min(x, s_min[w]);
+        st_agent(&st->minz, x);
     }
 }
 
@@ -391,7 +419,6 @@ static uint32_t grid_for(uint64_t work, uint64_t per_block, uint32_t cap) {
     return (uint32_t)(g < cap ? g : cap);
 }
 
-constexpr uint32_t kGridCap = 256 * 32;
 
 int run_init(Slot* s, uint64_t n, uint32_t* P, hipStream_t stream) {
     s->cur_n = n;
@@ -507,8 +534,15 @@ int run_hook(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P
 
 int run_compress(Slot* s, uint64_t n, uint32_t* P, uint32_t flags, hipStream_t stream) {
     const uint32_t g = grid_for(n, kBlock, kGridCap);
-    if (flags & CC_F_ZROOT) k_compress<true><<<g, kBlock, 0, stream>>>(P, n, s->st);
-    else k_compress<false><<<g, kBlock, 0, stream>>>(P, n, s->st);
+    if (flags & CC_F_ZROOT) {
+        k_compress<true><<<g, kBlock, 0, stream>>>(P, n, s->st, s->bmin);
+        CCM_HIP(hipGetLastError());
+        int rc = cohere(stream);
+        if (rc) return rc;
+        k_minz<<<1, 1024, 0, stream>>>(s->bmin, g, s->st);
+    } else {
+        k_compress<false><<<g, kBlock, 0, stream>>>(P, n, s->st, s->bmin);
+    }
     CCM_HIP(hipGetLastError());
     return CC_OK;
 }

@@ -500,17 +500,23 @@ __global__ __launch_bounds__(kHook3Block) void k_t3_filter(const u32x2* __restri
     __shared__ u32x2 queue[kWaves3 * kWaveQueue];
     __shared__ uint32_t wsum[kWaves3 + 1];
     __shared__ uint32_t s_used;
+    // Launch order: consecutive workgroups take different a (and spread over
+    // the b groups), so the workgroups running at the same time hold few
+    // copies of any one slice and see each other's marks through the global
+    // bitmap sooner. (a, bg) = (i mod R, (i div R + a) mod nbg) is a bijection.
     const int nbg = (R + kBPerBlock - 1) / kBPerBlock;
-    const int a = blockIdx.x / nbg, bg = blockIdx.x % nbg;
+    const int a = (int)(blockIdx.x % (uint32_t)R);
+    const int bg = (int)((blockIdx.x / (uint32_t)R + (uint32_t)a) % (uint32_t)nbg);
+    const uint32_t wi = (uint32_t)a * (uint32_t)nbg + (uint32_t)bg;   // region index
     const uint32_t cb = cbase[a];
     const uint32_t nch = cbase[a + 1] - cb;
     if (nch == 0) {
-        if (threadIdx.x == 0) wgcnt[blockIdx.x] = 0;
+        if (threadIdx.x == 0) wgcnt[wi] = 0;
         return;
     }
     if (threadIdx.x == 0) s_used = 0;
-    u32x2* out = surv + wgoff[blockIdx.x];
-    const uint32_t cap = (uint32_t)(wgoff[blockIdx.x + 1] - wgoff[blockIdx.x]);
+    u32x2* out = surv + wgoff[wi];
+    const uint32_t cap = (uint32_t)(wgoff[wi + 1] - wgoff[wi]);
     const uint32_t z = ld_agent(&st->zroot);
     constexpr int PER = kSliceWords / kHook3Block;       // 16 words per thread per slice
     {
@@ -628,7 +634,7 @@ __global__ __launch_bounds__(kHook3Block) void k_t3_filter(const u32x2* __restri
     }
     if (qn) t3_flush(wq, qn, lane, out, cap, &s_used, st);
     __syncthreads();
-    if (threadIdx.x == 0) wgcnt[blockIdx.x] = min(s_used, cap);
+    if (threadIdx.x == 0) wgcnt[wi] = min(s_used, cap);
 }
 
 // ---- 6. the survivor hook -------------------------------------------------------------------

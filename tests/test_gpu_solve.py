@@ -301,3 +301,26 @@ def test_compress_never_trusts_a_stale_root():
                 c.canon(n, P)
             assert c.sync() == cc.CC_OK
             assert_same_labels(to_host_u32(P), want, f"rep {rep} flags {fl}")
+
+
+def test_labels_read_back_by_the_next_kernel():
+    """Regression: after a plain solve that followed a zero-root solve, the first
+    torch kernel reading L saw an intermediate parent in one word (a splitting
+    store's line, left in the writing XCD's L2 and rewritten by another XCD's
+    compress), although the host copy was right. Alternate the two paths and
+    compare a device-side read of L (a conversion kernel) with the host copy."""
+    e, n = graphgen.rmat22_sym()
+    ed = to_dev(e)
+    want = None
+    with cc.Context() as c:
+        for rep in range(20):
+            fl = cc.F_ZROOT if rep % 2 == 0 else 0
+            L = c.solve(ed, n, flags=fl)
+            torch.cuda.synchronize()
+            host = L.cpu().numpy().view(np.uint32).astype(np.int64)
+            dev = (L.to(torch.int64) & 0xFFFFFFFF).cpu().numpy()
+            bad = np.flatnonzero(dev != host)
+            assert len(bad) == 0, f"rep {rep} flags {fl}: {len(bad)} words differ, first v={bad[0]}"
+            if want is None:
+                want = host
+            assert np.array_equal(host, want), f"rep {rep}: labels changed between solves"
