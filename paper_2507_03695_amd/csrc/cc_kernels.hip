@@ -331,13 +331,16 @@ __global__ __launch_bounds__(kBlock) void k_hook(const uint32_t* __restrict__ ed
 // (still ancestor) values freely, but the two facts the label rests on are read
 // coherently: the vertex's own entry, and the root the walk stops at (a stale
 // "root" would end the walk early); if the coherent value differs, the walk
-// continues from it. Lanes stopping at the same root share one request.
+// continues from it.
+// With a zero root the membership bitmap is part of the result: a set bit means
+// "connected to z" (the tiled hook records such links only as bits, see
+// cc_tiled.hip), so a tree that holds a marked vertex belongs to z's component.
+// Here every marked vertex passes its mark on to its root; k_resolve then
+// relabels the members of marked trees.
 template <bool ZR>
 __global__ __launch_bounds__(kBlock) void k_compress(uint32_t* P, uint64_t n, DevState* st,
-                                                     uint32_t* bmin) {
-    __shared__ uint32_t s_min[kBlock / 64];
+                                                     uint32_t* zbits) {
     const uint32_t z = ZR ? ld_agent(&st->zroot) : 0u;
-    uint32_t local_min = kEmpty;
     for (uint64_t v = (uint64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
          v += (uint64_t)gridDim.x * kBlock) {
         const uint32_t p = ld_agent(&P[v]);
@@ -353,20 +356,40 @@ __global__ __launch_bounds__(kBlock) void k_compress(uint32_t* P, uint64_t n, De
                 r = q;
             }
             if (r != p) st_agent(&P[v], r);
+            if (ZR && r != z && ((ld_agent(&zbits[v >> 5]) >> (v & 31)) & 1u))
+                atomicOr(&zbits[r >> 5], 1u << (r & 31));
         }
-        if (ZR && r == z && (uint32_t)v < local_min) local_min = (uint32_t)v;
     }
-    if (ZR) {
-        // the block's smallest member of z's tree; k_minz reduces over blocks
-        // (one atomic per block on a single word would serialise)
-        local_min = wave_min_u32(local_min);
-        if ((threadIdx.x & 63) == 0) s_min[threadIdx.x >> 6] = local_min;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t b = s_min[0];
-            for (int w = 1; w < kBlock / 64; ++w) b = min(b, s_min[w]);
-            bmin[blockIdx.x] = b;
+}
+
+// Zero root only, after k_compress: P_v <- z when v or its root is marked (v's
+// tree is then connected to z), and the block's smallest member of z's
+// component for minz. Marks are read coherently: they were set by atomics.
+__global__ __launch_bounds__(kBlock) void k_resolve(uint32_t* P, uint64_t n, DevState* st,
+                                                    const uint32_t* zbits, uint32_t* bmin) {
+    __shared__ uint32_t s_min[kBlock / 64];
+    const uint32_t z = ld_agent(&st->zroot);
+    uint32_t local_min = kEmpty;
+    for (uint64_t v = (uint64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
+         v += (uint64_t)gridDim.x * kBlock) {
+        const uint32_t r = ld_agent(&P[v]);
+        bool inz = r == z;
+        if (!inz) {
+            inz = ((ld_agent(&zbits[v >> 5]) >> (v & 31)) & 1u) ||
+                  (r != (uint32_t)v && ((ld_agent(&zbits[r >> 5]) >> (r & 31)) & 1u));
+            if (inz) st_agent(&P[v], z);
         }
+        if (inz && (uint32_t)v < local_min) local_min = (uint32_t)v;
+    }
+    // the block's smallest member of z's component; k_minz reduces over blocks
+    // (one atomic per block on a single word would serialise)
+    local_min = wave_min_u32(local_min);
+    if ((threadIdx.x & 63) == 0) s_min[threadIdx.x >> 6] = local_min;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t b = s_min[0];
+        for (int w = 1; w < kBlock / 64; ++w) b = min(b, s_min[w]);
+        bmin[blockIdx.x] = b;
     }
 }
 
@@ -535,13 +558,18 @@ int run_hook(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P
 int run_compress(Slot* s, uint64_t n, uint32_t* P, uint32_t flags, hipStream_t stream) {
     const uint32_t g = grid_for(n, kBlock, kGridCap);
     if (flags & CC_F_ZROOT) {
-        k_compress<true><<<g, kBlock, 0, stream>>>(P, n, s->st, s->bmin);
+        if (!s->zr_ready || s->cur_n != n)
+            return fail(CC_EINVAL, "a CC_F_ZROOT compress needs cc_init then cc_zroot on the same n");
+        k_compress<true><<<g, kBlock, 0, stream>>>(P, n, s->st, s->zbits);
         CCM_HIP(hipGetLastError());
         int rc = cohere(stream);
         if (rc) return rc;
+        k_resolve<<<g, kBlock, 0, stream>>>(P, n, s->st, s->zbits, s->bmin);
+        CCM_HIP(hipGetLastError());
+        if ((rc = cohere(stream))) return rc;
         k_minz<<<1, 1024, 0, stream>>>(s->bmin, g, s->st);
     } else {
-        k_compress<false><<<g, kBlock, 0, stream>>>(P, n, s->st, s->bmin);
+        k_compress<false><<<g, kBlock, 0, stream>>>(P, n, s->st, nullptr);
     }
     CCM_HIP(hipGetLastError());
     return CC_OK;

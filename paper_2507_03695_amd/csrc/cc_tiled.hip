@@ -17,14 +17,17 @@
 //                   segments, sorted in LDS by the slice of the second
 //                   endpoint (b) and written contiguously, with its b-runs.
 //  5. k_t3_filter — one workgroup per (a, b): both slices' bitmap words in
-//                   LDS; entries with both endpoints marked are dropped there,
-//                   the rest are appended to a survivor list, and an entry
-//                   with one marked endpoint marks the other (LDS and global).
+//                   LDS; an entry with both endpoints marked is dropped, one
+//                   with a single marked endpoint marks the other (LDS and
+//                   global) and is dropped, the rest go to a survivor list.
 //  6. k_t4_hook   — the ordinary hook over the survivor list.
 //
+// After this step the components are given by P and the bitmap together
+// (k_compress / k_resolve in cc_kernels.hip read both).
+//
 // The regrouping only reorders entries (and drops self-loops, which are
-// no-ops); hooking is order-independent (Sec. II), and dropped entries join
-// vertices the kept ones connect anyway, so the labels are those of the plain
+// no-ops), hooking is order-independent (Sec. II), and every dropped entry is
+// either redundant or recorded as a mark, so the labels are those of the plain
 // pass. Entries whose endpoints are out of range are dropped with
 // the status bit set, as in the plain hook.
 #include <algorithm>
@@ -369,17 +372,15 @@ __global__ __launch_bounds__(kPartBlock) void k_t2_part(const u32x2* __restrict_
 
 // ---- 5. the filter over bucket (a, b) with both slices' bitmap words in LDS ---------------
 //
-// While this kernel runs, a set bit means "connected to the zero root through
-// the entries hooked by the end of the step" (the warm-up's bits are stronger:
-// in z's tree already). An entry with both endpoints marked is dropped: it joins
-// two vertices that the kept entries connect anyway. Every other entry is kept
-// for the survivor hook, and when exactly one endpoint is marked the other is
-// marked at once (in LDS and in the global bitmap): once that kept entry is
-// hooked it is connected to z as well. Such an entry is kept as (x, z), x the
-// newly marked endpoint, which has the same effect on the components and
-// spares the hook the walk up the marked endpoint's path. Each mark thus rests on a kept entry and
-// an earlier mark, so no dropped entry is ever needed. Because marks are claims
-// about the end of the step, the survivor hook does not consult them.
+// From here on a set bit means "connected to the zero root" (the warm-up's and
+// the Initial Push's bits are stronger: in z's tree already). An entry with
+// both endpoints marked is dropped: the two are connected anyway. An entry with
+// exactly one marked endpoint is dropped too, after marking the other endpoint:
+// that mark is the entry's link to z, and compress later puts every tree that
+// holds a marked vertex into z's component. Each mark rests on an entry and an
+// earlier mark, so the marks never claim a connection the graph lacks. Only
+// entries with neither endpoint marked are kept, for the survivor hook, which
+// does not consult the bitmap.
 constexpr int kHook3Block = 1024;
 constexpr int kWaves3 = kHook3Block / 64;
 constexpr int kWin3 = 2048;      // level-2 chunks per window
@@ -517,7 +518,6 @@ __global__ __launch_bounds__(kHook3Block) void k_t3_filter(const u32x2* __restri
     if (threadIdx.x == 0) s_used = 0;
     u32x2* out = surv + wgoff[wi];
     const uint32_t cap = (uint32_t)(wgoff[wi + 1] - wgoff[wi]);
-    const uint32_t z = ld_agent(&st->zroot);
     constexpr int PER = kSliceWords / kHook3Block;       // 16 words per thread per slice
     {
         const uint64_t wa = (uint64_t)a * kSliceWords;
@@ -596,17 +596,14 @@ __global__ __launch_bounds__(kHook3Block) void k_t3_filter(const u32x2* __restri
                     const uint32_t iu = hv[k] ? (ou >> 5) : 0u, iv = hv[k] ? (ov >> 5) : 0u;
                     const uint32_t bu = 1u << (ou & 31), bv = 1u << (ov & 31);
                     const bool mu = (sa[iu] & bu) != 0u, mv = (lb[iv] & bv) != 0u;
-                    keep[k] = hv[k] && !(mu && mv);
+                    keep[k] = hv[k] && !mu && !mv;
                     if (hv[k] && mu != mv) {
-                        // mark the unmarked endpoint; the global word only once per workgroup
+                        // the entry's whole effect: mark the unmarked endpoint (the
+                        // global word only once per workgroup)
                         uint32_t* w = mu ? &lb[iv] : &sa[iu];
                         const uint32_t bit = mu ? bv : bu;
                         const uint32_t x = mu ? ev[k].y : ev[k].x;
                         if (!(atomicOr(w, bit) & bit)) atomicOr(&zbits[x >> 5], 1u << (x & 31));
-                        // the marked endpoint ends up connected to z: keep (x, z),
-                        // whose hook walks only x's path
-                        ev[k].x = x;
-                        ev[k].y = z;
                     }
                 }
 #pragma unroll
@@ -704,8 +701,9 @@ __global__ __launch_bounds__(256) void k_t4_pack(const u32x2* __restrict__ surv,
 }
 
 // Algorithm 3's hooking loop (keys of Formula 1 as an order, path splitting)
-// over the kept entries, with no bitmap: the marks may describe links that
-// this kernel has not made yet. Grid-stride over the dense list.
+// over the kept entries, with no bitmap: a mark is a link to z that is not in
+// P, so a marked vertex cannot stand in for z here. Grid-stride over the dense
+// list.
 constexpr int kHook4Block = 256;
 constexpr int kHook4EPT = 4;
 constexpr int kHook4Grid = 2048;     // 8 workgroups per CU
