@@ -570,62 +570,70 @@ __global__ __launch_bounds__(kHook3Block) void k_t3_filter(const u32x2* __restri
             // takes ranges of kRange consecutive indices (lanes step through the
             // runs).
             uint32_t j0 = (uint32_t)wave * kRange;
-            // Addresses first (LDS only), then the loads back to back: no loop
-            // sits between loads, so none forces an early wait on the loads in
-            // flight.
-            auto issue = [&](uint32_t jb, u32x2* ev, bool* hv) {
-                uint32_t t = t3_find_run(s_pre, nw, jb, lane);
-                uint64_t at[kRunsInFlight];
-#pragma unroll
-                for (int k = 0; k < kRunsInFlight; ++k) {
-                    const uint32_t j = jb + (uint32_t)k * 64 + lane;
-                    hv[k] = j < total;
-                    while (t + 1 < nw && s_pre[t + 1] <= j) ++t;
-                    at[k] = hv[k] ? (uint64_t)(w0 + t) * kC2 + s_r0[t] + (j - s_pre[t]) : 0ull;
-                }
-#pragma unroll
-                for (int k = 0; k < kRunsInFlight; ++k) ev[k] = __builtin_nontemporal_load(src + at[k]);
+            if (j0 >= total) continue;
+            constexpr uint32_t kStep = kWaves3 * kRange;
+            // Address of index j of the window (t: the run holding an earlier
+            // index of this lane, advanced in place).
+            auto addr = [&](uint32_t j, uint32_t& t) -> uint64_t {
+                while (t + 1 < nw && s_pre[t + 1] <= j) ++t;
+                return (uint64_t)(w0 + t) * kC2 + s_r0[t] + (j - s_pre[t]);
             };
-            // Membership tests of one range; kept entries are staged in the
-            // wave's queue (marks as described above).
-            auto test = [&](u32x2* ev, const bool* hv) {
-                bool keep[kRunsInFlight];
+            // Software pipeline: e[k] holds entry k of the current range; right
+            // after it is tested its register is reloaded with entry k of the
+            // next range, so a range's loads are in flight while the previous
+            // range is tested, and no loaded value is ever copied.
+            u32x2 e[kRunsInFlight];
+            bool h[kRunsInFlight];
+            {
+                uint32_t t = t3_find_run(s_pre, nw, j0, lane);
 #pragma unroll
                 for (int k = 0; k < kRunsInFlight; ++k) {
-                    const uint32_t ou = ev[k].x - abase, ov = ev[k].y - bbase;
-                    const uint32_t iu = hv[k] ? (ou >> 5) : 0u, iv = hv[k] ? (ov >> 5) : 0u;
+                    const uint32_t j = j0 + (uint32_t)k * 64 + lane;
+                    h[k] = j < total;
+                    const uint64_t at = h[k] ? addr(j, t) : 0ull;
+                    e[k] = __builtin_nontemporal_load(src + at);
+                }
+            }
+            while (true) {
+                const uint32_t jn = j0 + kStep;
+                const bool more = jn < total;
+                uint32_t tn = more ? t3_find_run(s_pre, nw, jn, lane) : 0u;
+#pragma unroll
+                for (int k = 0; k < kRunsInFlight; ++k) {
+                    // test entry k of the current range
+                    const u32x2 x = e[k];
+                    const uint32_t ou = x.x - abase, ov = x.y - bbase;
+                    const uint32_t iu = h[k] ? (ou >> 5) : 0u, iv = h[k] ? (ov >> 5) : 0u;
                     const uint32_t bu = 1u << (ou & 31), bv = 1u << (ov & 31);
                     const bool mu = (sa[iu] & bu) != 0u, mv = (lb[iv] & bv) != 0u;
-                    keep[k] = hv[k] && !mu && !mv;
-                    if (hv[k] && mu != mv) {
+                    const bool keep = h[k] && !mu && !mv;
+                    if (h[k] && mu != mv) {
                         // the entry's whole effect: mark the unmarked endpoint (the
                         // global word only once per workgroup)
                         uint32_t* w = mu ? &lb[iv] : &sa[iu];
                         const uint32_t bit = mu ? bv : bu;
-                        const uint32_t x = mu ? ev[k].y : ev[k].x;
-                        if (!(atomicOr(w, bit) & bit)) atomicOr(&zbits[x >> 5], 1u << (x & 31));
+                        const uint32_t y = mu ? x.y : x.x;
+                        if (!(atomicOr(w, bit) & bit)) atomicOr(&zbits[y >> 5], 1u << (y & 31));
                     }
-                }
-#pragma unroll
-                for (int k = 0; k < kRunsInFlight; ++k) {
-                    const uint64_t ball = __ballot(keep[k]);
-                    if (keep[k]) wq[qn + (uint32_t)__popcll(ball & ((1ull << lane) - 1ull))] = ev[k];
+                    const uint64_t ball = __ballot(keep);
+                    if (keep) wq[qn + (uint32_t)__popcll(ball & ((1ull << lane) - 1ull))] = x;
                     qn += (uint32_t)__popcll(ball);
                     if (qn >= 64) {
                         t3_flush(wq, qn, lane, out, cap, &s_used, st);
                         qn = 0;
                     }
+                    // reload register k with entry k of the next range (also after
+                    // the last range, from a safe address: an unconditional load
+                    // keeps the count of loads in flight known to the compiler)
+                    {
+                        const uint32_t j = jn + (uint32_t)k * 64 + lane;
+                        h[k] = more && j < total;
+                        const uint64_t at = h[k] ? addr(j, tn) : 0ull;
+                        e[k] = __builtin_nontemporal_load(src + at);
+                    }
                 }
-            };
-            // Each wave loads a whole range (kRunsInFlight entries per lane, all
-            // in flight at once) and then tests it; the other waves of the
-            // workgroup keep the memory system busy meanwhile.
-            constexpr uint32_t kStep = kWaves3 * kRange;
-            u32x2 e[kRunsInFlight];
-            bool h[kRunsInFlight];
-            for (; j0 < total; j0 += kStep) {
-                issue(j0, e, h);
-                test(e, h);
+                if (!more) break;
+                j0 = jn;
             }
         }
     }
