@@ -6,7 +6,8 @@ edge list already resident in HBM: init, zero root (sampled), Initial Push,
 hook, compress and the zero-component relabelling (flags CC_F_ZROOT), i.e.
 cc_init / cc_zroot / cc_push / cc_hook / cc_compress / cc_canon enqueued on one
 stream. The hook step (one cc_hook call: on the zero-root path a short direct
-hook over 1/64 of the entries, two partition passes and the tiled hook kernel)
+hook over 1/1024 of the entries, two partition passes, the membership filter and
+the hook of the surviving entries)
 is bracketed by its own HIP events on that stream inside the timed region; the
 roofline figure is its algorithmic bytes (8 per entry) over that duration.
 
@@ -38,8 +39,9 @@ TRAFFIC = {
 }
 
 HOOK_KERNELS = {
-    "zroot": "cc_hook step: k_hook<ZR> on 1/64 of the entries, k_t1_part, k_t1_tsum, k_t1_scan, "
-             "k_t1_bases, k_t2_bounds, k_t2_part, k_t3_hook",
+    "zroot": "cc_hook step: k_hook<ZR> on 1/1024 of the entries, k_t1_part, k_t1_tsum, k_t1_scan, "
+             "k_t1_bases, k_t2_bounds, k_t2_part, k_t3_regions, k_t3_filter, k_t4_scan, k_t4_pack, "
+             "k_t4_hook",
     "plain": "cc_hook step: k_hook<plain>",
 }
 

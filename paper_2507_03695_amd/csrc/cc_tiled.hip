@@ -40,11 +40,25 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kSliceBits = 19;                       // 2^19 vertices per slice
 constexpr uint32_t kSliceWords = (1u << kSliceBits) / 32;   // 16384 words = 64 KB
+constexpr uint32_t kLoMask = (1u << kSliceBits) - 1;
+
+// Packed entries. With at most 256 slices every ID is below 2^27, and inside a
+// bucket the slice bits of an endpoint are known, so the buffers between the
+// passes hold fewer than 8 bytes per entry:
+//  level 1 (bucket a known): w = u_lo | v << 19, h = v >> 13 (4 + 2 bytes)
+// (u_lo: the low 19 bits of u; the top 13 bits of w carry the low 13 bits of v).
+// The survivor regions reuse this format. The level-2 buffer keeps (u, v) as
+// two words: the filter that reads it is bound by latency, not by bytes.
+__device__ __forceinline__ uint32_t pk_w(uint32_t ulo, uint32_t v) { return ulo | (v << kSliceBits); }
+__device__ __forceinline__ uint32_t pk_v1(uint32_t w, uint16_t h) {
+    return (w >> kSliceBits) | ((uint32_t)h << (32 - kSliceBits));
+}
+
 constexpr int kMaxSlices = 256;
 constexpr int kC1 = 8192;                            // level-1 chunk (entries)
 constexpr int kC2 = 8192;                            // level-2 chunk (entries)
 constexpr int kPartBlock = 1024;
-constexpr int kPartEPT = kC1 / kPartBlock;           // 16
+constexpr int kPartEPT = kC1 / kPartBlock;           // 8
 
 // ---- shared device helpers (same rules as the plain hook) ---------------------
 
@@ -115,7 +129,8 @@ __device__ __forceinline__ void wave_scan_256(const uint32_t* cnt, uint32_t* sta
 // ---- 1. level-1 partition by the first endpoint's slice -----------------------------
 __global__ __launch_bounds__(kPartBlock) void k_t1_part(const uint32_t* __restrict__ edges,
                                                         uint64_t m, uint32_t n, int R,
-                                                        uint64_t nch1, u32x2* __restrict__ tmp1,
+                                                        uint64_t nch1, uint32_t* __restrict__ t1w,
+                                                        uint16_t* __restrict__ t1h,
                                                         uint16_t* __restrict__ segT,
                                                         uint32_t* __restrict__ cnt1,
                                                         DevState* st) {
@@ -155,8 +170,11 @@ __global__ __launch_bounds__(kPartBlock) void k_t1_part(const uint32_t* __restri
         if (rank[k] != 0xFFFF) stage[start[e[k].x >> kSliceBits] + rank[k]] = e[k];
     __syncthreads();
     const uint32_t kept = start[R];
-    u32x2* out = tmp1 + c * kC1;
-    for (uint32_t i = threadIdx.x; i < kept; i += kPartBlock) out[i] = stage[i];
+    for (uint32_t i = threadIdx.x; i < kept; i += kPartBlock) {
+        const u32x2 x = stage[i];
+        t1w[c * kC1 + i] = pk_w(x.x & kLoMask, x.y);
+        t1h[c * kC1 + i] = (uint16_t)(x.y >> (32 - kSliceBits));
+    }
     for (int d = threadIdx.x; d < R; d += kPartBlock) {
         segT[(uint64_t)d * nch1 + c] = (uint16_t)start[d];
         cnt1[(uint64_t)d * nch1 + c] = hist[d];
@@ -281,7 +299,8 @@ __global__ __launch_bounds__(256) void k_t2_bounds(const uint32_t* __restrict__ 
 // ---- 4b. level-2 partition by the second endpoint's slice ----------------------------------
 constexpr int kWin2 = 256;   // level-1 chunks per gather window (owner index fits a byte)
 
-__global__ __launch_bounds__(kPartBlock) void k_t2_part(const u32x2* __restrict__ tmp1,
+__global__ __launch_bounds__(kPartBlock) void k_t2_part(const uint32_t* __restrict__ t1w,
+                                                        const uint16_t* __restrict__ t1h,
                                                         const uint16_t* __restrict__ segT,
                                                         const uint32_t* __restrict__ pre1,
                                                         uint64_t nch1, int R,
@@ -334,21 +353,26 @@ __global__ __launch_bounds__(kPartBlock) void k_t2_part(const u32x2* __restrict_
         }
         __syncthreads();
         const uint32_t wlo = max(s_pre[0], vlo), whi = min(s_pre[nw], vhi);
-        u32x2 x[kPartEPT];
+        uint32_t xw[kPartEPT];
+        uint16_t xh[kPartEPT];
         bool in[kPartEPT];
 #pragma unroll
         for (int k = 0; k < kPartEPT; ++k) {
-            // unconditional load (a safe in-bounds address when the position is
+            // unconditional loads (a safe in-bounds address when the position is
             // not in this window) so that all loads of the thread are in flight
             const uint32_t p = vlo + (uint32_t)k * kPartBlock + threadIdx.x;
             in[k] = p >= wlo && p < whi;
             const uint32_t i = in[k] ? owner[p - vlo] : 0u;
             const uint64_t at = in[k] ? (cw + i) * kC1 + s_seg[i] + (p - s_pre[i]) : 0ull;
-            x[k] = tmp1[at];
+            xw[k] = t1w[at];
+            xh[k] = t1h[at];
         }
 #pragma unroll
         for (int k = 0; k < kPartEPT; ++k)
-            if (in[k]) e[k] = x[k];
+            if (in[k]) {
+                e[k].x = ((uint32_t)a << kSliceBits) | (xw[k] & kLoMask);
+                e[k].y = pk_v1(xw[k], xh[k]);
+            }
         __syncthreads();
     }
     uint16_t rank[kPartEPT];
@@ -417,9 +441,11 @@ __device__ __forceinline__ void block_scan_2048(uint32_t* x, uint32_t n, uint32_
 
 // Append the first `qn` staged entries of this wave (qn < 128) to the
 // workgroup's survivor region: the place comes from an LDS counter, so no
-// global atomic is involved; one entry per lane per round.
-__device__ __forceinline__ void t3_flush(const u32x2* wq, uint32_t qn, int lane, u32x2* out,
-                                         uint32_t cap, uint32_t* s_used, DevState* st) {
+// global atomic is involved; one entry per lane per round. Every entry of the
+// workgroup has its first endpoint in slice a, so the level-1 packing applies.
+__device__ __forceinline__ void t3_flush(const u32x2* wq, uint32_t qn, int lane, uint32_t* ow,
+                                         uint16_t* oh, uint32_t cap, uint32_t* s_used,
+                                         DevState* st) {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     uint32_t base = 0;
@@ -431,8 +457,17 @@ __device__ __forceinline__ void t3_flush(const u32x2* wq, uint32_t qn, int lane,
         if (lane == 0) atomicOr(&st->status, kStatusInternal);
         qn = 0;
     }
-    if ((uint32_t)lane < qn) out[base + lane] = wq[lane];
-    if ((uint32_t)lane + 64 < qn) out[base + lane + 64] = wq[lane + 64];
+    // wq holds (u_lo, v); the region stores the level-1 packed form
+    if ((uint32_t)lane < qn) {
+        const u32x2 x = wq[lane];
+        ow[base + lane] = pk_w(x.x, x.y);
+        oh[base + lane] = (uint16_t)(x.y >> (32 - kSliceBits));
+    }
+    if ((uint32_t)lane + 64 < qn) {
+        const u32x2 x = wq[lane + 64];
+        ow[base + lane + 64] = pk_w(x.x, x.y);
+        oh[base + lane + 64] = (uint16_t)(x.y >> (32 - kSliceBits));
+    }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
@@ -490,7 +525,8 @@ __global__ __launch_bounds__(kHook3Block) void k_t3_filter(const u32x2* __restri
                                                            const uint64_t* __restrict__ base2,
                                                            const uint32_t* __restrict__ cbase,
                                                            uint32_t* zbits, uint64_t words,
-                                                           u32x2* __restrict__ surv,
+                                                           uint32_t* __restrict__ sw,
+                                                           uint16_t* __restrict__ sh,
                                                            const uint64_t* __restrict__ wgoff,
                                                            uint32_t* __restrict__ wgcnt,
                                                            DevState* st) {
@@ -516,7 +552,8 @@ __global__ __launch_bounds__(kHook3Block) void k_t3_filter(const u32x2* __restri
         return;
     }
     if (threadIdx.x == 0) s_used = 0;
-    u32x2* out = surv + wgoff[wi];
+    uint32_t* ow = sw + wgoff[wi];
+    uint16_t* oh = sh + wgoff[wi];
     const uint32_t cap = (uint32_t)(wgoff[wi + 1] - wgoff[wi]);
     constexpr int PER = kSliceWords / kHook3Block;       // 16 words per thread per slice
     {
@@ -601,8 +638,7 @@ __global__ __launch_bounds__(kHook3Block) void k_t3_filter(const u32x2* __restri
 #pragma unroll
                 for (int k = 0; k < kRunsInFlight; ++k) {
                     // test entry k of the current range
-                    const u32x2 x = e[k];
-                    const uint32_t ou = x.x - abase, ov = x.y - bbase;
+                    const uint32_t ou = e[k].x - abase, ov = e[k].y - bbase;
                     const uint32_t iu = h[k] ? (ou >> 5) : 0u, iv = h[k] ? (ov >> 5) : 0u;
                     const uint32_t bu = 1u << (ou & 31), bv = 1u << (ov & 31);
                     const bool mu = (sa[iu] & bu) != 0u, mv = (lb[iv] & bv) != 0u;
@@ -612,14 +648,17 @@ __global__ __launch_bounds__(kHook3Block) void k_t3_filter(const u32x2* __restri
                         // global word only once per workgroup)
                         uint32_t* w = mu ? &lb[iv] : &sa[iu];
                         const uint32_t bit = mu ? bv : bu;
-                        const uint32_t y = mu ? x.y : x.x;
+                        const uint32_t y = mu ? bbase + ov : abase + ou;
                         if (!(atomicOr(w, bit) & bit)) atomicOr(&zbits[y >> 5], 1u << (y & 31));
                     }
                     const uint64_t ball = __ballot(keep);
-                    if (keep) wq[qn + (uint32_t)__popcll(ball & ((1ull << lane) - 1ull))] = x;
+                    if (keep) {
+                        const u32x2 x = {ou, bbase + ov};
+                        wq[qn + (uint32_t)__popcll(ball & ((1ull << lane) - 1ull))] = x;
+                    }
                     qn += (uint32_t)__popcll(ball);
                     if (qn >= 64) {
-                        t3_flush(wq, qn, lane, out, cap, &s_used, st);
+                        t3_flush(wq, qn, lane, ow, oh, cap, &s_used, st);
                         qn = 0;
                     }
                     // reload register k with entry k of the next range (also after
@@ -637,27 +676,28 @@ __global__ __launch_bounds__(kHook3Block) void k_t3_filter(const u32x2* __restri
             }
         }
     }
-    if (qn) t3_flush(wq, qn, lane, out, cap, &s_used, st);
+    if (qn) t3_flush(wq, qn, lane, ow, oh, cap, &s_used, st);
     __syncthreads();
     if (threadIdx.x == 0) wgcnt[wi] = min(s_used, cap);
 }
 
 // ---- 6. the survivor hook -------------------------------------------------------------------
-// The regions are first packed into one dense list (exclusive prefix of the
-// region counts, then one block per region copies its entries), so that the
-// hook can spread the list evenly over the whole chip.
+// Work items of kItem consecutive entries of one region: an exclusive prefix of
+// the regions' item counts, then a grid-stride loop over items, each mapped to
+// its region by a binary search of that prefix.
 constexpr int kPackBlock = 1024;
+constexpr uint32_t kItem = 1024;     // entries per work item (4 per thread)
 
-// Exclusive prefix of cnt[0..nw) into pref[0..nw], pref[nw] = total; one block.
+// ipref[w] = sum over v < w of ceil(cnt[v] / kItem); ipref[nw] = total; one block.
 __global__ __launch_bounds__(kPackBlock) void k_t4_scan(const uint32_t* __restrict__ cnt,
-                                                        uint32_t nw, uint32_t* __restrict__ pref) {
+                                                        uint32_t nw, uint32_t* __restrict__ ipref) {
     __shared__ uint32_t ws[kPackBlock / 64 + 1];
     __shared__ uint32_t s_carry;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (threadIdx.x == 0) s_carry = 0;
     for (uint32_t base = 0; base < nw; base += kPackBlock) {
         const uint32_t i = base + threadIdx.x;
-        const uint32_t x = i < nw ? cnt[i] : 0u;
+        const uint32_t x = i < nw ? (cnt[i] + kItem - 1) / kItem : 0u;
         uint32_t incl = x;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
@@ -672,76 +712,69 @@ __global__ __launch_bounds__(kPackBlock) void k_t4_scan(const uint32_t* __restri
             ws[kPackBlock / 64] = run;
         }
         __syncthreads();
-        if (i < nw) pref[i] = ws[wave] + incl - x;
+        if (i < nw) ipref[i] = ws[wave] + incl - x;
         __syncthreads();
         if (threadIdx.x == 0) s_carry = ws[kPackBlock / 64];
         __syncthreads();
     }
-    if (threadIdx.x == 0) pref[nw] = s_carry;
-}
-
-// Region w's entries to dense[pref[w] ..); one block per region, eight loads
-// per thread in flight.
-constexpr int kPackEPT = 8;
-
-__global__ __launch_bounds__(256) void k_t4_pack(const u32x2* __restrict__ surv,
-                                                 const uint64_t* __restrict__ wgoff,
-                                                 const uint32_t* __restrict__ cnt,
-                                                 const uint32_t* __restrict__ pref,
-                                                 u32x2* __restrict__ dense) {
-    const uint32_t w = blockIdx.x;
-    const uint32_t c = cnt[w];
-    const u32x2* src = surv + wgoff[w];
-    u32x2* dst = dense + pref[w];
-    for (uint32_t i0 = 0; i0 < c; i0 += 256 * kPackEPT) {
-        u32x2 x[kPackEPT];
-#pragma unroll
-        for (int k = 0; k < kPackEPT; ++k) {
-            const uint32_t i = i0 + (uint32_t)k * 256 + threadIdx.x;
-            x[k] = src[i < c ? i : 0u];
-        }
-#pragma unroll
-        for (int k = 0; k < kPackEPT; ++k) {
-            const uint32_t i = i0 + (uint32_t)k * 256 + threadIdx.x;
-            if (i < c) dst[i] = x[k];
-        }
-    }
+    if (threadIdx.x == 0) ipref[nw] = s_carry;
 }
 
 // Algorithm 3's hooking loop (keys of Formula 1 as an order, path splitting)
 // over the kept entries, with no bitmap: a mark is a link to z that is not in
-// P, so a marked vertex cannot stand in for z here. Grid-stride over the dense
-// list.
+// P, so a marked vertex cannot stand in for z here.
 constexpr int kHook4Block = 256;
-constexpr int kHook4EPT = 4;
+constexpr int kHook4EPT = (int)kItem / kHook4Block;
 constexpr int kHook4Grid = 2048;     // 8 workgroups per CU
 
-__global__ __launch_bounds__(kHook4Block) void k_t4_hook(const u32x2* __restrict__ list,
-                                                         const uint32_t* __restrict__ count,
-                                                         uint32_t* P, DevState* st) {
+__global__ __launch_bounds__(kHook4Block) void k_t4_hook(const uint32_t* __restrict__ sw,
+                                                         const uint16_t* __restrict__ sh,
+                                                         const uint64_t* __restrict__ wgoff,
+                                                         const uint32_t* __restrict__ cnt,
+                                                         const uint32_t* __restrict__ ipref,
+                                                         uint32_t nw, int nbg, uint32_t* P,
+                                                         DevState* st) {
+    __shared__ uint32_t s_w;
     const uint32_t z = ld_agent(&st->zroot);
-    const uint64_t S = ld_agent(count);
-    constexpr uint64_t per = (uint64_t)kHook4Block * kHook4EPT;
-    for (uint64_t t0 = (uint64_t)blockIdx.x * per; t0 < S; t0 += (uint64_t)gridDim.x * per) {
-        u32x2 e[kHook4EPT];
+    const uint32_t items = ld_agent(&ipref[nw]);
+    for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
+        __syncthreads();                       // s_w of the previous item consumed
+        if (threadIdx.x == 0) {
+            uint32_t lo = 0, hi = nw - 1;      // last w with ipref[w] <= it
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi + 1) / 2;
+                if (ipref[mid] <= it) lo = mid; else hi = mid - 1;
+            }
+            s_w = lo;
+        }
+        __syncthreads();
+        const uint32_t w = s_w;
+        const uint32_t abase = (uint32_t)(w / (uint32_t)nbg) << kSliceBits;
+        const uint32_t k0 = (it - ipref[w]) * kItem;
+        const uint32_t c = min(cnt[w] - k0, kItem);
+        const uint64_t base = wgoff[w] + k0;
+        uint32_t u[kHook4EPT], v[kHook4EPT];
         bool h[kHook4EPT];
 #pragma unroll
         for (int k = 0; k < kHook4EPT; ++k) {
-            const uint64_t i = t0 + (uint64_t)k * kHook4Block + threadIdx.x;
-            h[k] = i < S;
-            e[k] = list[h[k] ? i : 0];
+            const uint32_t i = (uint32_t)k * kHook4Block + threadIdx.x;
+            h[k] = i < c;
+            const uint64_t at = base + (h[k] ? i : 0u);
+            const uint32_t x = sw[at];
+            u[k] = abase | (x & kLoMask);
+            v[k] = pk_v1(x, sh[at]);
         }
         uint32_t pu[kHook4EPT], pv[kHook4EPT];
 #pragma unroll
         for (int k = 0; k < kHook4EPT; ++k) {
-            pu[k] = P[e[k].x];
-            pv[k] = P[e[k].y];
+            pu[k] = P[u[k]];
+            pv[k] = P[v[k]];
         }
 #pragma unroll
         for (int k = 0; k < kHook4EPT; ++k) {
             if (!h[k]) continue;
-            if (pu[k] == pv[k] || pu[k] == e[k].y || pv[k] == e[k].x) continue;
-            (void)t_link(P, e[k].x, pu[k], e[k].y, pv[k], z);
+            if (pu[k] == pv[k] || pu[k] == v[k] || pv[k] == u[k]) continue;
+            (void)t_link(P, u[k], pu[k], v[k], pv[k], z);
         }
     }
 }
@@ -788,10 +821,12 @@ void tiled_free(TiledScratch* t) {
 
 int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
                    hipStream_t stream) {
-    // Warm-up: the first 1/64 of the entries go through the direct hook, so the
-    // membership bitmap already holds the core of the zero root's tree when the
-    // first tiles load their slices.
-    const uint64_t m0 = m >> 6;
+    // Warm-up: the first 1/1024 of the entries go through the direct hook, so
+    // the membership bitmap already holds the core of the zero root's tree when
+    // the first tiles load their slices. (Measured on R-MAT-26: from 1/64 to
+    // 1/4096 the step time barely moves; a longer warm-up trades its own random
+    // accesses for marks the filter would otherwise set.)
+    const uint64_t m0 = m >> 10;
     if (m0) {
         int rc0 = run_hook(s, n, m0, edges, P, CC_F_ZROOT | CC_F_NO_TILE, stream);
         if (rc0) return rc0;
@@ -801,7 +836,8 @@ int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint3
     const TiledPlan pl = tiled_plan(n, m);
     const int R = pl.R;
     auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
-    const uint64_t b_tmp = al(8 * (pl.nch1 * kC1));
+    const uint64_t cap = pl.nch1 * kC1;                  // entries of each buffer
+    const uint64_t b_t1w = al(4 * cap), b_t1h = al(2 * cap), b_tmp2 = al(8 * cap);
     const uint64_t b_seg1 = al(2 * pl.nch1 * R);
     const uint32_t ntile = (uint32_t)((pl.nch1 + kScanTile - 1) / kScanTile);
     const uint64_t b_tsum = al(4 * (uint64_t)ntile * R);
@@ -814,14 +850,15 @@ int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint3
     const uint32_t nbg = (uint32_t)((R + kBPerBlock - 1) / kBPerBlock);
     const uint32_t nwg = (uint32_t)R * nbg;
     const uint64_t b_wgoff = al(8 * ((uint64_t)nwg + 1)), b_wgcnt = al(4 * (uint64_t)nwg);
-    const uint64_t b_spref = al(4 * ((uint64_t)nwg + 1));
-    const uint64_t total = 2 * b_tmp + b_seg1 + b_cnt1 + b_pre1 + b_base2 + b_cbase + b_run2 +
-                           2 * b_ctab + b_tsum + b_wgoff + b_wgcnt + b_spref;
+    const uint64_t b_ipref = al(4 * ((uint64_t)nwg + 1));
+    const uint64_t total = b_t1w + b_t1h + b_tmp2 + b_seg1 + b_cnt1 + b_pre1 + b_base2 +
+                           b_cbase + b_run2 + 2 * b_ctab + b_tsum + b_wgoff + b_wgcnt + b_ipref;
     int rc = grow(reinterpret_cast<void**>(&s->tiled.buf), &s->tiled.cap, total, stream);
     if (rc) return rc;
     char* q = s->tiled.buf;
-    u32x2* tmp1 = reinterpret_cast<u32x2*>(q); q += b_tmp;
-    u32x2* tmp2 = reinterpret_cast<u32x2*>(q); q += b_tmp;
+    uint32_t* t1w = reinterpret_cast<uint32_t*>(q); q += b_t1w;
+    uint16_t* t1h = reinterpret_cast<uint16_t*>(q); q += b_t1h;
+    u32x2* tmp2 = reinterpret_cast<u32x2*>(q); q += b_tmp2;
     uint16_t* segT = reinterpret_cast<uint16_t*>(q); q += b_seg1;
     uint32_t* cnt1 = reinterpret_cast<uint32_t*>(q); q += b_cnt1;
     uint32_t* pre1 = reinterpret_cast<uint32_t*>(q); q += b_pre1;
@@ -833,14 +870,14 @@ int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint3
     uint32_t* tsum = reinterpret_cast<uint32_t*>(q); q += b_tsum;
     uint64_t* wgoff = reinterpret_cast<uint64_t*>(q); q += b_wgoff;
     uint32_t* wgcnt = reinterpret_cast<uint32_t*>(q); q += b_wgcnt;
-    uint32_t* spref = reinterpret_cast<uint32_t*>(q);
-    u32x2* surv = tmp1;      // free once the level-2 partition has read it
-    u32x2* dense = tmp2;     // free once the filter has read it
+    uint32_t* ipref = reinterpret_cast<uint32_t*>(q);
+    // the survivor regions live in the level-1 buffers, free once the level-2
+    // partition has read them (positions [base2[a], base2[a+1]) for slice a)
     // every kernel below reads tables the previous one wrote: coherence points between
     int rc1;
     if ((rc1 = cohere(stream))) return rc1;
-    k_t1_part<<<(uint32_t)pl.nch1, kPartBlock, 0, stream>>>(edges, m, (uint32_t)n, R, pl.nch1, tmp1,
-                                                           segT, cnt1, s->st);
+    k_t1_part<<<(uint32_t)pl.nch1, kPartBlock, 0, stream>>>(edges, m, (uint32_t)n, R, pl.nch1, t1w,
+                                                           t1h, segT, cnt1, s->st);
     if ((rc1 = cohere(stream))) return rc1;
     k_t1_tsum<<<(uint32_t)R * ntile, kScanBlock, 0, stream>>>(cnt1, pl.nch1, ntile, tsum);
     if ((rc1 = cohere(stream))) return rc1;
@@ -852,20 +889,20 @@ int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint3
     k_t2_bounds<<<(uint32_t)((pairs + 255) / 256), 256, 0, stream>>>(pre1, pl.nch1, R, cbase, c0tab,
                                                                     c1tab);
     if ((rc1 = cohere(stream))) return rc1;
-    k_t2_part<<<(uint32_t)pl.nch2_max, kPartBlock, 0, stream>>>(tmp1, segT, pre1, pl.nch1, R, base2,
-                                                               cbase, c0tab, c1tab, tmp2, run2,
+    k_t2_part<<<(uint32_t)pl.nch2_max, kPartBlock, 0, stream>>>(t1w, t1h, segT, pre1, pl.nch1, R,
+                                                               base2, cbase, c0tab, c1tab, tmp2, run2,
                                                                pl.nch2_max);
     if ((rc1 = cohere(stream))) return rc1;
     k_t3_regions<<<(uint32_t)R, 256, 0, stream>>>(run2, pl.nch2_max, R, base2, cbase, wgoff);
     if ((rc1 = cohere(stream))) return rc1;
-    k_t3_filter<<<nwg, kHook3Block, 0, stream>>>(tmp2, run2, pl.nch2_max, R, base2, cbase, s->zbits,
-                                                (n + 31) / 32, surv, wgoff, wgcnt, s->st);
+    k_t3_filter<<<nwg, kHook3Block, 0, stream>>>(tmp2, run2, pl.nch2_max, R, base2, cbase,
+                                                s->zbits, (n + 31) / 32, t1w, t1h, wgoff, wgcnt,
+                                                s->st);
     if ((rc1 = cohere(stream))) return rc1;
-    k_t4_scan<<<1, kPackBlock, 0, stream>>>(wgcnt, nwg, spref);
+    k_t4_scan<<<1, kPackBlock, 0, stream>>>(wgcnt, nwg, ipref);
     if ((rc1 = cohere(stream))) return rc1;
-    k_t4_pack<<<nwg, 256, 0, stream>>>(surv, wgoff, wgcnt, spref, dense);
-    if ((rc1 = cohere(stream))) return rc1;
-    k_t4_hook<<<kHook4Grid, kHook4Block, 0, stream>>>(dense, spref + nwg, P, s->st);
+    k_t4_hook<<<kHook4Grid, kHook4Block, 0, stream>>>(t1w, t1h, wgoff, wgcnt, ipref, nwg, (int)nbg,
+                                                      P, s->st);
     CCM_HIP(hipGetLastError());
     return CC_OK;
 }
