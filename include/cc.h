@@ -160,14 +160,23 @@ int cc_push(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t
    the root of greater key is linked under the other by compare-and-swap,
    retrying from the value the failed CAS returns. key(x) = x, or with
    CC_F_ZROOT key(z) = 0 and key(x) = x + 1 (R of Formula 1). With
-   CC_F_ZROOT, entries whose endpoints both have parent z are skipped.
-   Out-of-range endpoints set the status word and are skipped. */
+   CC_F_ZROOT the context also keeps a membership bitmap of the vertices
+   known to be connected to z: an entry with both endpoints in it is skipped,
+   and on the tiled path an entry with exactly one endpoint in it only adds
+   the other endpoint (that bit is the entry's link to z). After a CC_F_ZROOT
+   hook the components are therefore given by P and the bitmap together;
+   cc_compress with CC_F_ZROOT resolves both. Requires cc_init then cc_zroot
+   on the same n (else CC_EINVAL). Out-of-range endpoints set the status word
+   and are skipped. */
 int cc_hook(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
             uint32_t flags, void* stream);
 
 /* Pointer jumping (Algorithm 1 / 3 final loop): P_v <- root of v for every
    v. On the plain path the result is the min-ID labelling. With CC_F_ZROOT
-   it also records the smallest vertex whose root is z. */
+   (requires cc_init then cc_zroot on the same n, else CC_EINVAL) a tree that
+   holds a vertex of the membership bitmap is z's component: its members get
+   P_v = z, and the smallest member of z's component is recorded for
+   cc_canon. */
 int cc_compress(cc_ctx* ctx, uint64_t n, uint32_t* P, uint32_t flags, void* stream);
 
 /* Relabelling of the zero root's component (CC_F_ZROOT only): L_v == z is
