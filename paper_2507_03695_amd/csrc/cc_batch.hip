@@ -4,9 +4,11 @@
 // ticket per graph) and runs Algorithm 1 for that graph on its own: init, one
 // pass of hooking over the graph's entries, pointer jumping, separated by
 // workgroup barriers, so the launch needs no grid-wide synchronisation. A graph
-// whose parent array fits the workgroup's LDS is solved there (LDS
-// compare-and-swap; labels go to HBM once, coalesced); a larger graph keeps its
-// parent array in its label slice in HBM.
+// of at most 2^16 vertices keeps its parent array in the workgroup's LDS as
+// 16-bit entries (128 KB at n = 2^16; a link is a compare-and-swap on the
+// 32-bit word holding the entry); labels go to HBM once, coalesced. A larger
+// graph keeps its parent array in its label slice in HBM. Every thread keeps
+// kBatchEPT edge loads in flight.
 #include <algorithm>
 #include <cstring>
 #include <numeric>
@@ -17,26 +19,136 @@
 namespace ccm {
 
 typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
+// Pointers read from the descriptors are generic; marking them global keeps the
+// compiler from emitting flat accesses, which also count as LDS operations and
+// would make every LDS wait also wait for the edge loads in flight.
+#define CCM_GLOBAL __attribute__((address_space(1)))
+typedef const CCM_GLOBAL i32x2 gedge_t;
+typedef CCM_GLOBAL uint32_t glabel_t;
 
 constexpr int kBatchBlock = 1024;
 constexpr size_t kTicketBytes = 256;
 
-// Root of x with path splitting (each visited vertex takes its grandparent).
-__device__ __forceinline__ uint32_t bfind(uint32_t* P, uint32_t x, uint32_t px) {
+constexpr int kBatchEPT = 8;
+
+// Agent-scope store to a global word (see the store rule in cc_kernels.hip).
+__device__ __forceinline__ void gstore(glabel_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+
+// ---- 16-bit parent array in LDS (n <= 2^16) ------------------------------------------
+
+__device__ __forceinline__ uint32_t bfind16(uint16_t* P, uint32_t x, uint32_t px) {
     while (px != x) {
         const uint32_t gp = P[px];
         if (gp == px) return px;
-        P[x] = gp;
+        P[x] = (uint16_t)gp;
         x = px;
         px = gp;
     }
     return x;
 }
 
-// Algorithm 1 hooking of one entry on parent array P (LDS or HBM): the root of
-// greater ID is linked under the smaller; a failed CAS resumes from the value
-// it returns.
-__device__ __forceinline__ void blink(uint32_t* P, uint32_t u, uint32_t v) {
+// CAS of the 16-bit entry hi from hi (a root) to lo, on the 32-bit word that
+// holds it; a change of the other half only makes the word CAS retry. Returns
+// hi on success, else the entry's current (non-root) value.
+__device__ __forceinline__ uint32_t cas16(uint32_t* P32, uint32_t hi, uint32_t lo) {
+    uint32_t* w = &P32[hi >> 1];
+    const uint32_t sh = (hi & 1u) << 4;
+    uint32_t cur = *w;
+    while (true) {
+        const uint32_t h = (cur >> sh) & 0xFFFFu;
+        if (h != hi) return h;
+        const uint32_t des = (cur & ~(0xFFFFu << sh)) | (lo << sh);
+        const uint32_t prev = atomicCAS(w, cur, des);
+        if (prev == cur) return hi;
+        cur = prev;
+    }
+}
+
+// Hooking of one entry whose endpoints u, v have parents pu, pv (read earlier).
+__device__ __forceinline__ void blink16(uint16_t* P, uint32_t* P32, uint32_t u, uint32_t pu,
+                                        uint32_t v, uint32_t pv) {
+    if (pu == pv || pu == v || pv == u) return;
+    while (true) {
+        const uint32_t ru = bfind16(P, u, pu);
+        const uint32_t rv = bfind16(P, v, pv);
+        if (ru == rv) return;
+        const uint32_t hi = ru < rv ? rv : ru;
+        const uint32_t lo = ru < rv ? ru : rv;
+        const uint32_t old = cas16(P32, hi, lo);
+        if (old == hi) return;
+        u = hi; pu = old;
+        v = lo; pv = lo;
+    }
+}
+
+__device__ __forceinline__ void solve_graph16(uint32_t* P32, uint32_t n, gedge_t* E, int64_t m,
+                                              glabel_t* out, int* bad_flag) {
+    const int tid = threadIdx.x;
+    uint16_t* P = reinterpret_cast<uint16_t*>(P32);
+    for (uint32_t i = tid; 2 * i < n; i += kBatchBlock) P32[i] = (2 * i) | ((2 * i + 1) << 16);
+    __syncthreads();
+    bool bad = false;
+    // Software pipeline over rounds of kBatchEPT entries per thread: register k
+    // is reloaded with entry k of the next round right after entry k is linked,
+    // so the next round's loads are in flight while this round is processed.
+    constexpr int64_t kRound = (int64_t)kBatchBlock * kBatchEPT;
+    i32x2 x[kBatchEPT];
+#pragma unroll
+    for (int k = 0; k < kBatchEPT; ++k) {
+        const int64_t e = tid + (int64_t)k * kBatchBlock;
+        x[k] = __builtin_nontemporal_load(E + (e < m ? e : 0));
+    }
+    for (int64_t e0 = tid; e0 < m; e0 += kRound) {
+        // every entry's two parent reads first (LDS latency overlaps), then the links
+        uint32_t pu[kBatchEPT], pv[kBatchEPT];
+        bool live[kBatchEPT];
+#pragma unroll
+        for (int k = 0; k < kBatchEPT; ++k) {
+            const uint32_t u = (uint32_t)x[k].x, v = (uint32_t)x[k].y;
+            const bool in = e0 + (int64_t)k * kBatchBlock < m;
+            const bool ok = u < n && v < n;
+            bad |= in && !ok;
+            live[k] = in && ok && u != v;
+            pu[k] = live[k] ? P[u] : 0u;
+            pv[k] = live[k] ? P[v] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kBatchEPT; ++k) {
+            if (live[k]) blink16(P, P32, (uint32_t)x[k].x, pu[k], (uint32_t)x[k].y, pv[k]);
+            const int64_t e = e0 + kRound + (int64_t)k * kBatchBlock;
+            x[k] = __builtin_nontemporal_load(E + (e < m ? e : 0));
+        }
+    }
+    if (bad) *bad_flag = 1;
+    __syncthreads();
+    for (uint32_t v = tid; v < n; v += kBatchBlock) {
+        uint32_t r = P[v];
+        uint32_t q = P[r];
+        while (q != r) { r = q; q = P[r]; }
+        gstore(&out[v], r);
+    }
+}
+
+// ---- 32-bit parent array in the label slice (HBM) --------------------------------------
+
+// Root of x with path splitting (each visited vertex takes its grandparent).
+__device__ __forceinline__ uint32_t bfind(glabel_t* P, uint32_t x, uint32_t px) {
+    while (px != x) {
+        const uint32_t gp = P[px];
+        if (gp == px) return px;
+        gstore(&P[x], gp);
+        x = px;
+        px = gp;
+    }
+    return x;
+}
+
+// Algorithm 1 hooking of one entry: the root of greater ID is linked under the
+// smaller; a failed CAS resumes from the value it returns.
+__device__ __forceinline__ void blink(glabel_t* P, uint32_t u, uint32_t v) {
     uint32_t pu = P[u], pv = P[v];
     if (pu == pv || pu == v || pv == u) return;
     while (true) {
@@ -45,39 +157,51 @@ __device__ __forceinline__ void blink(uint32_t* P, uint32_t u, uint32_t v) {
         if (ru == rv) return;
         const uint32_t hi = ru < rv ? rv : ru;
         const uint32_t lo = ru < rv ? ru : rv;
-        const uint32_t old = atomicCAS(&P[hi], hi, lo);
-        if (old == hi) return;
+        uint32_t old = hi;
+        if (__hip_atomic_compare_exchange_strong(&P[hi], &old, lo, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            return;
         u = hi; pu = old;
         v = lo; pv = lo;
     }
 }
 
-__device__ __forceinline__ void solve_graph(uint32_t* P, uint32_t n, const i32x2* E, int64_t m,
-                                            uint32_t* out, int* bad_flag) {
+__device__ __forceinline__ void solve_graph_hbm(glabel_t* P, uint32_t n, gedge_t* E, int64_t m,
+                                                int* bad_flag) {
     const int tid = threadIdx.x;
-    for (uint32_t v = tid; v < n; v += kBatchBlock) P[v] = v;
+    for (uint32_t v = tid; v < n; v += kBatchBlock) gstore(&P[v], v);
+    __threadfence_block();
     __syncthreads();
     bool bad = false;
-    for (int64_t e = tid; e < m; e += kBatchBlock) {
-        const i32x2 uv = __builtin_nontemporal_load(E + e);
-        const uint32_t u = (uint32_t)uv.x, v = (uint32_t)uv.y;
-        if (u >= n || v >= n) { bad = true; continue; }
-        if (u != v) blink(P, u, v);
+    for (int64_t e0 = tid; e0 < m; e0 += (int64_t)kBatchBlock * kBatchEPT) {
+        i32x2 x[kBatchEPT];
+#pragma unroll
+        for (int k = 0; k < kBatchEPT; ++k) {
+            const int64_t e = e0 + (int64_t)k * kBatchBlock;
+            x[k] = __builtin_nontemporal_load(E + (e < m ? e : 0));
+        }
+#pragma unroll
+        for (int k = 0; k < kBatchEPT; ++k) {
+            if (e0 + (int64_t)k * kBatchBlock >= m) continue;
+            const uint32_t u = (uint32_t)x[k].x, v = (uint32_t)x[k].y;
+            if (u >= n || v >= n) { bad = true; continue; }
+            if (u != v) blink(P, u, v);
+        }
     }
     if (bad) *bad_flag = 1;
+    __threadfence_block();
     __syncthreads();
     for (uint32_t v = tid; v < n; v += kBatchBlock) {
         uint32_t r = P[v];
         uint32_t q = P[r];
         while (q != r) { r = q; q = P[r]; }
-        if (out) out[v] = r;
-        else P[v] = r;
+        gstore(&P[v], r);
     }
 }
 
 __global__ __launch_bounds__(kBatchBlock) void k_batch(uint32_t G, const GraphDesc* __restrict__ descs,
                                                        const uint32_t* __restrict__ order,
-                                                       uint32_t* ticket, uint32_t lds_cap) {
+                                                       uint32_t* ticket, uint32_t lds16_cap) {
     extern __shared__ uint32_t sP[];
     __shared__ uint32_t s_next;
     __shared__ int s_bad;
@@ -90,12 +214,11 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(uint32_t G, const GraphDe
         const uint32_t t = s_next;
         if (t >= G) break;
         const GraphDesc d = descs[order[t]];
-        const i32x2* E = reinterpret_cast<const i32x2*>(d.edges);
-        uint32_t* Lg = reinterpret_cast<uint32_t*>(d.L);
-        if (d.n <= lds_cap) solve_graph(sP, d.n, E, d.m, Lg, &s_bad);
-        else solve_graph(Lg, d.n, E, d.m, nullptr, &s_bad);
+        gedge_t* E = (gedge_t*)d.edges;
+        if (d.n <= lds16_cap) solve_graph16(sP, d.n, E, d.m, (glabel_t*)d.L, &s_bad);
+        else solve_graph_hbm((glabel_t*)d.L, d.n, E, d.m, &s_bad);
         __syncthreads();
-        if (threadIdx.x == 0) *d.status = s_bad ? CC_ERANGE : CC_OK;
+        if (threadIdx.x == 0) *(CCM_GLOBAL int32_t*)d.status = s_bad ? CC_ERANGE : CC_OK;
         __syncthreads();
     }
 }
@@ -110,13 +233,16 @@ static size_t batch_bytes(uint64_t G) {
     return kTicketBytes + ((4 * G + 63) & ~63ull) + sizeof(GraphDesc) * G;
 }
 
-static int lds_capacity(int device, size_t* bytes, uint32_t* entries) {
+// Dynamic LDS for the 16-bit parent array: 2^16 entries (128 KB), or what the
+// device allows beside the static words; graphs above that size use HBM.
+static int lds_capacity(int device, size_t* bytes, uint32_t* entries16) {
     int max_lds = 0;
     CCM_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
     size_t b = (size_t)max_lds > 1024 ? (size_t)max_lds - 1024 : 0;   // static words beside
+    b = std::min<size_t>(b, (size_t)1 << 17);
     b &= ~(size_t)255;
     *bytes = b;
-    *entries = (uint32_t)(b / sizeof(uint32_t));
+    *entries16 = (uint32_t)std::min<size_t>(b / sizeof(uint16_t), (size_t)1 << 16);
     return CC_OK;
 }
 

@@ -273,15 +273,17 @@ __global__ void k_t1_bases(const uint32_t* __restrict__ pre1, uint64_t nch1, int
     cbase[R] = cb;
 }
 
-// ---- 4a. level-2 chunk bounds -------------------------------------------------------------
+// ---- 4a. level-2 chunk descriptors ----------------------------------------------------------
 // Level-2 chunk t of bucket a covers virtual positions [t*kC2, min((t+1)*kC2, size_a)).
-// For every level-1 chunk c with a nonempty a-segment [pre[c], pre[c+1]), record c
-// as the first chunk (c0tab) of the level-2 chunks starting inside it and as the
-// last chunk (c1tab) of those ending inside it. One thread per (a, c).
+// Its descriptor (8 words at desc[8 g], g = cbase[a] + t) holds what k_t2_part
+// needs in one read: the first (c0) and last (c1) level-1 chunk it gathers
+// from, a | count << 8, t, and the 64-bit output offset base2[a] + t*kC2. One
+// thread per (a, c): it writes the fields of the chunks that start or end in
+// its segment [pre[c], pre[c+1]).
 __global__ __launch_bounds__(256) void k_t2_bounds(const uint32_t* __restrict__ pre1, uint64_t nch1,
                                                    int R, const uint32_t* __restrict__ cbase,
-                                                   uint32_t* __restrict__ c0tab,
-                                                   uint32_t* __restrict__ c1tab) {
+                                                   const uint64_t* __restrict__ base2,
+                                                   uint32_t* __restrict__ desc) {
     const uint64_t id = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     if (id >= (uint64_t)R * nch1) return;
     const uint64_t a = id / nch1, c = id % nch1;
@@ -291,8 +293,16 @@ __global__ __launch_bounds__(256) void k_t2_bounds(const uint32_t* __restrict__ 
     for (uint32_t t = p0 / kC2; t <= (p1 - 1) / kC2; ++t) {
         const uint32_t first = t * kC2;
         const uint32_t last = min(first + (uint32_t)kC2, size) - 1;
-        if (first >= p0 && first < p1) c0tab[cbase[a] + t] = (uint32_t)c;
-        if (last >= p0 && last < p1) c1tab[cbase[a] + t] = (uint32_t)c;
+        uint32_t* d = desc + (uint64_t)(cbase[a] + t) * 8;
+        if (first >= p0 && first < p1) {
+            const uint64_t o = base2[a] + first;
+            d[0] = (uint32_t)c;
+            d[2] = (uint32_t)a | ((last + 1 - first) << 8);
+            d[3] = t;
+            d[4] = (uint32_t)o;
+            d[5] = (uint32_t)(o >> 32);
+        }
+        if (last >= p0 && last < p1) d[1] = (uint32_t)c;
     }
 }
 
@@ -304,10 +314,8 @@ __global__ __launch_bounds__(kPartBlock) void k_t2_part(const uint32_t* __restri
                                                         const uint16_t* __restrict__ segT,
                                                         const uint32_t* __restrict__ pre1,
                                                         uint64_t nch1, int R,
-                                                        const uint64_t* __restrict__ base2,
                                                         const uint32_t* __restrict__ cbase,
-                                                        const uint32_t* __restrict__ c0tab,
-                                                        const uint32_t* __restrict__ c1tab,
+                                                        const uint32_t* __restrict__ desc,
                                                         u32x2* __restrict__ tmp2,
                                                         uint16_t* __restrict__ run2T,
                                                         uint64_t nch2) {
@@ -317,29 +325,19 @@ __global__ __launch_bounds__(kPartBlock) void k_t2_part(const uint32_t* __restri
     __shared__ uint32_t s_seg[kWin2];
     __shared__ uint32_t hist[kMaxSlices + 1];
     __shared__ uint32_t start[kMaxSlices + 1];
-    __shared__ uint32_t s_cb[kMaxSlices + 1];
-    __shared__ int s_a;
     const uint32_t g = blockIdx.x;
-    for (int i = threadIdx.x; i <= R; i += kPartBlock) s_cb[i] = cbase[i];
+    if (g >= cbase[R]) return;                  // the grid is an upper bound
+    const uint4 d0 = reinterpret_cast<const uint4*>(desc)[2 * (uint64_t)g];
+    const uint4 d1 = reinterpret_cast<const uint4*>(desc)[2 * (uint64_t)g + 1];
     for (int i = threadIdx.x; i <= kMaxSlices; i += kPartBlock) hist[i] = 0;
-    __syncthreads();
-    if (g >= s_cb[R]) return;
-    if (threadIdx.x == 0) {
-        int lo = 0, hi = R - 1;                 // last a with cbase[a] <= g
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) / 2;
-            if (s_cb[mid] <= g) lo = mid; else hi = mid - 1;
-        }
-        s_a = lo;
-    }
-    __syncthreads();
-    const int a = s_a;
-    const uint32_t t = g - s_cb[a];
+    const uint64_t c0 = d0.x, c1 = d0.y;
+    const int a = (int)(d0.z & 0xFFu);
+    const uint32_t cnt = d0.z >> 8;
+    const uint32_t t = d0.w;
+    const uint64_t obase = (uint64_t)d1.x | ((uint64_t)d1.y << 32);
     const uint32_t* pre = pre1 + (uint64_t)a * (nch1 + 1);
     const uint32_t vlo = t * (uint32_t)kC2;
-    const uint32_t vhi = min(vlo + (uint32_t)kC2, pre[nch1]);
-    const uint32_t cnt = vhi - vlo;
-    const uint64_t c0 = c0tab[g], c1 = c1tab[g];
+    const uint32_t vhi = vlo + cnt;
     u32x2 e[kPartEPT];
     for (uint64_t cw = c0; cw <= c1; cw += kWin2) {
         const uint32_t nw = (uint32_t)min<uint64_t>((uint64_t)kWin2, c1 - cw + 1);
@@ -389,7 +387,7 @@ __global__ __launch_bounds__(kPartBlock) void k_t2_part(const uint32_t* __restri
     for (int k = 0; k < kPartEPT; ++k)
         if (rank[k] != 0xFFFF) stage[start[e[k].y >> kSliceBits] + rank[k]] = e[k];
     __syncthreads();
-    u32x2* out = tmp2 + base2[a] + vlo;
+    u32x2* out = tmp2 + obase;
     for (uint32_t i = threadIdx.x; i < cnt; i += kPartBlock) out[i] = stage[i];
     for (int d = threadIdx.x; d <= R; d += kPartBlock) run2T[(uint64_t)d * nch2 + g] = (uint16_t)start[d];
 }
@@ -846,13 +844,13 @@ int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint3
     const uint64_t b_base2 = al(8 * (R + 1));
     const uint64_t b_cbase = al(4 * (R + 1));
     const uint64_t b_run2 = al(2 * pl.nch2_max * (R + 1));
-    const uint64_t b_ctab = al(4 * pl.nch2_max);
+    const uint64_t b_desc = al(32 * pl.nch2_max);
     const uint32_t nbg = (uint32_t)((R + kBPerBlock - 1) / kBPerBlock);
     const uint32_t nwg = (uint32_t)R * nbg;
     const uint64_t b_wgoff = al(8 * ((uint64_t)nwg + 1)), b_wgcnt = al(4 * (uint64_t)nwg);
     const uint64_t b_ipref = al(4 * ((uint64_t)nwg + 1));
     const uint64_t total = b_t1w + b_t1h + b_tmp2 + b_seg1 + b_cnt1 + b_pre1 + b_base2 +
-                           b_cbase + b_run2 + 2 * b_ctab + b_tsum + b_wgoff + b_wgcnt + b_ipref;
+                           b_cbase + b_run2 + b_desc + b_tsum + b_wgoff + b_wgcnt + b_ipref;
     int rc = grow(reinterpret_cast<void**>(&s->tiled.buf), &s->tiled.cap, total, stream);
     if (rc) return rc;
     char* q = s->tiled.buf;
@@ -865,8 +863,7 @@ int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint3
     uint64_t* base2 = reinterpret_cast<uint64_t*>(q); q += b_base2;
     uint32_t* cbase = reinterpret_cast<uint32_t*>(q); q += b_cbase;
     uint16_t* run2 = reinterpret_cast<uint16_t*>(q); q += b_run2;
-    uint32_t* c0tab = reinterpret_cast<uint32_t*>(q); q += b_ctab;
-    uint32_t* c1tab = reinterpret_cast<uint32_t*>(q); q += b_ctab;
+    uint32_t* desc = reinterpret_cast<uint32_t*>(q); q += b_desc;
     uint32_t* tsum = reinterpret_cast<uint32_t*>(q); q += b_tsum;
     uint64_t* wgoff = reinterpret_cast<uint64_t*>(q); q += b_wgoff;
     uint32_t* wgcnt = reinterpret_cast<uint32_t*>(q); q += b_wgcnt;
@@ -886,12 +883,11 @@ int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint3
     k_t1_bases<<<1, 64, 0, stream>>>(pre1, pl.nch1, R, base2, cbase);
     if ((rc1 = cohere(stream))) return rc1;
     const uint64_t pairs = (uint64_t)R * pl.nch1;
-    k_t2_bounds<<<(uint32_t)((pairs + 255) / 256), 256, 0, stream>>>(pre1, pl.nch1, R, cbase, c0tab,
-                                                                    c1tab);
+    k_t2_bounds<<<(uint32_t)((pairs + 255) / 256), 256, 0, stream>>>(pre1, pl.nch1, R, cbase, base2,
+                                                                    desc);
     if ((rc1 = cohere(stream))) return rc1;
     k_t2_part<<<(uint32_t)pl.nch2_max, kPartBlock, 0, stream>>>(t1w, t1h, segT, pre1, pl.nch1, R,
-                                                               base2, cbase, c0tab, c1tab, tmp2, run2,
-                                                               pl.nch2_max);
+                                                               cbase, desc, tmp2, run2, pl.nch2_max);
     if ((rc1 = cohere(stream))) return rc1;
     k_t3_regions<<<(uint32_t)R, 256, 0, stream>>>(run2, pl.nch2_max, R, base2, cbase, wgoff);
     if ((rc1 = cohere(stream))) return rc1;
