@@ -186,6 +186,42 @@ int cc_canon(cc_ctx* ctx, uint64_t n, uint32_t* L, void* stream);
 /* Synchronously read the context's current zero root (after cc_zroot). */
 int cc_get_zroot(cc_ctx* ctx, void* stream, uint32_t* zroot_out);
 
+/* ---- exchange between edge shares (Reducer emulation on one device) --------
+ * Sec. III (SiskinCC, high-level algorithm): every machine processes its share
+ * of the edges into its own global-size P, then sends the pairs (v, P_v) with
+ * P_v != v to a Reducer, which processes them like edges and ends with pointer
+ * jumping. Sec. IV (RobinCC): vertices whose parent is the zero root are sent
+ * as the ID alone (zero-converged vertices). Sec. V bounds the volume by
+ * min(|E|, (g-1)|V|) pairs for g machines.                                    */
+
+/* Export of one share's parent array after cc_compress (so P_v is v's root,
+   or the zero root z for its component when the share was solved with
+   CC_F_ZROOT). For every v < n with P_v != v: if P_v == zroot, v goes to
+   zero_ids; otherwise the pair (v, P_v) goes to pairs. zroot = 0xFFFFFFFF sends
+   every non-root as a pair. Both lists are written in increasing v.
+     P        device, n uint32, read
+     pairs    device, 2*pairs_cap uint32, written (may be NULL if pairs_cap == 0)
+     zero_ids device, zero_cap uint32, written (may be NULL if zero_cap == 0)
+     n_pairs, n_zero  host, the counts (always set on CC_OK and on CC_ENOMEM)
+   Synchronous on `stream`. CC_ENOMEM (nothing written) when a count exceeds its
+   capacity: call again with larger buffers. */
+int cc_export(cc_ctx* ctx, uint64_t n, const uint32_t* P, uint32_t zroot, uint32_t* pairs,
+              uint64_t pairs_cap, uint32_t* zero_ids, uint64_t zero_cap, uint64_t* n_pairs,
+              uint64_t* n_zero, void* stream);
+
+/* The Reducer side of zero-converged messages (Algorithm 4's received
+   (v, max_degree_vID) pairs): every ids[i] is connected to `target`.
+   Without CC_F_ZROOT: the pairs (ids[i], target) are hooked (Algorithm 1,
+   key = ID). With CC_F_ZROOT and target equal to the context's zero root
+   (cc_init then cc_zroot on the same n): each ids[i] is added to the membership
+   bitmap, which is the link to z that cc_compress resolves. With CC_F_ZROOT
+   and another target: hooked with the keys of Formula 1.
+     ids  device, count uint32 (each < n; out-of-range IDs set CC_ERANGE at
+          cc_sync and are skipped)
+     P    device, n uint32, updated in place */
+int cc_hook_ids(cc_ctx* ctx, uint64_t n, uint64_t count, const uint32_t* ids, uint32_t target,
+                uint32_t* P, uint32_t flags, void* stream);
+
 /* ---- many graphs in one launch ------------------------------------------- */
 
 /*

@@ -75,6 +75,9 @@ SIGNATURES = {
     "cc_compress": (_I32, [_P, _U64, _P, _U32, _P]),
     "cc_canon": (_I32, [_P, _U64, _P, _P]),
     "cc_get_zroot": (_I32, [_P, _P, ctypes.POINTER(_U32)]),
+    "cc_export": (_I32, [_P, _U64, _P, _U32, _P, _U64, _P, _U64, ctypes.POINTER(_U64),
+                         ctypes.POINTER(_U64), _P]),
+    "cc_hook_ids": (_I32, [_P, _U64, _U64, _P, _U32, _P, _U32, _P]),
     "cc_batch": (_I32, [_P, _U32, _P, _P, _P, _P, _P, _P]),
     "cc_serve_open": (_I32, [_P, ctypes.POINTER(_ServeOpts), ctypes.POINTER(_P)]),
     "cc_serve_submit": (_I32, [_P, _U64, _U64, _P, _P, _U32, ctypes.POINTER(_U64)]),
@@ -226,6 +229,34 @@ class Context:
 
     def canon(self, n, L, stream=None):
         _check(self.lib.cc_canon(self._h, n, _dptr(L, _ID), _stream(stream)), "cc_canon")
+
+    # exchange between edge shares
+    def export(self, P, n, zroot=0xFFFFFFFF, pairs=None, zero_ids=None, stream=None):
+        """cc_export: (n_pairs, n_zero). pairs: (cap, 2) and zero_ids: (cap,) device
+        tensors of P's dtype, or None to only count (raises CCError(CC_ENOMEM) when
+        a capacity is too small)."""
+        npairs, nzero = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        pcap = 0 if pairs is None else pairs.shape[0]
+        zcap = 0 if zero_ids is None else zero_ids.shape[0]
+        rc = self.lib.cc_export(self._h, n, _dptr(P, _ID), zroot, _dptr(pairs, _ID), pcap,
+                                _dptr(zero_ids, _ID), zcap, ctypes.byref(npairs),
+                                ctypes.byref(nzero), _stream(stream))
+        if rc != CC_OK and not (rc == CC_ENOMEM and pairs is None and zero_ids is None):
+            _check(rc, "cc_export")
+        return int(npairs.value), int(nzero.value)
+
+    def export_lists(self, P, n, zroot=0xFFFFFFFF, stream=None):
+        """Count, allocate and export: returns (pairs (k, 2), zero_ids (j,))."""
+        npairs, nzero = self.export(P, n, zroot, stream=stream)
+        pairs = torch.empty((npairs, 2), dtype=P.dtype, device=P.device)
+        zero = torch.empty(nzero, dtype=P.dtype, device=P.device)
+        self.export(P, n, zroot, pairs, zero, stream=stream)
+        return pairs, zero
+
+    def hook_ids(self, ids, target, n, P, flags=0, stream=None):
+        """cc_hook_ids: every ids[i] is connected to target."""
+        _check(self.lib.cc_hook_ids(self._h, n, ids.numel(), _dptr(ids, _ID), target, _dptr(P, _ID),
+                                    flags, _stream(stream)), "cc_hook_ids")
 
     # batch
     def batch(self, vtx_off, edge_off, edges, L=None, status=None, stream=None):

@@ -8,7 +8,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libccmi.so")
-SOURCES = ["cc_api.hip", "cc_kernels.hip", "cc_tiled.hip", "cc_batch.hip", "cc_serve.hip"]
+SOURCES = ["cc_api.hip", "cc_kernels.hip", "cc_tiled.hip", "cc_batch.hip", "cc_serve.hip",
+           "cc_exchange.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

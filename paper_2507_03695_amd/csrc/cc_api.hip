@@ -48,7 +48,7 @@ int slot_create(Slot* s, int device, uint32_t samples) {
     s->table = next_pow2(4ull * samples);
     if (s->table < 1024) s->table = 1024;
     CCM_HIP(hipSetDevice(device));
-    size_t bytes = sizeof(DevState) + (2ull * s->table + kGridCap) * sizeof(uint32_t);
+    size_t bytes = sizeof(DevState) + (2ull * s->table + 5ull * kGridCap + 2) * sizeof(uint32_t);
     char* base = nullptr;
     hipError_t e = hipMalloc(&base, bytes);
     if (e != hipSuccess) {
@@ -59,6 +59,7 @@ int slot_create(Slot* s, int device, uint32_t samples) {
     s->hkeys = reinterpret_cast<uint32_t*>(base + sizeof(DevState));
     s->hcounts = s->hkeys + s->table;
     s->bmin = s->hcounts + s->table;
+    s->xs = s->bmin + kGridCap;
     CCM_HIP(hipMemset(s->st, 0, sizeof(DevState)));
     e = hipHostMalloc(&s->host_status, sizeof(uint32_t), hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -302,6 +303,32 @@ extern "C" int cc_canon(cc_ctx* ctx, uint64_t n, uint32_t* L, void* stream) {
     if ((rc = set_dev(ctx))) return rc;
     if ((rc = cohere((hipStream_t)stream))) return rc;
     if ((rc = run_canon(&ctx->slot, n, L, (hipStream_t)stream))) return rc;
+    return cohere((hipStream_t)stream);
+}
+
+extern "C" int cc_export(cc_ctx* ctx, uint64_t n, const uint32_t* P, uint32_t zroot,
+                         uint32_t* pairs, uint64_t pairs_cap, uint32_t* zero_ids, uint64_t zero_cap,
+                         uint64_t* n_pairs, uint64_t* n_zero, void* stream) {
+    if (!ctx || !n_pairs || !n_zero) return fail(CC_EINVAL, "NULL argument");
+    *n_pairs = 0;
+    *n_zero = 0;
+    int rc = check_graph(n, 0, nullptr, P);
+    if (rc || n == 0) return rc;
+    if ((rc = set_dev(ctx))) return rc;
+    return run_export(&ctx->slot, n, P, zroot, pairs, pairs_cap, zero_ids, zero_cap, n_pairs, n_zero,
+                      (hipStream_t)stream);
+}
+
+extern "C" int cc_hook_ids(cc_ctx* ctx, uint64_t n, uint64_t count, const uint32_t* ids,
+                           uint32_t target, uint32_t* P, uint32_t flags, void* stream) {
+    if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    int rc = check_graph(n, count, ids, P);
+    if (rc || n == 0 || count == 0) return rc;
+    if (target >= n) return fail(CC_EINVAL, "target must be < n");
+    if ((rc = set_dev(ctx))) return rc;
+    if ((rc = cohere((hipStream_t)stream))) return rc;
+    if ((rc = run_hook_ids(&ctx->slot, n, count, ids, target, P, flags, (hipStream_t)stream)))
+        return rc;
     return cohere((hipStream_t)stream);
 }
 

@@ -62,6 +62,7 @@ struct Slot {
     uint32_t* hkeys = nullptr;     // device, zroot hash table keys   [table]
     uint32_t* hcounts = nullptr;   // device, zroot hash table counts [table]
     uint32_t* bmin = nullptr;      // device, per-block minima of compress [kGridCap]
+    uint32_t* xs = nullptr;        // device, export counts and offsets [4 * kGridCap + 2]
     uint32_t table = 0;            // power of two >= 4 * samples
     uint32_t samples = 0;          // K
     uint32_t* deg = nullptr;       // device, exact-degree counts (grown on demand)
@@ -91,6 +92,13 @@ int run_hook(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P
              uint32_t flags, hipStream_t stream);
 int run_compress(Slot* s, uint64_t n, uint32_t* P, uint32_t flags, hipStream_t stream);
 int run_canon(Slot* s, uint64_t n, uint32_t* L, hipStream_t stream);
+int run_hook_ids(Slot* s, uint64_t n, uint64_t count, const uint32_t* ids, uint32_t target,
+                 uint32_t* P, uint32_t flags, hipStream_t stream);
+
+// Exchange (cc_exchange.hip): synchronous export of a share's parent array.
+int run_export(Slot* s, uint64_t n, const uint32_t* P, uint32_t zroot, uint32_t* pairs,
+               uint64_t pairs_cap, uint32_t* zero_ids, uint64_t zero_cap, uint64_t* n_pairs,
+               uint64_t* n_zero, hipStream_t stream);
 int run_solve(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* L,
               uint32_t flags, uint32_t hint, hipStream_t stream);
 // Copy the status word to the host, clear it, wait for the stream; CC_OK/CC_ERANGE.

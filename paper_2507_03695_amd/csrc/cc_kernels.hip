@@ -575,6 +575,47 @@ int run_compress(Slot* s, uint64_t n, uint32_t* P, uint32_t flags, hipStream_t s
     return CC_OK;
 }
 
+// Every ids[i] is connected to target (the Reducer's zero-converged messages).
+// With a zero root equal to target the link is the bitmap mark itself.
+template <bool ZR, int SPLIT>
+__global__ __launch_bounds__(kBlock) void k_hook_ids(const uint32_t* __restrict__ ids,
+                                                     uint64_t count, uint32_t target, uint32_t n,
+                                                     uint32_t* P, uint32_t* zbits, DevState* st) {
+    const uint32_t z = ZR ? ld_agent(&st->zroot) : 0u;
+    const bool mark = ZR && target == z;
+    bool bad = false;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * kBlock) {
+        const uint32_t x = ids[i];
+        if (x >= n) { bad = true; continue; }
+        if (x == target) continue;
+        if (mark) {
+            zbit_set(zbits, x);
+            continue;
+        }
+        const uint32_t px = P[x], pt = P[target];
+        if (px == pt || px == target || pt == x) continue;
+        (void)link<ZR, SPLIT>(P, x, px, target, pt, z);
+    }
+    if (bad) atomicOr(&st->status, kStatusRange);
+}
+
+int run_hook_ids(Slot* s, uint64_t n, uint64_t count, const uint32_t* ids, uint32_t target,
+                 uint32_t* P, uint32_t flags, hipStream_t stream) {
+    const bool zr = flags & CC_F_ZROOT;
+    const bool split = !(flags & CC_F_NO_SPLIT);
+    if (zr && (!s->zr_ready || s->cur_n != n))
+        return fail(CC_EINVAL, "a CC_F_ZROOT id hook needs cc_init then cc_zroot on the same n");
+    const uint32_t g = grid_for(count, kBlock, kGridCap);
+    const uint32_t n32 = (uint32_t)n;
+    if (zr && split) k_hook_ids<true, 1><<<g, kBlock, 0, stream>>>(ids, count, target, n32, P, s->zbits, s->st);
+    else if (zr) k_hook_ids<true, 0><<<g, kBlock, 0, stream>>>(ids, count, target, n32, P, s->zbits, s->st);
+    else if (split) k_hook_ids<false, 1><<<g, kBlock, 0, stream>>>(ids, count, target, n32, P, s->zbits, s->st);
+    else k_hook_ids<false, 0><<<g, kBlock, 0, stream>>>(ids, count, target, n32, P, s->zbits, s->st);
+    CCM_HIP(hipGetLastError());
+    return CC_OK;
+}
+
 int run_canon(Slot* s, uint64_t n, uint32_t* L, hipStream_t stream) {
     k_canon<<<grid_for(n, kBlock, kGridCap), kBlock, 0, stream>>>(L, n, s->st);
     CCM_HIP(hipGetLastError());
