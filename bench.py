@@ -188,6 +188,67 @@ def bench_batch(cc, torch, reps=5):
             "speedup": round(t_loop / t_batch, 2), "identical_labels": same}
 
 
+def bench_reducer(cc, torch, ed, n, L_ref, g=16, reps=3):
+    """Reducer emulation (Sec. III / IV / V): the workload's entries split into g
+    shares by the first endpoint's vertex range, each solved into its own
+    global-size parent array with the global zero root, exported as (v, P_v)
+    pairs and zero-converged IDs, then merged by a Reducer. Reports the message
+    counts against Sec. V's min(|E|, (g-1)|V|) and the time of each phase."""
+    m = ed.shape[0]
+    u = ed[:, 0].to(torch.int64) & 0xFFFFFFFF
+    k = (u * g) // n
+    parts = [ed[k == s].contiguous() for s in range(g)]
+    del u, k
+    ctx = cc.Context()
+    stream = torch.cuda.current_stream()
+    Ps = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in range(g)]
+    L = torch.empty(n, dtype=torch.int32, device="cuda")
+    ctx.init(n, L)
+    ctx.zroot(ed, n)
+    z = ctx.get_zroot()
+    hint = cc.F_ZROOT | cc.F_ZROOT_HINT
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    res = []
+    for rep in range(reps):
+        e0, e1, e2, e3 = ev(), ev(), ev(), ev()
+        e0.record(stream)
+        for P, es in zip(Ps, parts):
+            ctx.init(n, P, stream)
+            ctx.zroot(es, n, flags=hint, zroot_hint=z, stream=stream)
+            ctx.push(es, n, P, stream=stream)
+            ctx.hook(es, n, P, flags=cc.F_ZROOT, stream=stream)
+            ctx.compress(n, P, flags=cc.F_ZROOT, stream=stream)
+        e1.record(stream)
+        exported = [ctx.export_lists(P, n, z, stream=stream) for P in Ps]
+        pairs = torch.cat([p for p, _ in exported])
+        zero = torch.cat([q for _, q in exported])
+        del exported
+        e2.record(stream)
+        ctx.init(n, L, stream)
+        ctx.zroot(pairs, n, flags=hint, zroot_hint=z, stream=stream)
+        ctx.hook(pairs, n, L, flags=cc.F_ZROOT, stream=stream)
+        ctx.hook_ids(zero, z, n, L, flags=cc.F_ZROOT, stream=stream)
+        ctx.compress(n, L, flags=cc.F_ZROOT, stream=stream)
+        ctx.canon(n, L, stream=stream)
+        e3.record(stream)
+        assert ctx.sync(stream) == cc.CC_OK
+        res.append((e0.elapsed_time(e1), e1.elapsed_time(e2), e2.elapsed_time(e3),
+                    int(pairs.shape[0]), int(zero.shape[0])))
+        del pairs, zero
+    same = bool(torch.equal(L, L_ref))
+    ctx.close()
+    med = lambda i: float(np.median([r[i] for r in res]))
+    npairs, nzero = res[-1][3], res[-1][4]
+    id_bytes = max(1, ((n - 1).bit_length() + 7) // 8)      # compact IDs of Sec. V
+    return {"shares": g, "zero_root": z,
+            "pairs": npairs, "zero_ids": nzero,
+            "bound_min_E_gm1V": min(m, (g - 1) * n),
+            "message_bytes": npairs * 2 * id_bytes + nzero * id_bytes,
+            "message_bytes_without_zero_ids": (npairs + nzero) * 2 * id_bytes,
+            "share_solves_ms": round(med(0), 3), "export_ms": round(med(1), 3),
+            "reducer_ms": round(med(2), 3), "identical_labels": same}
+
+
 def bench_serve(cc, torch, count=2000, seed=0x2507036950000005):
     """Poisson stream of requests (Pareto n in [2^10, 2^24]) through cc_serve at an
     offered load above a FIFO plain-path server's capacity; p50/p99 latency."""
@@ -282,6 +343,11 @@ def main():
                                      0 if flags else cc.F_ZROOT)
     assert torch.equal(L, L_o), "variants disagree"
     del L_o
+    reducer = None
+    if not args.no_extras:
+        t1 = time.time()
+        reducer = bench_reducer(cc, torch, ed, n, L)
+        log(f"reducer emulation done in {time.time() - t1:.1f} s")
 
     alg_bytes = 8 * m + 12 * n
     gteps = m / (ms * 1e-3) / 1e9
@@ -310,6 +376,8 @@ def main():
         other: {"ms_per_step": round(ms_o, 4), "hook_ms": round(hook_o, 4),
                 "GTEPS": round(m / (ms_o * 1e-3) / 1e9, 3)},
     }
+    if reducer is not None:
+        line["reducer"] = reducer
     del ed, L
     torch.cuda.empty_cache()
     if not args.no_extras:
