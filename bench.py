@@ -34,13 +34,14 @@ PEAK_HBM_GBS = 8000.0
 # each counter scaled by what it reads for a 4 GiB device copy. Keyed by
 # (workload, variant); valid only for the kernel sources they were taken on.
 TRAFFIC = {
-    ("rmat26", "zroot"): {"bytes": 51574618700,
-                          "src_sha256": "63ae5ad3ada1476fbb9bf395aeaed44aa1c320282b1a3c9e1a541eef355f201f"},
+    ("rmat26", "zroot"): {"bytes": 51695070147,
+                          "src_sha256": "934c3b7615ead04f24e0e70ef6f32b43ae621e238bbf59b90a9dcc5e999a2ff6"},
 }
 
 HOOK_KERNELS = {
     "zroot": "cc_hook step: k_hook<ZR> on 1/1024 of the entries, k_t1_part, k_t1_tsum, k_t1_scan, "
-             "k_t1_bases, k_t2_bounds, k_t2_part, k_t3_regions, k_t3_filter, k_t4_scan, k_t4_hook",
+             "k_t1_bases, k_t2_bounds, k_t2_part, k_t3_regions, k_t3_offsets, k_t3_filter, k_t4_scan, "
+             "k_t4_hook",
     "plain": "cc_hook step: k_hook<plain>",
 }
 

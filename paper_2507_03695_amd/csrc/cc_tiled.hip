@@ -256,21 +256,34 @@ __global__ __launch_bounds__(kScanBlock) void k_t1_scan(const uint32_t* __restri
 
 // ---- 3. bucket bases and level-2 chunk counts ---------------------------------------------
 // base2[a]: first entry of bucket a in the second buffer; cbase[a]: first level-2
-// chunk of bucket a; cbase[R] is the total. Single thread: R <= 256.
-__global__ void k_t1_bases(const uint32_t* __restrict__ pre1, uint64_t nch1, int R,
-                           uint64_t* __restrict__ base2, uint32_t* __restrict__ cbase) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    uint64_t b = 0;
-    uint32_t cb = 0;
-    for (int a = 0; a < R; ++a) {
-        const uint32_t size = pre1[(uint64_t)a * (nch1 + 1) + nch1];
-        base2[a] = b;
-        cbase[a] = cb;
-        b += size;
-        cb += (size + kC2 - 1) / kC2;
+// chunk of bucket a; cbase[R] is the total.
+__global__ __launch_bounds__(256) void k_t1_bases(const uint32_t* __restrict__ pre1, uint64_t nch1,
+                                                  int R, uint64_t* __restrict__ base2,
+                                                  uint32_t* __restrict__ cbase) {
+    // one thread per slice (R <= 256): sizes, then block-wide exclusive prefixes
+    __shared__ uint64_t s_b[256];
+    __shared__ uint32_t s_c[256];
+    const int a = threadIdx.x;
+    const uint32_t size = a < R ? pre1[(uint64_t)a * (nch1 + 1) + nch1] : 0u;
+    s_b[a] = size;
+    s_c[a] = (size + kC2 - 1) / kC2;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {          // inclusive Hillis-Steele scan
+        const uint64_t xb = a >= off ? s_b[a - off] : 0ull;
+        const uint32_t xc = a >= off ? s_c[a - off] : 0u;
+        __syncthreads();
+        s_b[a] += xb;
+        s_c[a] += xc;
+        __syncthreads();
     }
-    base2[R] = b;
-    cbase[R] = cb;
+    if (a < R) {
+        base2[a] = s_b[a] - size;
+        cbase[a] = s_c[a] - (size + kC2 - 1) / kC2;
+    }
+    if (a == R - 1) {
+        base2[R] = s_b[a];
+        cbase[R] = s_c[a];
+    }
 }
 
 // ---- 4a. level-2 chunk descriptors ----------------------------------------------------------
@@ -470,36 +483,46 @@ __device__ __forceinline__ void t3_flush(const u32x2* wq, uint32_t qn, int lane,
     __builtin_amdgcn_wave_barrier();
 }
 
-constexpr int kBPerBlock = 4;    // second-endpoint slices handled by one workgroup
+constexpr int kBPerBlock = 2;    // second-endpoint slices handled by one workgroup
 
 // Survivor regions: workgroup (a, bg) of the filter reads exactly the entries of
-// tiles (a, b), b in [4 bg, 4 bg + 4); its kept entries go to a region of that
+// tiles (a, b), b in [2 bg, 2 bg + 2); its kept entries go to a region of that
 // size inside [base2[a], base2[a+1]) of the survivor buffer; regions are
 // consecutive, so wgoff[w + 1] ends region w (wgoff has R * nbg + 1 entries).
 // One block per a.
 __global__ __launch_bounds__(256) void k_t3_regions(const uint16_t* __restrict__ run2T,
                                                     uint64_t nch2, int R,
-                                                    const uint64_t* __restrict__ base2,
                                                     const uint32_t* __restrict__ cbase,
-                                                    uint64_t* __restrict__ wgoff) {
+                                                    uint32_t* __restrict__ wgsize) {
+    // one block per (a, bg): the group's entries summed over bucket a's chunks
     __shared__ uint32_t ws[4];
-    const int a = blockIdx.x;
     const int nbg = (R + kBPerBlock - 1) / kBPerBlock;
+    const int a = blockIdx.x / nbg, bg = blockIdx.x % nbg;
+    const int blo = bg * kBPerBlock, bhi = min(R, blo + kBPerBlock);
     const uint32_t g0 = cbase[a], g1 = cbase[a + 1];
+    uint32_t t = 0;
+    for (uint32_t g = g0 + threadIdx.x; g < g1; g += 256)
+        t += (uint32_t)run2T[(uint64_t)bhi * nch2 + g] - (uint32_t)run2T[(uint64_t)blo * nch2 + g];
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) wgsize[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+// Per slice a, the regions' offsets: base2[a] plus the sizes of the groups
+// before bg. One thread per a.
+__global__ __launch_bounds__(256) void k_t3_offsets(const uint32_t* __restrict__ wgsize, int R,
+                                                    const uint64_t* __restrict__ base2,
+                                                    uint64_t* __restrict__ wgoff) {
+    const int a = blockIdx.x * 256 + threadIdx.x;
+    if (a >= R) return;
+    const int nbg = (R + kBPerBlock - 1) / kBPerBlock;
     uint64_t run = base2[a];
     for (int bg = 0; bg < nbg; ++bg) {
-        const int blo = bg * kBPerBlock, bhi = min(R, blo + kBPerBlock);
-        uint32_t t = 0;
-        for (uint32_t g = g0 + threadIdx.x; g < g1; g += 256)
-            t += (uint32_t)run2T[(uint64_t)bhi * nch2 + g] - (uint32_t)run2T[(uint64_t)blo * nch2 + g];
-        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-        __syncthreads();                       // ws of the previous group consumed
-        if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = t;
-        __syncthreads();
-        if (threadIdx.x == 0) wgoff[(uint64_t)a * nbg + bg] = run;
-        run += (uint64_t)ws[0] + ws[1] + ws[2] + ws[3];
+        wgoff[(uint64_t)a * nbg + bg] = run;
+        run += wgsize[(uint64_t)a * nbg + bg];
     }
-    if (a == R - 1 && threadIdx.x == 0) wgoff[(uint64_t)R * nbg] = run;   // end of the last region
+    if (a == R - 1) wgoff[(uint64_t)R * nbg] = run;   // end of the last region
 }
 
 // Run holding index j0 of the window (last t < nw with s_pre[t] <= j0), found
@@ -880,7 +903,7 @@ int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint3
     if ((rc1 = cohere(stream))) return rc1;
     k_t1_scan<<<(uint32_t)R * ntile, kScanBlock, 0, stream>>>(cnt1, pl.nch1, ntile, tsum, pre1);
     if ((rc1 = cohere(stream))) return rc1;
-    k_t1_bases<<<1, 64, 0, stream>>>(pre1, pl.nch1, R, base2, cbase);
+    k_t1_bases<<<1, 256, 0, stream>>>(pre1, pl.nch1, R, base2, cbase);
     if ((rc1 = cohere(stream))) return rc1;
     const uint64_t pairs = (uint64_t)R * pl.nch1;
     k_t2_bounds<<<(uint32_t)((pairs + 255) / 256), 256, 0, stream>>>(pre1, pl.nch1, R, cbase, base2,
@@ -889,7 +912,9 @@ int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint3
     k_t2_part<<<(uint32_t)pl.nch2_max, kPartBlock, 0, stream>>>(t1w, t1h, segT, pre1, pl.nch1, R,
                                                                cbase, desc, tmp2, run2, pl.nch2_max);
     if ((rc1 = cohere(stream))) return rc1;
-    k_t3_regions<<<(uint32_t)R, 256, 0, stream>>>(run2, pl.nch2_max, R, base2, cbase, wgoff);
+    k_t3_regions<<<nwg, 256, 0, stream>>>(run2, pl.nch2_max, R, cbase, wgcnt);
+    if ((rc1 = cohere(stream))) return rc1;
+    k_t3_offsets<<<(uint32_t)((R + 255) / 256), 256, 0, stream>>>(wgcnt, R, base2, wgoff);
     if ((rc1 = cohere(stream))) return rc1;
     k_t3_filter<<<nwg, kHook3Block, 0, stream>>>(tmp2, run2, pl.nch2_max, R, base2, cbase,
                                                 s->zbits, (n + 31) / 32, t1w, t1h, wgoff, wgcnt,
