@@ -55,6 +55,8 @@ def _load():
         lib.oracle_zroot.argtypes = [u64, u64, p, u64, p]; lib.oracle_zroot.restype = i32
         lib.oracle_push.argtypes = [u64, u64, p, u64, u32, p]; lib.oracle_push.restype = i32
         lib.oracle_jt_seq.argtypes = [u64, u64, p, u64, i32, p]; lib.oracle_jt_seq.restype = i32
+        lib.oracle_siskin_log.argtypes = [u64, u64, p, p, u64, ctypes.POINTER(u64)]
+        lib.oracle_siskin_log.restype = i32
         lib.oracle_rf_jt.argtypes = [u64, u64, p, u32, p]; lib.oracle_rf_jt.restype = i32
         lib.oracle_check_forest.argtypes = [u64, p, i32, u32, p]
         lib.oracle_check_forest.restype = ctypes.c_int64
@@ -132,6 +134,18 @@ def jt_seq(n: int, edges, steps: int | None = None, jump: bool = False) -> np.nd
     if rc != OK:
         raise OracleError(rc)
     return P
+
+
+def siskin_log(n: int, edges) -> np.ndarray:
+    """Algorithm 2's messages on one thread: (child, new parent) per link, in order."""
+    e = _edges(edges)
+    cap = max(n, 1)
+    log = np.empty((cap, 2), np.uint32)
+    k = ctypes.c_uint64(0)
+    rc = _load().oracle_siskin_log(n, len(e), _p(e), _p(log), cap, ctypes.byref(k))
+    if rc != OK:
+        raise OracleError(rc)
+    return log[: k.value].copy()
 
 
 def rf_jt(n: int, edges, zmax: int) -> np.ndarray:

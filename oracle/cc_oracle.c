@@ -27,6 +27,9 @@
  *                     point at it.
  *   - oracle_jt_seq:  Algorithm 1 run sequentially over a prefix of the
  *                     entries, for the worked example of Fig. 1.
+ *   - oracle_siskin_log: the messages one SiskinCC machine sends (Sec. III,
+ *                     Algorithm 2): Algorithm 1 on one thread, recording
+ *                     (child, new parent) at every link.
  *   - oracle_rf_jt:   Algorithm 3 with the root function R (Formulas 1-2),
  *                     run sequentially, returning the final P (root values).
  *   - oracle_check_forest: structural checks on a parent array taken after
@@ -199,6 +202,39 @@ int oracle_jt_seq(uint64_t n, uint64_t m, const uint32_t* edges, uint64_t steps,
         }
     }
     return OR_OK;
+}
+
+/*
+ * SiskinCC's update messages (Sec. III, Algorithm 2), one machine, one thread.
+ * Each entry is processed as in Algorithm 1; whenever the root with the greater
+ * ID is given the smaller root as its parent, the pair (that root, its new
+ * parent) is a message to the Reducer, recorded in processing order. Non-roots
+ * are never changed, so every vertex appears as a child at most once and the
+ * messages number n minus the number of components of the processed entries.
+ * Writes min(count, cap) pairs to log (2 uint32 each) and the full count to
+ * *count; returns -3 when count > cap.
+ */
+int oracle_siskin_log(uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* log, uint64_t cap,
+                      uint64_t* count) {
+    if (n > 0xFFFFFFFFull) return OR_EINVAL;
+    uint32_t* P = (uint32_t*)malloc((n ? n : 1) * sizeof(uint32_t));
+    if (!P) return OR_ENOMEM;
+    for (uint64_t v = 0; v < n; ++v) P[v] = (uint32_t)v;
+    uint64_t k = 0;
+    for (uint64_t i = 0; i < m; ++i) {
+        uint32_t u = edges[2 * i], v = edges[2 * i + 1];
+        if (u >= n || v >= n) { free(P); *count = k; return OR_ERANGE; }
+        while (P[u] != u) u = P[u];
+        while (P[v] != v) v = P[v];
+        if (u == v) continue;
+        const uint32_t child = u < v ? v : u, parent = u < v ? u : v;
+        P[child] = parent;
+        if (k < cap) { log[2 * k] = child; log[2 * k + 1] = parent; }
+        ++k;
+    }
+    free(P);
+    *count = k;
+    return k > cap ? OR_ENOMEM : OR_OK;
 }
 
 /*

@@ -209,6 +209,46 @@ def test_jt_seq_reaches_min_labels():
         np.testing.assert_array_equal(oracle.jt_seq(n, e, jump=True), closure_labels(n, e.tolist()))
 
 
+# ---- SiskinCC's update messages (Sec. III, Algorithm 2) -----------------------
+
+def test_siskin_log_fig1():
+    """The two Fig. 1 steps change P_3 to 2, then P_2 to 1: each change is one
+    message (vertex, new parent), read off the printed parent arrays."""
+    n, edges, states = _read_fig1()
+    want = []
+    for a, b in zip(states, states[1:]):
+        changed = [v for v in range(n) if a[1 + v] != b[1 + v]]
+        assert len(changed) == 1
+        want.append([changed[0], b[1 + changed[0]]])
+    got = oracle.siskin_log(n, np.array(edges, np.uint32))
+    np.testing.assert_array_equal(got, np.array(want, np.uint32))
+
+
+def test_siskin_log_against_closure():
+    """Every vertex but its component's lowest ID is a child exactly once (non-roots
+    are never updated again), parents have smaller IDs and share the child's
+    component, and the messages taken as edges connect exactly what the graph does."""
+    rng = np.random.default_rng(31)
+    for _ in range(300):
+        n = int(rng.integers(1, 40))
+        e = rng.integers(0, n, size=(int(rng.integers(0, 2 * n)), 2)).astype(np.uint32)
+        L = closure_labels(n, e.tolist())
+        log = oracle.siskin_log(n, e)
+        kids = sorted(log[:, 0].tolist())
+        assert kids == [v for v in range(n) if L[v] != v]
+        assert np.all(log[:, 1] < log[:, 0])
+        assert np.array_equal(L[log[:, 0]], L[log[:, 1]])
+        np.testing.assert_array_equal(closure_labels(n, log.tolist()), L)
+
+
+def test_siskin_log_capacity_and_range():
+    e = np.array([[0, 1], [1, 2], [3, 4]], np.uint32)
+    assert oracle.siskin_log(5, e).tolist() == [[1, 0], [2, 0], [4, 3]]
+    with pytest.raises(oracle.OracleError) as ei:
+        oracle.siskin_log(4, e)
+    assert ei.value.code == oracle.ERANGE
+
+
 # ---- Algorithm 3 with the root function R (Formulas 1-2) ----------------------
 
 def test_root_function_jt_closed_form():
