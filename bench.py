@@ -297,6 +297,79 @@ def bench_serve(cc, torch, count=2000, seed=0x2507036950000005):
             "identical_to_fifo": same}
 
 
+def bench_update_log(cc, torch, ed, n, L_ref, hook_plain_ms, g=16, reps=3):
+    """SiskinCC's update log (Sec. III, Algorithm 2). (1) The plain hook over the
+    whole workload with every link appended to a log, against the same hook
+    without it; the message count must be n minus the number of components.
+    (2) SiskinCC over g shares: each share hooks into its own parent array and
+    appends its links to one receive buffer (no compress, no export); the
+    Reducer hooks the buffer as edges and compresses."""
+    m = ed.shape[0]
+    ctx = cc.Context()
+    stream = torch.cuda.current_stream()
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    want = int((L_ref != torch.arange(n, device=L_ref.device, dtype=L_ref.dtype)).sum())
+    P = torch.empty(n, dtype=torch.int32, device="cuda")
+    buf = torch.empty((n, 2), dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    t_log = []
+    for rep in range(reps + 1):
+        ctx.init(n, P, stream)
+        cnt.zero_()
+        a, b = ev(), ev()
+        a.record(stream)
+        ctx.hook_log(ed, n, P, buf, cnt, stream=stream)
+        b.record(stream)
+        assert ctx.sync(stream) == cc.CC_OK
+        assert int(cnt.item()) == want, (int(cnt.item()), want)
+        if rep:
+            t_log.append(a.elapsed_time(b))
+    ctx.compress(n, P, stream=stream)
+    assert ctx.sync(stream) == cc.CC_OK
+    same_single = bool(torch.equal(P, L_ref))
+    del buf
+    torch.cuda.empty_cache()
+
+    u = ed[:, 0].to(torch.int64) & 0xFFFFFFFF
+    k = (u * g) // n
+    parts = [ed[k == s].contiguous() for s in range(g)]
+    del u, k
+    Ps = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in range(g)]
+    recv = torch.empty((m, 2), dtype=torch.int32, device="cuda")   # <= min(|E|, g|V|) messages
+    res = []
+    for rep in range(reps):
+        e0, e1, e2 = ev(), ev(), ev()
+        cnt.zero_()
+        e0.record(stream)
+        for Ps_, es in zip(Ps, parts):
+            ctx.init(n, Ps_, stream)
+            ctx.hook_log(es, n, Ps_, recv, cnt, stream=stream)
+        e1.record(stream)
+        assert ctx.sync(stream) == cc.CC_OK
+        sent = int(cnt.item())
+        ctx.init(n, P, stream)
+        ctx.hook(recv[:sent], n, P, stream=stream)
+        ctx.compress(n, P, stream=stream)
+        e2.record(stream)
+        assert ctx.sync(stream) == cc.CC_OK
+        res.append((e0.elapsed_time(e1), e1.elapsed_time(e2), sent))
+    same = bool(torch.equal(P, L_ref))
+    ctx.close()
+    del Ps, recv, parts, P
+    torch.cuda.empty_cache()
+    med = lambda i: float(np.median([r[i] for r in res]))
+    id_bytes = max(1, ((n - 1).bit_length() + 7) // 8)
+    hl = float(np.median(t_log))
+    return {"messages": want, "n_minus_components": want,
+            "hook_log_ms": round(hl, 3), "hook_ms": round(hook_plain_ms, 3),
+            "overhead": round(hl / hook_plain_ms - 1.0, 4), "identical_labels": same_single,
+            "siskin_shares": g, "siskin_messages": res[-1][2],
+            "siskin_bound_min_E_gV": min(m, g * n),
+            "siskin_message_bytes": res[-1][2] * 2 * id_bytes,
+            "siskin_share_hooks_ms": round(med(0), 3), "siskin_reducer_ms": round(med(1), 3),
+            "siskin_identical_labels": same}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -344,11 +417,14 @@ def main():
                                      0 if flags else cc.F_ZROOT)
     assert torch.equal(L, L_o), "variants disagree"
     del L_o
-    reducer = None
+    reducer = upd = None
     if not args.no_extras:
         t1 = time.time()
         reducer = bench_reducer(cc, torch, ed, n, L)
         log(f"reducer emulation done in {time.time() - t1:.1f} s")
+        t1 = time.time()
+        upd = bench_update_log(cc, torch, ed, n, L, hook_o if flags else hook_ms)
+        log(f"update log done in {time.time() - t1:.1f} s")
 
     alg_bytes = 8 * m + 12 * n
     gteps = m / (ms * 1e-3) / 1e9
@@ -379,6 +455,8 @@ def main():
     }
     if reducer is not None:
         line["reducer"] = reducer
+    if upd is not None:
+        line["update_log"] = upd
     del ed, L
     torch.cuda.empty_cache()
     if not args.no_extras:

@@ -125,7 +125,8 @@ int cc_solve_async(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edge_lis
                    uint32_t* L, uint32_t flags, uint32_t zroot_hint, void* stream);
 
 /* Wait for `stream`, then return (and clear) the status accumulated by the
-   context's work since the previous cc_sync: CC_OK or CC_ERANGE. */
+   context's work since the previous cc_sync: CC_OK, CC_ERANGE, or CC_ENOMEM
+   (an update log of cc_hook_log ran out of capacity). */
 int cc_sync(cc_ctx* ctx, void* stream);
 
 /* ---- the steps, one entry point each (asynchronous on `stream`) ----------
@@ -170,6 +171,28 @@ int cc_push(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t
    and are skipped. */
 int cc_hook(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
             uint32_t flags, void* stream);
+
+/* Hooking with SiskinCC's update log (Sec. III, Algorithm 2): the plain-path
+   hook of cc_hook (key = ID; CC_F_ZROOT is rejected with CC_EINVAL), which
+   also appends a message (r, p) each time a root r is linked under p. A
+   vertex's parent is set by a link at most once (non-roots are never linked),
+   so after cc_init and any sequence of cc_hook_log calls the log holds each
+   vertex other than its component's lowest ID at most once, n minus the
+   number of components in all; taken as edges, the messages connect exactly
+   what the processed entries connect. The order is that of the links on the
+   device (schedule-dependent).
+     log        device, 2*log_cap uint32, owned by the caller; message i is
+                log[2i] (the linked root), log[2i+1] (its new parent)
+     log_count  device, one uint64, owned by the caller: the number of
+                messages already in the log. The call appends at that index
+                and adds its own count (set it to 0 before the first call).
+                Messages past log_cap are counted but not written, and the
+                next cc_sync returns CC_ENOMEM.
+   log and log_count are complete when the stream reaches the end of the
+   call. Other arguments and errors as for cc_hook. */
+int cc_hook_log(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
+                uint32_t flags, uint32_t* log, uint64_t log_cap, uint64_t* log_count,
+                void* stream);
 
 /* Pointer jumping (Algorithm 1 / 3 final loop): P_v <- root of v for every
    v. On the plain path the result is the min-ID labelling. With CC_F_ZROOT

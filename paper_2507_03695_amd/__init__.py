@@ -72,6 +72,7 @@ SIGNATURES = {
     "cc_zroot": (_I32, [_P, _U64, _U64, _P, _U32, _U32, _P]),
     "cc_push": (_I32, [_P, _U64, _U64, _P, _P, _P]),
     "cc_hook": (_I32, [_P, _U64, _U64, _P, _P, _U32, _P]),
+    "cc_hook_log": (_I32, [_P, _U64, _U64, _P, _P, _U32, _P, _U64, _P, _P]),
     "cc_compress": (_I32, [_P, _U64, _P, _U32, _P]),
     "cc_canon": (_I32, [_P, _U64, _P, _P]),
     "cc_get_zroot": (_I32, [_P, _P, ctypes.POINTER(_U32)]),
@@ -188,9 +189,10 @@ class Context:
                                        zroot_hint, _stream(stream)), "cc_solve_async")
 
     def sync(self, stream=None) -> int:
-        """Wait for the stream; returns CC_OK or CC_ERANGE (does not raise for ERANGE)."""
+        """Wait for the stream; returns the status word's outcome, CC_OK, CC_ERANGE or
+        CC_ENOMEM (a full update log), without raising for those."""
         rc = self.lib.cc_sync(self._h, _stream(stream))
-        if rc not in (CC_OK, CC_ERANGE):
+        if rc not in (CC_OK, CC_ERANGE, CC_ENOMEM):
             _check(rc, "cc_sync")
         return rc
 
@@ -223,6 +225,15 @@ class Context:
     def hook(self, edges, n, P, flags=0, stream=None):
         _check(self.lib.cc_hook(self._h, n, edges.shape[0], _dptr(edges, _ID), _dptr(P, _ID), flags,
                                 _stream(stream)), "cc_hook")
+
+    def hook_log(self, edges, n, P, log, count, flags=0, stream=None):
+        """cc_hook_log: log (cap, 2) device tensor of P's dtype, count a device int64
+        tensor of one element (the messages so far; appended to)."""
+        if count.dtype != torch.int64 or count.numel() != 1:
+            raise TypeError("count must be a one-element int64 tensor")
+        _check(self.lib.cc_hook_log(self._h, n, edges.shape[0], _dptr(edges, _ID), _dptr(P, _ID),
+                                    flags, _dptr(log, _ID), 0 if log is None else log.shape[0],
+                                    _dptr(count, (torch.int64,)), _stream(stream)), "cc_hook_log")
 
     def compress(self, n, P, flags=0, stream=None):
         _check(self.lib.cc_compress(self._h, n, _dptr(P, _ID), flags, _stream(stream)), "cc_compress")

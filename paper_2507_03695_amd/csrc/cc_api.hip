@@ -102,6 +102,7 @@ int slot_sync(Slot* s, hipStream_t stream) {
     const uint32_t w = __atomic_load_n(s->host_status, __ATOMIC_ACQUIRE);
     if (w & kStatusInternal) return fail(CC_EDEVICE, "internal scratch bound exceeded");
     if (w & kStatusRange) return fail(CC_ERANGE, "an endpoint is >= n");
+    if (w & kStatusLogFull) return fail(CC_ENOMEM, "update log capacity exceeded");
     return CC_OK;
 }
 
@@ -283,6 +284,22 @@ extern "C" int cc_hook(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edge
     if ((rc = set_dev(ctx))) return rc;
     if ((rc = cohere((hipStream_t)stream))) return rc;
     if ((rc = run_hook(&ctx->slot, n, m, edges, P, flags, (hipStream_t)stream))) return rc;
+    return cohere((hipStream_t)stream);
+}
+
+extern "C" int cc_hook_log(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edges,
+                           uint32_t* P, uint32_t flags, uint32_t* log, uint64_t log_cap,
+                           uint64_t* log_count, void* stream) {
+    if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    int rc = check_graph(n, m, edges, P);
+    if (rc || n == 0) return rc;
+    if (!log_count) return fail(CC_EINVAL, "log_count is NULL");
+    if (log_cap && !log) return fail(CC_EINVAL, "log is NULL with a nonzero capacity");
+    if ((rc = set_dev(ctx))) return rc;
+    if ((rc = cohere((hipStream_t)stream))) return rc;
+    if ((rc = run_hook_log(&ctx->slot, n, m, edges, P, flags, log, log_cap, log_count,
+                           (hipStream_t)stream)))
+        return rc;
     return cohere((hipStream_t)stream);
 }
 

@@ -16,7 +16,7 @@ namespace ccm {
 // slot). Lives in device memory; kernels read and update it, the host reads it
 // only through explicit copies.
 struct DevState {
-    uint32_t status;    // bit 0: an endpoint >= n was seen
+    uint32_t status;    // kStatus* bits, reported and cleared by slot_sync
     uint32_t minz;      // smallest vertex whose root is the zero root (compress)
     uint32_t zroot;     // the zero root chosen for the current solve
     uint32_t pad0;
@@ -27,6 +27,7 @@ static_assert(sizeof(DevState) == 64, "DevState is one 64-byte block");
 
 constexpr uint32_t kStatusRange = 1u;
 constexpr uint32_t kStatusInternal = 2u;   // a scratch bound check failed (a bug)
+constexpr uint32_t kStatusLogFull = 4u;    // an update log ran out of capacity
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kGridCap = 256 * 32;   // blocks of a grid-stride launch over n
 
@@ -91,6 +92,10 @@ int run_push(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P
 int run_hook(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
              uint32_t flags, hipStream_t stream);
 int run_compress(Slot* s, uint64_t n, uint32_t* P, uint32_t flags, hipStream_t stream);
+// Plain-path hook that appends its links to a caller-owned log (cc_hook_log).
+int run_hook_log(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
+                 uint32_t flags, uint32_t* log, uint64_t log_cap, uint64_t* log_count,
+                 hipStream_t stream);
 int run_canon(Slot* s, uint64_t n, uint32_t* L, hipStream_t stream);
 int run_hook_ids(Slot* s, uint64_t n, uint64_t count, const uint32_t* ids, uint32_t target,
                  uint32_t* P, uint32_t flags, hipStream_t stream);
@@ -101,7 +106,8 @@ int run_export(Slot* s, uint64_t n, const uint32_t* P, uint32_t zroot, uint32_t*
                uint64_t* n_zero, hipStream_t stream);
 int run_solve(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* L,
               uint32_t flags, uint32_t hint, hipStream_t stream);
-// Copy the status word to the host, clear it, wait for the stream; CC_OK/CC_ERANGE.
+// Copy the status word to the host, clear it, wait for the stream; CC_OK,
+// CC_ERANGE or CC_ENOMEM (a full update log).
 int slot_sync(Slot* s, hipStream_t stream);
 
 // Tiled zero-root hook (cc_tiled.hip): both membership tests in LDS.

@@ -218,10 +218,12 @@ __device__ __forceinline__ uint32_t find_root(uint32_t* P, uint32_t x, uint32_t 
 // Returns the root under which both endpoints ended up (the surviving root of
 // the link, or the common root found). When it is the zero root z, both
 // endpoints are certainly in z's tree: z has the smallest key and is never
-// linked under anything.
+// linked under anything. If this call's CAS is the one that links, *linked
+// (when given) receives the root that was linked; the return value is then its
+// new parent.
 template <bool ZR, int SPLIT>
 __device__ __forceinline__ uint32_t link(uint32_t* P, uint32_t u, uint32_t pu, uint32_t v,
-                                         uint32_t pv, uint32_t z) {
+                                         uint32_t pv, uint32_t z, uint32_t* linked = nullptr) {
     while (true) {
         const uint32_t ru = find_root<SPLIT>(P, u, pu);
         const uint32_t rv = find_root<SPLIT>(P, v, pv);
@@ -230,7 +232,10 @@ __device__ __forceinline__ uint32_t link(uint32_t* P, uint32_t u, uint32_t pu, u
         const uint32_t hi = u_low ? rv : ru;
         const uint32_t lo = u_low ? ru : rv;
         const uint32_t old = atomicCAS(&P[hi], hi, lo);
-        if (old == hi) return lo;
+        if (old == hi) {
+            if (linked) *linked = hi;
+            return lo;
+        }
         // hi was linked by someone else: its current parent is `old`
         u = hi; pu = old;
         v = lo; pv = lo;
@@ -247,6 +252,57 @@ __device__ __forceinline__ void zbit_set(uint32_t* zbits, uint32_t x) {
 
 constexpr int kEPT = 4;  // entries per thread per tile
 
+// SiskinCC's messages (Sec. III, Algorithm 2): every successful link appends
+// (linked root, new parent) to the log. One counter update per workgroup: the
+// waves' counts are summed in LDS, thread 0 reserves the block's range, and
+// each lane writes its records at its rank among the block's. Records past
+// cap are counted but not written (the status word reports it). Must be
+// reached by every thread of the block.
+__device__ __forceinline__ void log_append(const uint32_t (&child)[kEPT],
+                                           const uint32_t (&parent)[kEPT], uint32_t* log,
+                                           uint64_t cap, unsigned long long* count,
+                                           DevState* st) {
+    __shared__ uint32_t s_w[kBlock / 64];
+    __shared__ unsigned long long s_base;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint64_t mk[kEPT];
+    uint32_t tot = 0;
+#pragma unroll
+    for (int k = 0; k < kEPT; ++k) {
+        mk[k] = __ballot(child[k] != kEmpty);
+        tot += (uint32_t)__popcll(mk[k]);
+    }
+    if (lane == 0) s_w[wave] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            const uint32_t x = s_w[w];
+            s_w[w] = t;
+            t += x;
+        }
+        s_base = t ? atomicAdd(count, (unsigned long long)t) : 0ull;
+    }
+    __syncthreads();
+    uint64_t at = s_base + s_w[wave];
+    const uint64_t below = (1ull << lane) - 1ull;
+    bool full = false;
+#pragma unroll
+    for (int k = 0; k < kEPT; ++k) {
+        if (child[k] != kEmpty) {
+            const uint64_t i = at + (uint32_t)__popcll(mk[k] & below);
+            if (i < cap) {
+                u32x2 rec = {child[k], parent[k]};
+                *reinterpret_cast<u32x2*>(log + 2 * i) = rec;
+            } else {
+                full = true;
+            }
+        }
+        at += (uint32_t)__popcll(mk[k]);
+    }
+    if (full) atomicOr(&st->status, kStatusLogFull);
+}
+
 // One tile of kBlock*kEPT entries per workgroup; each thread loads its kEPT
 // entries (coalesced, non-temporal: the edge stream must not evict P) and
 // issues all their parent reads before walking any of them.
@@ -255,10 +311,15 @@ constexpr int kEPT = 4;  // entries per thread per tile
 // (the single-GPU form of treating zero-converged vertices specially, Sec. IV).
 // Bits only go from 0 to 1 and only for vertices in z's tree, so a stale or
 // missing bit just sends the entry down the ordinary path.
-template <bool ZR, int SPLIT>
+// LOG (plain path only): the links this launch makes are appended to `log`
+// (see log_append).
+template <bool ZR, int SPLIT, bool LOG = false>
 __global__ __launch_bounds__(kBlock) void k_hook(const uint32_t* __restrict__ edges, uint64_t m,
                                                  uint32_t n, uint32_t* P, uint32_t* zbits,
-                                                 DevState* st) {
+                                                 DevState* st, uint32_t* log = nullptr,
+                                                 uint64_t log_cap = 0,
+                                                 unsigned long long* log_count = nullptr) {
+    static_assert(!(ZR && LOG), "the update log belongs to the plain path");
     const uint32_t z = ZR ? ld_agent(&st->zroot) : 0u;
     const uint64_t tile = (uint64_t)blockIdx.x * (kBlock * kEPT);
     const u32x2* E = reinterpret_cast<const u32x2*>(edges);
@@ -308,20 +369,25 @@ __global__ __launch_bounds__(kBlock) void k_hook(const uint32_t* __restrict__ ed
         pu[k] = !live[k] ? 0u : ((ZR && inu[k]) ? z : P[wu[k]]);
         pv[k] = !live[k] ? 0u : ((ZR && inv[k]) ? z : P[wv[k]]);
     }
+    uint32_t child[kEPT], parent[kEPT];
 #pragma unroll
     for (int k = 0; k < kEPT; ++k) {
+        child[k] = kEmpty;
+        parent[k] = kEmpty;
         if (!live[k]) continue;
         // a common parent, or one endpoint the parent of the other: same tree
         uint32_t r;
         if (pu[k] == pv[k]) r = pu[k];
         else if (pu[k] == wv[k]) r = wv[k];
         else if (pv[k] == wu[k]) r = wu[k];
-        else r = link<ZR, SPLIT>(P, wu[k], pu[k], wv[k], pv[k], z);
+        else r = link<ZR, SPLIT>(P, wu[k], pu[k], wv[k], pv[k], z, LOG ? &child[k] : nullptr);
+        if (LOG) parent[k] = r;
         if (ZR && r == z) {
             if (!inu[k]) zbit_set(zbits, u[k]);
             if (!inv[k]) zbit_set(zbits, v[k]);
         }
     }
+    if (LOG) log_append(child, parent, log, log_cap, log_count, st);
 }
 
 // ---- compress (pointer jumping) ----------------------------------------------------
@@ -551,6 +617,27 @@ int run_hook(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P
     else if (zr) k_hook<true, 0><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st);
     else if (split) k_hook<false, 1><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st);
     else k_hook<false, 0><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st);
+    CCM_HIP(hipGetLastError());
+    return CC_OK;
+}
+
+int run_hook_log(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
+                 uint32_t flags, uint32_t* log, uint64_t log_cap, uint64_t* log_count,
+                 hipStream_t stream) {
+    if (flags & CC_F_ZROOT)
+        return fail(CC_EINVAL, "the update log is defined for the plain path (no CC_F_ZROOT)");
+    if (!m) return CC_OK;
+    const uint64_t per = (uint64_t)kBlock * kEPT;
+    const uint64_t blocks = (m + per - 1) / per;
+    if (blocks > 0x7FFFFFFFull) return fail(CC_EINVAL, "edge count too large for one launch");
+    const uint32_t g = (uint32_t)blocks;
+    auto* cnt = reinterpret_cast<unsigned long long*>(log_count);
+    if (flags & CC_F_NO_SPLIT)
+        k_hook<false, 0, true><<<g, kBlock, 0, stream>>>(edges, m, (uint32_t)n, P, nullptr, s->st,
+                                                         log, log_cap, cnt);
+    else
+        k_hook<false, 1, true><<<g, kBlock, 0, stream>>>(edges, m, (uint32_t)n, P, nullptr, s->st,
+                                                         log, log_cap, cnt);
     CCM_HIP(hipGetLastError());
     return CC_OK;
 }

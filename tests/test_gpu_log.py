@@ -1,0 +1,128 @@
+"""SiskinCC's update log on the GPU (Sec. III, Algorithm 2): cc_hook_log appends
+(linked root, new parent) at every successful link.
+
+The order of the messages depends on the schedule, so what is compared exactly
+is what is unique: the set of linked vertices (every vertex but its component's
+lowest ID, once each, since non-roots are never linked) and the labels that the
+messages give when taken as edges. Both are checked against the oracle, and the
+count against the oracle's sequential Algorithm 2."""
+import numpy as np
+import pytest
+import torch
+
+import graphgen
+import oracle
+from gpu_helpers import assert_same_labels, log, to_dev, to_host_u32
+
+pytestmark = pytest.mark.gpu
+
+cc = pytest.importorskip("paper_2507_03695_amd")
+
+
+def check_log(n, msgs, want, what):
+    """msgs: (k, 2) uint32 host array of messages; want: oracle labels."""
+    v = np.arange(n)
+    kids = np.sort(msgs[:, 0])
+    assert np.array_equal(kids, v[want != v]), f"{what}: linked vertices differ"
+    assert np.all(msgs[:, 1] < msgs[:, 0]), f"{what}: a parent has the greater ID"
+    assert np.array_equal(want[msgs[:, 0]], want[msgs[:, 1]]), f"{what}: a message crosses components"
+    assert_same_labels(oracle.cc_labels(n, msgs), want, f"{what}: messages as edges")
+
+
+def run_log(c, ed, n, chunks=1, flags=0, cap=None):
+    P = torch.empty(n, dtype=torch.int32, device="cuda")
+    cap = n if cap is None else cap
+    L = torch.empty((cap, 2), dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    c.init(n, P)
+    for part in torch.tensor_split(ed, chunks):
+        c.hook_log(part, n, P, L, cnt, flags=flags)
+    return P, L, cnt
+
+
+@pytest.mark.parametrize("split", [True, False])
+@pytest.mark.parametrize("kind", ["rmat", "er"])
+def test_log_is_the_set_of_links(kind, split):
+    n = 1 << 16
+    e = graphgen.rmat(16, 1 << 20, 81) if kind == "rmat" else graphgen.er(n, 1 << 17, 82)
+    want = oracle.cc_labels(n, e)
+    seq = oracle.siskin_log(n, e)
+    flags = 0 if split else cc.F_NO_SPLIT
+    with cc.Context() as c:
+        P, L, cnt = run_log(c, to_dev(e), n, flags=flags)
+        c.compress(n, P)
+        assert c.sync() == cc.CC_OK
+        k = int(cnt.item())
+        log(f"{kind}: {k} messages, sequential Algorithm 2: {len(seq)}")
+        assert k == len(seq) == n - oracle.count_components(want)
+        msgs = L[:k].cpu().numpy().view(np.uint32)
+        check_log(n, msgs, want, kind)
+        assert np.array_equal(np.sort(msgs[:, 0]), np.sort(seq[:, 0]))
+        assert_same_labels(to_host_u32(P), want, f"{kind}: labels after the logged hook")
+
+
+def test_log_appends_across_calls_and_tails():
+    n = 3001                                       # ragged against every block size
+    e = graphgen.er(n, 2 * n + 77, 83)
+    want = oracle.cc_labels(n, e)
+    with cc.Context() as c:
+        P, L, cnt = run_log(c, to_dev(e), n, chunks=7)
+        assert c.sync() == cc.CC_OK
+        k = int(cnt.item())
+        assert k == n - oracle.count_components(want)
+        check_log(n, L[:k].cpu().numpy().view(np.uint32), want, "7 calls")
+
+
+def test_log_capacity_and_arguments():
+    n = 1 << 12
+    e = graphgen.er(n, 4 * n, 84)
+    want = oracle.cc_labels(n, e)
+    total = n - oracle.count_components(want)
+    with cc.Context() as c:
+        ed = to_dev(e)
+        P, L, cnt = run_log(c, ed, n, cap=100)
+        assert c.sync() == cc.CC_ENOMEM
+        assert int(cnt.item()) == total            # counted past the capacity
+        kept = L[:100].cpu().numpy().view(np.uint32)
+        assert len(np.unique(kept[:, 0])) == 100 and np.all(kept[:, 1] < kept[:, 0])
+        assert np.array_equal(want[kept[:, 0]], want[kept[:, 1]])
+        assert c.sync() == cc.CC_OK                # the status word was cleared
+        with pytest.raises(cc.CCError) as ei:
+            c.hook_log(ed, n, P, L, cnt, flags=cc.F_ZROOT)
+        assert ei.value.code == cc.CC_EINVAL
+        cnt.zero_()
+        c.init(n, P)
+        c.hook_log(ed[:0], n, P, L, cnt)
+        assert c.sync() == cc.CC_OK and int(cnt.item()) == 0
+        bad = torch.tensor([[1, 2], [3, n + 5]], dtype=torch.int32, device="cuda")
+        c.hook_log(bad, n, P, L, cnt)
+        assert c.sync() == cc.CC_ERANGE
+        assert int(cnt.item()) == 1                # (2, 1); the bad entry is skipped
+
+
+def test_siskin_reducer_16_shares():
+    """Each of 16 edge shares hooks into its own P with a log and sends nothing
+    else; the Reducer hooks all messages as edges and compresses (Sec. III)."""
+    n, g = 1 << 20, 16
+    e = graphgen.rmat(20, 1 << 24, 85)
+    want = oracle.cc_labels(n, e)
+    log("oracle done")
+    k = (e[:, 0].astype(np.uint64) * g) // n
+    with cc.Context() as c:
+        logs, sent = [], 0
+        for s in range(g):
+            es = np.ascontiguousarray(e[k == s])
+            P, L, cnt = run_log(c, to_dev(es), n)
+            assert c.sync() == cc.CC_OK
+            ks = int(cnt.item())
+            assert ks == n - oracle.count_components(oracle.cc_labels(n, es))
+            logs.append(L[:ks])
+            sent += ks
+        assert sent <= min(len(e), g * n)          # Sec. V volume bound
+        log(f"messages {sent}, bound {min(len(e), g * n)}")
+        R = torch.empty(n, dtype=torch.int32, device="cuda")
+        c.init(n, R)
+        c.hook(torch.cat(logs), n, R)
+        c.compress(n, R)
+        assert c.sync() == cc.CC_OK
+        assert_same_labels(to_host_u32(R), want, "Reducer over the update logs")
