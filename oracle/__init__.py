@@ -167,3 +167,41 @@ def check_forest(P: np.ndarray, zroot_on: bool = False, zmax: int = 0) -> int:
     if r < 0:
         raise AssertionError(f"parent array is not a key-monotone forest at vertex {bad.value}")
     return int(r)
+
+
+# ---- compact vertex IDs of the exchange (Sec. V) ---------------------------------
+# Each ID travels in ceil(log2(|V|) / 8) bytes (at least one), least significant
+# byte first; a list of IDs is the concatenation of their byte groups.
+
+def id_bytes(n: int) -> int:
+    """Bytes per compact ID for IDs in [0, n): the smallest k >= 1 with 256^k >= n."""
+    k = 1
+    while 256 ** k < n:
+        k += 1
+    return k
+
+
+def pack_ids(ids, k: int) -> np.ndarray:
+    """uint8 array of len(ids) * k bytes; raises OracleError(ERANGE) if an ID
+    does not fit in k bytes."""
+    a = np.asarray(ids, dtype=np.uint64).ravel()
+    if k < 1 or k > 4:
+        raise OracleError(EINVAL)
+    if a.size and int(a.max()) >= 256 ** k:
+        raise OracleError(ERANGE)
+    out = np.empty(a.size * k, np.uint8)
+    for j in range(k):                                 # byte j of every ID
+        out[j::k] = (a >> np.uint64(8 * j)) & np.uint64(0xFF)
+    return out
+
+
+def unpack_ids(buf, k: int) -> np.ndarray:
+    """Inverse of pack_ids: uint32 IDs from len(buf) / k byte groups."""
+    b = np.asarray(buf, dtype=np.uint8).ravel()
+    if k < 1 or k > 4 or b.size % k:
+        raise OracleError(EINVAL)
+    out = np.zeros(b.size // k, np.uint64)
+    for j in range(k):
+        out |= b[j::k].astype(np.uint64) << np.uint64(8 * j)
+    return out.astype(np.uint32)
+

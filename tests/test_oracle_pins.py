@@ -249,6 +249,43 @@ def test_siskin_log_capacity_and_range():
     assert ei.value.code == oracle.ERANGE
 
 
+# ---- compact IDs of the exchange (Sec. V) --------------------------------------
+
+def test_id_bytes_closed_forms():
+    """ceil(log2(n) / 8) bytes hold every ID below n (one byte at least)."""
+    cases = {1: 1, 2: 1, 256: 1, 257: 2, 65536: 2, 65537: 3, 1 << 24: 3, (1 << 24) + 1: 4,
+             68109812: 4, 1 << 30: 4, 1 << 32: 4}
+    for n, k in cases.items():
+        assert oracle.id_bytes(n) == k, n
+
+
+def test_pack_ids_worked_bytes():
+    assert oracle.pack_ids([0x010203, 0xA0B0C0], 3).tolist() == [3, 2, 1, 0xC0, 0xB0, 0xA0]
+    assert oracle.pack_ids([0x1234, 0xFF, 0], 2).tolist() == [0x34, 0x12, 0xFF, 0, 0, 0]
+    assert oracle.pack_ids([7, 200], 1).tolist() == [7, 200]
+    assert oracle.pack_ids([0xDEADBEEF], 4).tolist() == [0xEF, 0xBE, 0xAD, 0xDE]
+    assert oracle.pack_ids([], 3).size == 0
+    assert oracle.unpack_ids([3, 2, 1, 0xC0, 0xB0, 0xA0], 3).tolist() == [0x010203, 0xA0B0C0]
+    with pytest.raises(oracle.OracleError):
+        oracle.pack_ids([1 << 24], 3)
+    with pytest.raises(oracle.OracleError):
+        oracle.unpack_ids([1, 2, 3, 4], 3)
+
+
+def test_pack_ids_round_trip_and_width():
+    rng = np.random.default_rng(41)
+    for n in [1, 2, 255, 256, 257, 70000, 1 << 24, (1 << 24) + 3, 1 << 31]:
+        k = oracle.id_bytes(n)
+        ids = rng.integers(0, n, size=int(rng.integers(0, 500)), dtype=np.uint64).astype(np.uint32)
+        ids[:1] = n - 1 if ids.size else ids[:1]
+        buf = oracle.pack_ids(ids, k)
+        assert buf.size == ids.size * k
+        np.testing.assert_array_equal(oracle.unpack_ids(buf, k), ids)
+        # the same bytes as the low k bytes of each little-endian 32-bit word
+        np.testing.assert_array_equal(
+            buf.reshape(-1, k), ids.astype("<u4").view(np.uint8).reshape(-1, 4)[:, :k])
+
+
 # ---- Algorithm 3 with the root function R (Formulas 1-2) ----------------------
 
 def test_root_function_jt_closed_form():
