@@ -193,8 +193,9 @@ def bench_reducer(cc, torch, ed, n, L_ref, g=16, reps=3):
     """Reducer emulation (Sec. III / IV / V): the workload's entries split into g
     shares by the first endpoint's vertex range, each solved into its own
     global-size parent array with the global zero root, exported as (v, P_v)
-    pairs and zero-converged IDs, then merged by a Reducer. Reports the message
-    counts against Sec. V's min(|E|, (g-1)|V|) and the time of each phase."""
+    pairs and zero-converged IDs, sent through the compact-ID codec (Sec. V) and
+    merged by a Reducer. Reports the message counts against Sec. V's
+    min(|E|, (g-1)|V|), the bytes on the wire and the time of each phase."""
     m = ed.shape[0]
     u = ed[:, 0].to(torch.int64) & 0xFFFFFFFF
     k = (u * g) // n
@@ -209,9 +210,10 @@ def bench_reducer(cc, torch, ed, n, L_ref, g=16, reps=3):
     z = ctx.get_zroot()
     hint = cc.F_ZROOT | cc.F_ZROOT_HINT
     ev = lambda: torch.cuda.Event(enable_timing=True)
+    kb = ctx.id_bytes(n)                                    # compact IDs of Sec. V
     res = []
     for rep in range(reps):
-        e0, e1, e2, e3 = ev(), ev(), ev(), ev()
+        e0, e1, e2, e3, e4, e5 = ev(), ev(), ev(), ev(), ev(), ev()
         e0.record(stream)
         for P, es in zip(Ps, parts):
             ctx.init(n, P, stream)
@@ -225,28 +227,42 @@ def bench_reducer(cc, torch, ed, n, L_ref, g=16, reps=3):
         zero = torch.cat([q for _, q in exported])
         del exported
         e2.record(stream)
+        # on the wire: every ID in kb bytes; the Reducer works on what it decodes
+        wire_p = ctx.pack_ids(pairs, kb, stream=stream)
+        wire_z = ctx.pack_ids(zero, kb, stream=stream)
+        e3.record(stream)
+        pairs2 = ctx.unpack_ids(wire_p, pairs.numel(), kb, stream=stream).view(-1, 2)
+        zero2 = ctx.unpack_ids(wire_z, zero.numel(), kb, stream=stream)
+        e4.record(stream)
+        wire_bytes = wire_p.numel() + wire_z.numel()
+        del wire_p, wire_z
+        assert torch.equal(pairs2, pairs) and torch.equal(zero2, zero)
+        pairs, zero = pairs2, zero2
+        e4b = ev()
+        e4b.record(stream)
         ctx.init(n, L, stream)
         ctx.zroot(pairs, n, flags=hint, zroot_hint=z, stream=stream)
         ctx.hook(pairs, n, L, flags=cc.F_ZROOT, stream=stream)
         ctx.hook_ids(zero, z, n, L, flags=cc.F_ZROOT, stream=stream)
         ctx.compress(n, L, flags=cc.F_ZROOT, stream=stream)
         ctx.canon(n, L, stream=stream)
-        e3.record(stream)
+        e5.record(stream)
         assert ctx.sync(stream) == cc.CC_OK
-        res.append((e0.elapsed_time(e1), e1.elapsed_time(e2), e2.elapsed_time(e3),
-                    int(pairs.shape[0]), int(zero.shape[0])))
+        res.append((e0.elapsed_time(e1), e1.elapsed_time(e2), e4b.elapsed_time(e5),
+                    int(pairs.shape[0]), int(zero.shape[0]), e2.elapsed_time(e3),
+                    e3.elapsed_time(e4), wire_bytes))
         del pairs, zero
     same = bool(torch.equal(L, L_ref))
     ctx.close()
     med = lambda i: float(np.median([r[i] for r in res]))
     npairs, nzero = res[-1][3], res[-1][4]
-    id_bytes = max(1, ((n - 1).bit_length() + 7) // 8)      # compact IDs of Sec. V
     return {"shares": g, "zero_root": z,
             "pairs": npairs, "zero_ids": nzero,
             "bound_min_E_gm1V": min(m, (g - 1) * n),
-            "message_bytes": npairs * 2 * id_bytes + nzero * id_bytes,
-            "message_bytes_without_zero_ids": (npairs + nzero) * 2 * id_bytes,
+            "id_bytes": kb, "message_bytes": res[-1][7],
+            "message_bytes_without_zero_ids": (npairs + nzero) * 2 * kb,
             "share_solves_ms": round(med(0), 3), "export_ms": round(med(1), 3),
+            "pack_ms": round(med(5), 3), "unpack_ms": round(med(6), 3),
             "reducer_ms": round(med(2), 3), "identical_labels": same}
 
 

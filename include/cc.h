@@ -245,6 +245,31 @@ int cc_export(cc_ctx* ctx, uint64_t n, const uint32_t* P, uint32_t zroot, uint32
 int cc_hook_ids(cc_ctx* ctx, uint64_t n, uint64_t count, const uint32_t* ids, uint32_t target,
                 uint32_t* P, uint32_t flags, void* stream);
 
+/* Compact vertex IDs of the exchange (Sec. V): an ID below n travels in
+   cc_id_bytes(n) = ceil(log2(n) / 8) bytes (1 for n <= 256; at least 1).
+   Host-only arithmetic; valid for any n >= 0. */
+uint32_t cc_id_bytes(uint64_t n);
+
+/* Encode count IDs as count * id_bytes bytes: ID i occupies bytes
+   [i*id_bytes, (i+1)*id_bytes) of out, least significant byte first. Pairs
+   are encoded as their 2*count IDs.
+     ids       device, count uint32, 4-byte aligned
+     id_bytes  1..4 (else CC_EINVAL)
+     out       device, count * id_bytes bytes, 4-byte aligned, owned by the
+               caller
+   An ID >= 2^(8*id_bytes) has only its low bytes written and sets CC_ERANGE
+   at the next cc_sync. Asynchronous on `stream`. */
+int cc_pack_ids(cc_ctx* ctx, uint64_t count, const uint32_t* ids, uint32_t id_bytes, uint8_t* out,
+                void* stream);
+
+/* Decode count IDs written by cc_pack_ids with the same id_bytes.
+     in   device, count * id_bytes bytes, 4-byte aligned (nothing past
+          count * id_bytes is read)
+     ids  device, count uint32, 4-byte aligned, owned by the caller
+   Asynchronous on `stream`. */
+int cc_unpack_ids(cc_ctx* ctx, uint64_t count, const uint8_t* in, uint32_t id_bytes, uint32_t* ids,
+                  void* stream);
+
 /* ---- many graphs in one launch ------------------------------------------- */
 
 /*

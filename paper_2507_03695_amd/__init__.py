@@ -79,6 +79,9 @@ SIGNATURES = {
     "cc_export": (_I32, [_P, _U64, _P, _U32, _P, _U64, _P, _U64, ctypes.POINTER(_U64),
                          ctypes.POINTER(_U64), _P]),
     "cc_hook_ids": (_I32, [_P, _U64, _U64, _P, _U32, _P, _U32, _P]),
+    "cc_id_bytes": (_U32, [_U64]),
+    "cc_pack_ids": (_I32, [_P, _U64, _P, _U32, _P, _P]),
+    "cc_unpack_ids": (_I32, [_P, _U64, _P, _U32, _P, _P]),
     "cc_batch": (_I32, [_P, _U32, _P, _P, _P, _P, _P, _P]),
     "cc_serve_open": (_I32, [_P, ctypes.POINTER(_ServeOpts), ctypes.POINTER(_P)]),
     "cc_serve_submit": (_I32, [_P, _U64, _U64, _P, _P, _U32, ctypes.POINTER(_U64)]),
@@ -268,6 +271,30 @@ class Context:
         """cc_hook_ids: every ids[i] is connected to target."""
         _check(self.lib.cc_hook_ids(self._h, n, ids.numel(), _dptr(ids, _ID), target, _dptr(P, _ID),
                                     flags, _stream(stream)), "cc_hook_ids")
+
+    # compact IDs (Sec. V)
+    def id_bytes(self, n) -> int:
+        return int(self.lib.cc_id_bytes(n))
+
+    def pack_ids(self, ids, id_bytes, out=None, stream=None):
+        """cc_pack_ids: ids (any shape, P's dtype) -> uint8 tensor of ids.numel() * id_bytes."""
+        if out is None:
+            out = torch.empty(ids.numel() * id_bytes, dtype=torch.uint8, device=ids.device)
+        if out.numel() < ids.numel() * id_bytes:
+            raise ValueError("out is too small")
+        _check(self.lib.cc_pack_ids(self._h, ids.numel(), _dptr(ids, _ID), id_bytes,
+                                    _dptr(out, (torch.uint8,)), _stream(stream)), "cc_pack_ids")
+        return out
+
+    def unpack_ids(self, buf, count, id_bytes, out=None, stream=None):
+        """cc_unpack_ids: the first count IDs of a packed uint8 tensor -> int32 tensor."""
+        if buf.numel() < count * id_bytes:
+            raise ValueError("buf is too small")
+        if out is None:
+            out = torch.empty(count, dtype=torch.int32, device=buf.device)
+        _check(self.lib.cc_unpack_ids(self._h, count, _dptr(buf, (torch.uint8,)), id_bytes,
+                                      _dptr(out, _ID), _stream(stream)), "cc_unpack_ids")
+        return out
 
     # batch
     def batch(self, vtx_off, edge_off, edges, L=None, status=None, stream=None):

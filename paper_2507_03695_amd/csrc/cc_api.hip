@@ -349,6 +349,42 @@ extern "C" int cc_hook_ids(cc_ctx* ctx, uint64_t n, uint64_t count, const uint32
     return cohere((hipStream_t)stream);
 }
 
+extern "C" uint32_t cc_id_bytes(uint64_t n) {
+    uint32_t k = 1;
+    while (k < 8 && (n - 1) >> (8 * k)) ++k;
+    return n <= 1 ? 1u : k;
+}
+
+static int check_codec(uint64_t count, const void* a, const void* b, uint32_t id_bytes) {
+    if (id_bytes < 1 || id_bytes > 4) return fail(CC_EINVAL, "id_bytes must be 1..4");
+    if (count && (!a || !b)) return fail(CC_EINVAL, "NULL buffer with a nonzero count");
+    if (((uintptr_t)a | (uintptr_t)b) & 3u) return fail(CC_EINVAL, "buffers must be 4-byte aligned");
+    if (count > (UINT64_MAX >> 3)) return fail(CC_EINVAL, "count too large");
+    return CC_OK;
+}
+
+extern "C" int cc_pack_ids(cc_ctx* ctx, uint64_t count, const uint32_t* ids, uint32_t id_bytes,
+                           uint8_t* out, void* stream) {
+    if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    int rc = check_codec(count, ids, out, id_bytes);
+    if (rc || count == 0) return rc;
+    if ((rc = set_dev(ctx))) return rc;
+    if ((rc = cohere((hipStream_t)stream))) return rc;
+    if ((rc = run_pack_ids(&ctx->slot, count, ids, id_bytes, out, (hipStream_t)stream))) return rc;
+    return cohere((hipStream_t)stream);
+}
+
+extern "C" int cc_unpack_ids(cc_ctx* ctx, uint64_t count, const uint8_t* in, uint32_t id_bytes,
+                             uint32_t* ids, void* stream) {
+    if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    int rc = check_codec(count, in, ids, id_bytes);
+    if (rc || count == 0) return rc;
+    if ((rc = set_dev(ctx))) return rc;
+    if ((rc = cohere((hipStream_t)stream))) return rc;
+    if ((rc = run_unpack_ids(&ctx->slot, count, in, id_bytes, ids, (hipStream_t)stream))) return rc;
+    return cohere((hipStream_t)stream);
+}
+
 extern "C" int cc_get_zroot(cc_ctx* ctx, void* stream, uint32_t* zroot_out) {
     if (!ctx || !zroot_out) return fail(CC_EINVAL, "NULL argument");
     int rc = set_dev(ctx);

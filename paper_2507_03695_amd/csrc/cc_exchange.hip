@@ -7,6 +7,8 @@
 // counts its pairs and IDs (pass 1), an exclusive prefix over blocks gives each
 // block its output offsets, and pass 2 writes with an order-preserving
 // compaction inside the block.
+#include <algorithm>
+
 #include "cc_internal.h"
 
 namespace ccm {
@@ -166,6 +168,109 @@ int run_export(Slot* s, uint64_t n, const uint32_t* P, uint32_t zroot, uint32_t*
     CCM_HIP(hipGetLastError());
     if ((rc = cohere(stream))) return rc;
     CCM_HIP(hipStreamSynchronize(stream));
+    return CC_OK;
+}
+
+// ---- compact IDs (Sec. V) --------------------------------------------------------
+// ID i of a list occupies bytes [i*K, i*K + K) of the stream, least significant
+// byte first. Packing: one thread per 4-byte output word, which draws on at
+// most four consecutive IDs; full words are one aligned store, the tail word
+// byte stores. Unpacking: one thread per ID, aligned word loads, byte loads
+// where a word would reach past the end of the stream.
+
+template <int K>
+__global__ __launch_bounds__(kXBlock) void k_pack_ids(const uint32_t* __restrict__ ids,
+                                                      uint64_t count, uint8_t* __restrict__ out,
+                                                      DevState* st) {
+    const uint64_t total = count * K;
+    const uint64_t words = (total + 3) / 4;
+    bool bad = false;
+    for (uint64_t w = (uint64_t)blockIdx.x * kXBlock + threadIdx.x; w < words;
+         w += (uint64_t)gridDim.x * kXBlock) {
+        const uint64_t b0 = 4 * w;
+        const uint64_t i0 = b0 / K;
+        // the word's bytes lie in IDs i0 .. i0 + (K + 2) / K
+        constexpr int kIds = (K + 2) / K + 1;
+        uint32_t x[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const uint64_t i = i0 + t;
+            x[t] = (t < kIds && i < count) ? ids[i] : 0u;
+        }
+        if (K < 4) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if ((x[t] >> (8 * K)) != 0u && (i0 + t) * K >= b0 && (i0 + t) * K < b0 + 4) bad = true;
+        }
+        uint32_t word = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint64_t b = b0 + j;
+            const uint32_t t = (uint32_t)(b / K - i0);     // 0..3
+            const uint32_t sh = 8u * (uint32_t)(b % K);
+            const uint32_t v = t == 0 ? x[0] : t == 1 ? x[1] : t == 2 ? x[2] : x[3];
+            word |= ((v >> sh) & 0xFFu) << (8 * j);
+        }
+        if (b0 + 4 <= total) {
+            *reinterpret_cast<uint32_t*>(out + b0) = word;
+        } else {
+            for (int j = 0; b0 + j < total; ++j) out[b0 + j] = (uint8_t)(word >> (8 * j));
+        }
+    }
+    if (bad) atomicOr(&st->status, kStatusRange);
+}
+
+template <int K>
+__global__ __launch_bounds__(kXBlock) void k_unpack_ids(const uint8_t* __restrict__ in,
+                                                        uint64_t count, uint32_t* __restrict__ ids) {
+    const uint64_t total = count * K;
+    const uint32_t mask = K == 4 ? 0xFFFFFFFFu : ((1u << (8 * K)) - 1u);
+    for (uint64_t i = (uint64_t)blockIdx.x * kXBlock + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * kXBlock) {
+        const uint64_t b = i * K;
+        const uint64_t w0 = b / 4;
+        const uint32_t off = (uint32_t)(b % 4);
+        const uint64_t w1 = (b + K - 1) / 4;                 // last word touched
+        uint32_t x;
+        if (4 * w1 + 4 <= total) {
+            const uint32_t* W = reinterpret_cast<const uint32_t*>(in);
+            const uint64_t lo = W[w0];
+            const uint64_t hi = (w1 != w0) ? W[w1] : 0u;
+            x = (uint32_t)(((hi << 32) | lo) >> (8 * off)) & mask;
+        } else {
+            x = 0;
+            for (int j = 0; j < K; ++j) x |= (uint32_t)in[b + j] << (8 * j);
+        }
+        ids[i] = x;
+    }
+}
+
+int run_pack_ids(Slot* s, uint64_t count, const uint32_t* ids, uint32_t k, uint8_t* out,
+                 hipStream_t stream) {
+    if (!count) return CC_OK;
+    const uint32_t g = (uint32_t)std::min<uint64_t>((count * k / 4 + kXBlock) / kXBlock + 1, kGridCap);
+    switch (k) {
+        case 1: k_pack_ids<1><<<g, kXBlock, 0, stream>>>(ids, count, out, s->st); break;
+        case 2: k_pack_ids<2><<<g, kXBlock, 0, stream>>>(ids, count, out, s->st); break;
+        case 3: k_pack_ids<3><<<g, kXBlock, 0, stream>>>(ids, count, out, s->st); break;
+        default: k_pack_ids<4><<<g, kXBlock, 0, stream>>>(ids, count, out, s->st); break;
+    }
+    CCM_HIP(hipGetLastError());
+    return CC_OK;
+}
+
+int run_unpack_ids(Slot* s, uint64_t count, const uint8_t* in, uint32_t k, uint32_t* ids,
+                   hipStream_t stream) {
+    (void)s;
+    if (!count) return CC_OK;
+    const uint32_t g = (uint32_t)std::min<uint64_t>((count + kXBlock - 1) / kXBlock, kGridCap);
+    switch (k) {
+        case 1: k_unpack_ids<1><<<g, kXBlock, 0, stream>>>(in, count, ids); break;
+        case 2: k_unpack_ids<2><<<g, kXBlock, 0, stream>>>(in, count, ids); break;
+        case 3: k_unpack_ids<3><<<g, kXBlock, 0, stream>>>(in, count, ids); break;
+        default: k_unpack_ids<4><<<g, kXBlock, 0, stream>>>(in, count, ids); break;
+    }
+    CCM_HIP(hipGetLastError());
     return CC_OK;
 }
 

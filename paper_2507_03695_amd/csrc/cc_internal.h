@@ -104,6 +104,11 @@ int run_hook_ids(Slot* s, uint64_t n, uint64_t count, const uint32_t* ids, uint3
 int run_export(Slot* s, uint64_t n, const uint32_t* P, uint32_t zroot, uint32_t* pairs,
                uint64_t pairs_cap, uint32_t* zero_ids, uint64_t zero_cap, uint64_t* n_pairs,
                uint64_t* n_zero, hipStream_t stream);
+// Compact IDs of the exchange (cc_exchange.hip); k in 1..4, buffers 4-byte aligned.
+int run_pack_ids(Slot* s, uint64_t count, const uint32_t* ids, uint32_t k, uint8_t* out,
+                 hipStream_t stream);
+int run_unpack_ids(Slot* s, uint64_t count, const uint8_t* in, uint32_t k, uint32_t* ids,
+                   hipStream_t stream);
 int run_solve(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* L,
               uint32_t flags, uint32_t hint, hipStream_t stream);
 // Copy the status word to the host, clear it, wait for the stream; CC_OK,

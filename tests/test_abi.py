@@ -76,3 +76,13 @@ def test_oracle_never_touches_the_product():
         if f.endswith((".py", ".c", ".h")):
             text = open(os.path.join(ROOT, "oracle", f)).read()
             assert "paper_2507_03695_amd" not in text and "cc.h" not in text
+
+
+def test_id_bytes_without_gpu():
+    """cc_id_bytes is host arithmetic: it agrees with the oracle's width rule."""
+    import oracle
+    import paper_2507_03695_amd as pkg
+    lib = pkg.load()
+    for n in [0, 1, 2, 255, 256, 257, 65535, 65536, 65537, (1 << 24) - 1, 1 << 24, (1 << 24) + 1,
+              68109812, 1 << 30, (1 << 32) - 1, 1 << 32]:
+        assert lib.cc_id_bytes(n) == oracle.id_bytes(n), n
