@@ -205,3 +205,30 @@ def unpack_ids(buf, k: int) -> np.ndarray:
         out |= b[j::k].astype(np.uint64) << np.uint64(8 * j)
     return out.astype(np.uint32)
 
+
+# ---- CSR input ---------------------------------------------------------------------
+# Row u of a CSR graph holds the entries (u, adj[j]), offsets[u] <= j < offsets[u+1];
+# as unordered pairs they are a COO list, which is what the labels are defined on.
+
+def csr_pairs(offsets, adj) -> np.ndarray:
+    """The (m, 2) uint32 entries of a CSR graph, row by row."""
+    off = np.asarray(offsets, dtype=np.int64)
+    if off.size == 0 or off[0] != 0 or np.any(np.diff(off) < 0):
+        raise OracleError(EINVAL)
+    n = off.size - 1
+    a = np.asarray(adj, dtype=np.uint32)[: off[-1]]
+    u = np.repeat(np.arange(n, dtype=np.uint32), np.diff(off))
+    return np.stack([u, a], axis=1)
+
+
+def cc_labels_csr(offsets, adj) -> np.ndarray:
+    off = np.asarray(offsets, dtype=np.int64)
+    return cc_labels(off.size - 1, csr_pairs(off, adj))
+
+
+def zroot_csr(offsets) -> int:
+    """The vertex with the longest row (Algorithm 4's max degree on CSR), ties to the
+    lowest ID; 0 when every row is empty."""
+    d = np.diff(np.asarray(offsets, dtype=np.int64))
+    return int(np.argmax(d)) if d.size and d.max() > 0 else 0
+

@@ -286,6 +286,39 @@ def test_pack_ids_round_trip_and_width():
             buf.reshape(-1, k), ids.astype("<u4").view(np.uint8).reshape(-1, 4)[:, :k])
 
 
+# ---- CSR input ---------------------------------------------------------------------
+
+def test_csr_pairs_by_hand():
+    # rows: 0 -> {1, 2}, 1 -> {}, 2 -> {0}, 3 -> {3, 1}
+    off = [0, 2, 2, 3, 5]
+    adj = [1, 2, 0, 3, 1]
+    assert oracle.csr_pairs(off, adj).tolist() == [[0, 1], [0, 2], [2, 0], [3, 3], [3, 1]]
+    assert oracle.cc_labels_csr(off, adj).tolist() == [0, 0, 0, 0]
+    assert oracle.zroot_csr(off) == 0                  # rows 0 and 3 tie at 2: lowest ID
+    with pytest.raises(oracle.OracleError):
+        oracle.csr_pairs([0, 3, 2], [0, 1, 1])
+    assert oracle.zroot_csr([0, 0, 0]) == 0
+    assert oracle.cc_labels_csr([0, 0, 0], []).tolist() == [0, 1]
+
+
+def test_csr_star_and_isolated_run():
+    """A star centred at 7 with both directions listed, plus empty rows: the centre
+    has the longest row and every leaf's label is the star's lowest ID."""
+    n = 20
+    leaves = [3, 9, 15, 19]
+    rows = [[] for _ in range(n)]
+    for x in leaves:
+        rows[7].append(x)
+        rows[x].append(7)
+    off = np.cumsum([0] + [len(r) for r in rows])
+    adj = [x for r in rows for x in r]
+    assert oracle.zroot_csr(off) == 7
+    L = oracle.cc_labels_csr(off, adj)
+    want = np.arange(n)
+    want[[3, 7, 9, 15, 19]] = 3
+    np.testing.assert_array_equal(L, want)
+
+
 # ---- Algorithm 3 with the root function R (Formulas 1-2) ----------------------
 
 def test_root_function_jt_closed_form():
