@@ -386,6 +386,45 @@ def bench_update_log(cc, torch, ed, n, L_ref, hook_plain_ms, g=16, reps=3):
             "siskin_identical_labels": same}
 
 
+def bench_csr(cc, torch, ed, n, L_ref, steps=3):
+    """CSR input (cc_solve_csr): the workload's entries grouped by first endpoint
+    (stable, so rows keep entry order), solved with the exact longest-row zero
+    root and on the plain path. The conversion is not timed; each step is one
+    cc_solve_csr (init, zero root, push, hook, compress, canon)."""
+    m = ed.shape[0]
+    u = ed[:, 0]
+    order = torch.argsort(u, stable=True)
+    adj = ed[:, 1][order].contiguous()
+    del order
+    off = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
+    off[1:] = torch.cumsum(torch.bincount(u, minlength=n), 0)
+    torch.cuda.synchronize()
+    ctx = cc.Context()
+    stream = torch.cuda.current_stream()
+    L = torch.empty(n, dtype=torch.int32, device="cuda")
+    out = {}
+    for name, flags in (("zroot", cc.F_ZROOT), ("plain", 0)):
+        ctx.solve_csr_async(off, adj, n, L, flags=flags, stream=stream)
+        assert ctx.sync(stream) == cc.CC_OK
+        ts = []
+        for _ in range(steps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            ctx.solve_csr_async(off, adj, n, L, flags=flags, stream=stream)
+            b.record(stream)
+            assert ctx.sync(stream) == cc.CC_OK
+            ts.append(a.elapsed_time(b))
+        ms = float(np.median(ts))
+        out[name] = {"ms_per_step": round(ms, 3), "GTEPS": round(m / (ms * 1e-3) / 1e9, 3),
+                     "identical_labels": bool(torch.equal(L, L_ref))}
+        if flags:
+            out[name]["zero_root_exact"] = ctx.get_zroot()
+    ctx.close()
+    del adj, off, L
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -433,7 +472,7 @@ def main():
                                      0 if flags else cc.F_ZROOT)
     assert torch.equal(L, L_o), "variants disagree"
     del L_o
-    reducer = upd = None
+    reducer = upd = csr = None
     if not args.no_extras:
         t1 = time.time()
         reducer = bench_reducer(cc, torch, ed, n, L)
@@ -441,6 +480,9 @@ def main():
         t1 = time.time()
         upd = bench_update_log(cc, torch, ed, n, L, hook_o if flags else hook_ms)
         log(f"update log done in {time.time() - t1:.1f} s")
+        t1 = time.time()
+        csr = bench_csr(cc, torch, ed, n, L)
+        log(f"csr done in {time.time() - t1:.1f} s")
 
     alg_bytes = 8 * m + 12 * n
     gteps = m / (ms * 1e-3) / 1e9
@@ -473,6 +515,8 @@ def main():
         line["reducer"] = reducer
     if upd is not None:
         line["update_log"] = upd
+    if csr is not None:
+        line["csr"] = csr
     del ed, L
     torch.cuda.empty_cache()
     if not args.no_extras:

@@ -124,9 +124,31 @@ int cc_solve(uint64_t n, uint64_t m, const uint32_t* edge_list, uint32_t* L);
 int cc_solve_async(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edge_list,
                    uint32_t* L, uint32_t flags, uint32_t zroot_hint, void* stream);
 
+/* The whole path on CSR input: row u of the graph holds the entries
+   (u, adj[j]) for j in [offsets[u], offsets[u+1]), unordered pairs as in the
+   COO form (a symmetric CSR lists each edge twice, which is allowed; no
+   symmetry is needed, Sec. II). With CC_F_ZROOT the zero root is the vertex
+   with the longest row, ties to the lowest ID (Algorithm 4 reads degrees from
+   CSR; CC_F_ZROOT_HINT uses zroot_hint instead), and the Initial Push covers
+   its whole row. Rows are hooked in order, so runs of entries share their
+   first endpoint's parent reads.
+     n        vertices, < 2^32
+     offsets  device, n+1 uint64, non-decreasing, offsets[0] = 0; m =
+              offsets[n] is read back (the call waits for `stream` once, before
+              enqueueing)
+     adj      device, m uint32 (each < n; others set CC_ERANGE at cc_sync)
+     L        device, n uint32, written: L_v = smallest vertex ID of v's
+              component
+   Offsets that are not a valid row index make the next cc_sync return
+   CC_EINVAL (labels unspecified; no access leaves the arrays). Asynchronous
+   after the read-back; status through cc_sync. */
+int cc_solve_csr(cc_ctx* ctx, uint64_t n, const uint64_t* offsets, const uint32_t* adj, uint32_t* L,
+                 uint32_t flags, uint32_t zroot_hint, void* stream);
+
 /* Wait for `stream`, then return (and clear) the status accumulated by the
-   context's work since the previous cc_sync: CC_OK, CC_ERANGE, or CC_ENOMEM
-   (an update log of cc_hook_log ran out of capacity). */
+   context's work since the previous cc_sync: CC_OK, CC_ERANGE, CC_ENOMEM
+   (an update log of cc_hook_log ran out of capacity) or CC_EINVAL (CSR
+   offsets of cc_solve_csr were not a valid row index). */
 int cc_sync(cc_ctx* ctx, void* stream);
 
 /* ---- the steps, one entry point each (asynchronous on `stream`) ----------

@@ -68,6 +68,7 @@ SIGNATURES = {
     "cc_solve": (_I32, [_U64, _U64, _P, _P]),
     "cc_solve_async": (_I32, [_P, _U64, _U64, _P, _P, _U32, _U32, _P]),
     "cc_sync": (_I32, [_P, _P]),
+    "cc_solve_csr": (_I32, [_P, _U64, _P, _P, _P, _U32, _U32, _P]),
     "cc_init": (_I32, [_P, _U64, _P, _P]),
     "cc_zroot": (_I32, [_P, _U64, _U64, _P, _U32, _U32, _P]),
     "cc_push": (_I32, [_P, _U64, _U64, _P, _P, _P]),
@@ -191,11 +192,25 @@ class Context:
         _check(self.lib.cc_solve_async(self._h, n, m, _dptr(edges, _ID), _dptr(L, _ID), flags,
                                        zroot_hint, _stream(stream)), "cc_solve_async")
 
+    def solve_csr_async(self, offsets, adj, n, L, flags=0, zroot_hint=0, stream=None):
+        """cc_solve_csr: offsets (n+1,) int64 and adj (m,) ID tensors on the device."""
+        _check(self.lib.cc_solve_csr(self._h, n, _dptr(offsets, (torch.int64, torch.uint64)),
+                                     _dptr(adj, _ID), _dptr(L, _ID), flags, zroot_hint,
+                                     _stream(stream)), "cc_solve_csr")
+
+    def solve_csr(self, offsets, adj, n, flags=0, zroot_hint=0, out=None, stream=None):
+        if out is None:
+            out = torch.empty(n, dtype=adj.dtype, device=adj.device)
+        self.solve_csr_async(offsets, adj, n, out, flags, zroot_hint, stream)
+        _check(self.sync(stream), "solve_csr")
+        return out
+
     def sync(self, stream=None) -> int:
-        """Wait for the stream; returns the status word's outcome, CC_OK, CC_ERANGE or
-        CC_ENOMEM (a full update log), without raising for those."""
+        """Wait for the stream; returns the status word's outcome, CC_OK, CC_ERANGE,
+        CC_ENOMEM (a full update log) or CC_EINVAL (bad CSR offsets), without raising
+        for those."""
         rc = self.lib.cc_sync(self._h, _stream(stream))
-        if rc not in (CC_OK, CC_ERANGE, CC_ENOMEM):
+        if rc not in (CC_OK, CC_ERANGE, CC_ENOMEM, CC_EINVAL):
             _check(rc, "cc_sync")
         return rc
 

@@ -61,7 +61,8 @@ int slot_create(Slot* s, int device, uint32_t samples) {
     s->bmin = s->hcounts + s->table;
     s->xs = s->bmin + kGridCap;
     CCM_HIP(hipMemset(s->st, 0, sizeof(DevState)));
-    e = hipHostMalloc(&s->host_status, sizeof(uint32_t), hipHostMallocDefault);
+    // one 64-byte block: the status word, or a 64-bit value read back by an entry point
+    e = hipHostMalloc(&s->host_status, 64, hipHostMallocDefault);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         (void)hipFree(base);
@@ -80,6 +81,7 @@ void slot_destroy(Slot* s) {
     if (s->st) (void)hipFree(s->st);
     if (s->deg) (void)hipFree(s->deg);
     if (s->zbits) (void)hipFree(s->zbits);
+    if (s->csr_tiles) (void)hipFree(s->csr_tiles);
     tiled_free(&s->tiled);
     batch_scratch_free(&s->batch);
     if (s->host_status) (void)hipHostFree(s->host_status);
@@ -102,6 +104,7 @@ int slot_sync(Slot* s, hipStream_t stream) {
     const uint32_t w = __atomic_load_n(s->host_status, __ATOMIC_ACQUIRE);
     if (w & kStatusInternal) return fail(CC_EDEVICE, "internal scratch bound exceeded");
     if (w & kStatusRange) return fail(CC_ERANGE, "an endpoint is >= n");
+    if (w & kStatusBadOffsets) return fail(CC_EINVAL, "CSR offsets are not a valid row index");
     if (w & kStatusLogFull) return fail(CC_ENOMEM, "update log capacity exceeded");
     return CC_OK;
 }
@@ -230,6 +233,28 @@ extern "C" int cc_solve_async(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_
         return fail(CC_EINVAL, "zroot_hint must be < n");
     if ((rc = set_dev(ctx))) return rc;
     return run_solve(&ctx->slot, n, m, edge_list, L, flags, zroot_hint, (hipStream_t)stream);
+}
+
+extern "C" int cc_solve_csr(cc_ctx* ctx, uint64_t n, const uint64_t* offsets, const uint32_t* adj,
+                            uint32_t* L, uint32_t flags, uint32_t zroot_hint, void* stream) {
+    if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    if (n >= (1ull << 32)) return fail(CC_EINVAL, "n must be < 2^32");
+    if (n == 0) return CC_OK;
+    if (!offsets || !L) return fail(CC_EINVAL, "NULL offsets or L");
+    if ((flags & CC_F_ZROOT_HINT) && zroot_hint >= n) return fail(CC_EINVAL, "zroot_hint must be < n");
+    int rc = set_dev(ctx);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    // the entry count sizes the launches: read off[n] (a coherent copy)
+    if ((rc = cohere(st))) return rc;
+    uint64_t* hm = reinterpret_cast<uint64_t*>(ctx->slot.host_status);
+    CCM_HIP(hipMemcpyAsync(hm, offsets + n, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    CCM_HIP(hipStreamSynchronize(st));
+    const uint64_t m = *hm;
+    *hm = 0;
+    if (m && !adj) return fail(CC_EINVAL, "NULL adj with a nonzero entry count");
+    if (m > (1ull << 40)) return fail(CC_EINVAL, "offsets[n] is implausibly large");
+    return run_solve_csr(&ctx->slot, n, m, offsets, adj, L, flags, zroot_hint, st);
 }
 
 extern "C" int cc_sync(cc_ctx* ctx, void* stream) {

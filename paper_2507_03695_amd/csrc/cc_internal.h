@@ -28,6 +28,7 @@ static_assert(sizeof(DevState) == 64, "DevState is one 64-byte block");
 constexpr uint32_t kStatusRange = 1u;
 constexpr uint32_t kStatusInternal = 2u;   // a scratch bound check failed (a bug)
 constexpr uint32_t kStatusLogFull = 4u;    // an update log ran out of capacity
+constexpr uint32_t kStatusBadOffsets = 8u; // CSR offsets not a valid row index
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kGridCap = 256 * 32;   // blocks of a grid-stride launch over n
 
@@ -68,7 +69,7 @@ struct Slot {
     uint32_t samples = 0;          // K
     uint32_t* deg = nullptr;       // device, exact-degree counts (grown on demand)
     uint64_t deg_cap = 0;
-    uint32_t* host_status = nullptr;  // pinned host word
+    uint32_t* host_status = nullptr;  // pinned host block of 64 bytes (status word, read-backs)
     BatchScratch batch;
     // Zero-root membership bitmap: bit x set => x is in the zero root's tree.
     uint32_t* zbits = nullptr;     // device, ceil(n/32) words (grown on demand)
@@ -78,6 +79,8 @@ struct Slot {
     uint64_t cur_n = 0;
     bool zr_ready = false;
     TiledScratch tiled;
+    uint32_t* csr_tiles = nullptr; // device, first row of every CSR tile (grown on demand)
+    uint64_t csr_tiles_cap = 0;
 };
 
 int slot_create(Slot* s, int device, uint32_t samples);
@@ -111,8 +114,13 @@ int run_unpack_ids(Slot* s, uint64_t count, const uint8_t* in, uint32_t k, uint3
                    hipStream_t stream);
 int run_solve(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* L,
               uint32_t flags, uint32_t hint, hipStream_t stream);
+// Whole path on CSR input (m = off[n], read by the caller).
+int run_solve_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, const uint32_t* adj,
+                  uint32_t* L, uint32_t flags, uint32_t hint, hipStream_t stream);
+// Size the zero-root membership bitmap for n and clear it (only z set).
+int zbits_reset(Slot* s, uint64_t n, hipStream_t stream);
 // Copy the status word to the host, clear it, wait for the stream; CC_OK,
-// CC_ERANGE or CC_ENOMEM (a full update log).
+// CC_ERANGE, CC_ENOMEM (a full update log) or CC_EINVAL (bad CSR offsets).
 int slot_sync(Slot* s, hipStream_t stream);
 
 // Tiled zero-root hook (cc_tiled.hip): both membership tests in LDS.

@@ -303,35 +303,16 @@ __device__ __forceinline__ void log_append(const uint32_t (&child)[kEPT],
     if (full) atomicOr(&st->status, kStatusLogFull);
 }
 
-// One tile of kBlock*kEPT entries per workgroup; each thread loads its kEPT
-// entries (coalesced, non-temporal: the edge stream must not evict P) and
-// issues all their parent reads before walking any of them.
-// With a zero root (ZR) the membership bitmap is consulted first: an entry
-// whose endpoints are both known to be in z's tree is dropped without reading P
-// (the single-GPU form of treating zero-converged vertices specially, Sec. IV).
-// Bits only go from 0 to 1 and only for vertices in z's tree, so a stale or
-// missing bit just sends the entry down the ordinary path.
-// LOG (plain path only): the links this launch makes are appended to `log`
-// (see log_append).
-template <bool ZR, int SPLIT, bool LOG = false>
-__global__ __launch_bounds__(kBlock) void k_hook(const uint32_t* __restrict__ edges, uint64_t m,
-                                                 uint32_t n, uint32_t* P, uint32_t* zbits,
-                                                 DevState* st, uint32_t* log = nullptr,
-                                                 uint64_t log_cap = 0,
-                                                 unsigned long long* log_count = nullptr) {
+// Hooking of the kEPT entries (u[k], v[k]) a thread holds (entries beyond the
+// input are passed as (0, 0): a self-loop, skipped); z is the zero root (ZR). Shared by the COO and the
+// CSR launches. LOG (plain path only): the links made are appended to `log`
+// (see log_append); every thread of the block must then call it.
+template <bool ZR, int SPLIT, bool LOG>
+__device__ __forceinline__ void hook_entries(uint32_t (&u)[kEPT], uint32_t (&v)[kEPT], uint32_t n,
+                                             uint32_t z, uint32_t* P, uint32_t* zbits,
+                                             DevState* st, uint32_t* log, uint64_t log_cap,
+                                             unsigned long long* log_count) {
     static_assert(!(ZR && LOG), "the update log belongs to the plain path");
-    const uint32_t z = ZR ? ld_agent(&st->zroot) : 0u;
-    const uint64_t tile = (uint64_t)blockIdx.x * (kBlock * kEPT);
-    const u32x2* E = reinterpret_cast<const u32x2*>(edges);
-    uint32_t u[kEPT], v[kEPT];
-#pragma unroll
-    for (int k = 0; k < kEPT; ++k) {
-        const uint64_t e = tile + (uint64_t)k * kBlock + threadIdx.x;
-        u32x2 uv = {0u, 0u};
-        if (e < m) uv = __builtin_nontemporal_load(E + e);
-        u[k] = uv.x;
-        v[k] = uv.y;
-    }
     bool bad = false;
 #pragma unroll
     for (int k = 0; k < kEPT; ++k) {
@@ -388,6 +369,196 @@ __global__ __launch_bounds__(kBlock) void k_hook(const uint32_t* __restrict__ ed
         }
     }
     if (LOG) log_append(child, parent, log, log_cap, log_count, st);
+}
+
+// One tile of kBlock*kEPT entries per workgroup; each thread loads its kEPT
+// entries (coalesced, non-temporal: the edge stream must not evict P) and
+// issues all their parent reads before walking any of them.
+// With a zero root (ZR) the membership bitmap is consulted first: an entry
+// whose endpoints are both known to be in z's tree is dropped without reading P
+// (the single-GPU form of treating zero-converged vertices specially, Sec. IV).
+// Bits only go from 0 to 1 and only for vertices in z's tree, so a stale or
+// missing bit just sends the entry down the ordinary path.
+template <bool ZR, int SPLIT, bool LOG = false>
+__global__ __launch_bounds__(kBlock) void k_hook(const uint32_t* __restrict__ edges, uint64_t m,
+                                                 uint32_t n, uint32_t* P, uint32_t* zbits,
+                                                 DevState* st, uint32_t* log = nullptr,
+                                                 uint64_t log_cap = 0,
+                                                 unsigned long long* log_count = nullptr) {
+    const uint32_t z = ZR ? ld_agent(&st->zroot) : 0u;
+    const uint64_t tile = (uint64_t)blockIdx.x * (kBlock * kEPT);
+    const u32x2* E = reinterpret_cast<const u32x2*>(edges);
+    uint32_t u[kEPT], v[kEPT];
+#pragma unroll
+    for (int k = 0; k < kEPT; ++k) {
+        const uint64_t e = tile + (uint64_t)k * kBlock + threadIdx.x;
+        u32x2 uv = {0u, 0u};
+        if (e < m) uv = __builtin_nontemporal_load(E + e);
+        u[k] = uv.x;
+        v[k] = uv.y;
+    }
+    hook_entries<ZR, SPLIT, LOG>(u, v, n, z, P, zbits, st, log, log_cap, log_count);
+}
+
+// ---- CSR input -------------------------------------------------------------------
+// Row u of a CSR graph holds the entries (u, adj[j]) for j in [off[u], off[u+1]);
+// these are the same unordered pairs as a COO list, sorted by first endpoint,
+// so every consecutive run of a tile shares u (and its parent reads).
+// A workgroup takes kCsrTile consecutive positions and needs the row of each:
+// tstart[t] is the row that holds position t*kCsrTile (written by k_csr_tiles,
+// one thread per row), and the rows that start inside the tile are found by a
+// sweep of the rows between the tile's first and next tile's first row plus a
+// max-scan in LDS. A tile that spans more than kSweepMax rows (long runs of
+// empty rows) searches each position's row instead, so no workgroup's work
+// grows with the length of such runs beyond a logarithm.
+constexpr int kCsrTile = kBlock * kEPT;
+constexpr uint32_t kSweepMax = 4 * kCsrTile;
+
+// Checks the offsets (non-decreasing, off[0] = 0, off[n] = m) and writes the
+// first row of every tile. Indices are clamped so that invalid offsets never
+// make an access leave its array; the result is then only reported.
+__global__ __launch_bounds__(kBlock) void k_csr_tiles(const uint64_t* __restrict__ off, uint64_t n,
+                                                      uint64_t m, uint32_t* __restrict__ tstart,
+                                                      uint64_t ntiles, DevState* st) {
+    bool bad = false;
+    for (uint64_t v = (uint64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
+         v += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t lo = off[v], hi = off[v + 1];
+        if (hi < lo || hi > m || (v == 0 && lo != 0)) { bad = true; continue; }
+        if (hi == lo) continue;
+        for (uint64_t t = (lo + kCsrTile - 1) / kCsrTile; t * kCsrTile < hi && t < ntiles; ++t)
+            tstart[t] = (uint32_t)v;
+    }
+    if (bad) atomicOr(&st->status, kStatusBadOffsets);
+}
+
+// Exact maximum degree from the row lengths (Algorithm 4 reads it from CSR),
+// ties to the lowest ID; one atomic per wave on the packed (count, ~ID) key.
+__global__ __launch_bounds__(kBlock) void k_csr_zmax(const uint64_t* __restrict__ off, uint64_t n,
+                                                     DevState* st) {
+    uint64_t best = 0;
+    for (uint64_t v = (uint64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
+         v += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t lo = off[v], hi = off[v + 1];
+        const uint64_t d = hi > lo ? hi - lo : 0;
+        const uint64_t sel = pack_sel(d > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)d, (uint32_t)v);
+        best = sel > best ? sel : best;
+    }
+    best = wave_max_u64(best);
+    if ((threadIdx.x & 63) == 0 && best)
+        atomicMax((unsigned long long*)&st->zsel, (unsigned long long)best);
+}
+
+__global__ void k_zsel_reset(DevState* st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) st_agent64(&st->zsel, 0);
+}
+
+// Initial Push over the zero root's whole row (Algorithm 4 initial-push loop).
+__global__ __launch_bounds__(kBlock) void k_csr_push(const uint64_t* __restrict__ off,
+                                                     const uint32_t* __restrict__ adj, uint64_t n,
+                                                     uint64_t m, uint32_t* P, uint32_t* zbits,
+                                                     DevState* st) {
+    const uint32_t z = ld_agent(&st->zroot);
+    uint64_t lo = off[z], hi = off[z + 1];
+    if (hi > m) hi = m;
+    bool bad = false;
+    for (uint64_t j = lo + (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < hi;
+         j += (uint64_t)gridDim.x * kBlock) {
+        const uint32_t x = adj[j];
+        if (x >= n) { bad = true; continue; }
+        if (x == z) continue;
+        st_agent(&P[x], z);
+        zbit_set(zbits, x);
+    }
+    if (bad) atomicOr(&st->status, kStatusRange);
+}
+
+template <bool ZR, int SPLIT>
+__global__ __launch_bounds__(kBlock) void k_csr_hook(const uint64_t* __restrict__ off,
+                                                     const uint32_t* __restrict__ adj, uint32_t n,
+                                                     uint64_t m, const uint32_t* __restrict__ tstart,
+                                                     uint64_t ntiles, uint32_t* P, uint32_t* zbits,
+                                                     DevState* st) {
+    __shared__ uint32_t head[kCsrTile];
+    __shared__ uint32_t s_wmax[kBlock / 64];
+    const uint32_t z = ZR ? ld_agent(&st->zroot) : 0u;
+    const uint64_t t = blockIdx.x;
+    const uint64_t p0 = t * kCsrTile;
+    uint32_t ua = tstart[t];
+    uint32_t ub = (t + 1 < ntiles) ? tstart[t + 1] : n - 1;
+    if (ua >= n) ua = n - 1;                            // only with invalid offsets
+    if (ub >= n || ub < ua) ub = ua;
+    uint32_t v[kEPT];
+#pragma unroll
+    for (int k = 0; k < kEPT; ++k) {
+        const uint64_t p = p0 + (uint64_t)k * kBlock + threadIdx.x;
+        v[k] = p < m ? __builtin_nontemporal_load(adj + p) : 0u;
+    }
+    uint32_t u[kEPT];
+    if (ub - ua <= kSweepMax) {
+        for (int i = threadIdx.x; i < kCsrTile; i += kBlock) head[i] = 0;
+        __syncthreads();
+        if (threadIdx.x == 0) head[0] = ua;
+        for (uint64_t x0 = (uint64_t)ua + 1; x0 <= ub; x0 += 4 * kBlock) {
+            uint64_t lo[4], hi[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint64_t x = x0 + r * kBlock + threadIdx.x;
+                const uint64_t xs = x <= ub ? x : ub;
+                lo[r] = off[xs];
+                hi[r] = off[xs + 1];
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint64_t x = x0 + r * kBlock + threadIdx.x;
+                if (x <= ub && lo[r] < hi[r] && lo[r] >= p0 && lo[r] < p0 + kCsrTile)
+                    head[lo[r] - p0] = (uint32_t)x;
+            }
+        }
+        __syncthreads();
+        // inclusive max-scan of head: thread i owns head[4i .. 4i + 3]
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        uint32_t h[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) h[r] = head[4 * threadIdx.x + r];
+#pragma unroll
+        for (int r = 1; r < 4; ++r) h[r] = max(h[r], h[r - 1]);
+        uint32_t incl = h[3];
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl = max(incl, y);
+        }
+        if (lane == 63) s_wmax[wave] = incl;
+        uint32_t before = __shfl_up(incl, 1, 64);
+        if (lane == 0) before = 0;
+        __syncthreads();
+        for (int w = 0; w < wave; ++w) before = max(before, s_wmax[w]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) head[4 * threadIdx.x + r] = max(h[r], before);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kEPT; ++k) u[k] = head[k * kBlock + threadIdx.x];
+    } else {
+        // the last row x in [ua, ub] with off[x] <= p owns p
+#pragma unroll
+        for (int k = 0; k < kEPT; ++k) {
+            const uint64_t p = p0 + (uint64_t)k * kBlock + threadIdx.x;
+            uint32_t lo = ua, hi = ub;
+            while (lo < hi) {
+                const uint32_t mid = lo + (hi - lo + 1) / 2;
+                if (off[mid] <= p) lo = mid;
+                else hi = mid - 1;
+            }
+            u[k] = lo;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kEPT; ++k) {
+        const uint64_t p = p0 + (uint64_t)k * kBlock + threadIdx.x;
+        if (p >= m) u[k] = v[k] = 0;
+    }
+    hook_entries<ZR, SPLIT, false>(u, v, n, z, P, zbits, st, nullptr, 0, nullptr);
 }
 
 // ---- compress (pointer jumping) ----------------------------------------------------
@@ -521,7 +692,7 @@ static uint64_t sample_count(uint64_t m, uint64_t K) { return m <= K ? m : K; }
 
 // Size the membership bitmap for n vertices and clear it (only z set). Marks the
 // slot ready for a zero-root hook when n is the current solve's.
-static int zbits_reset(Slot* s, uint64_t n, hipStream_t stream) {
+int zbits_reset(Slot* s, uint64_t n, hipStream_t stream) {
     const uint64_t words = (n + 31) / 32;
     if (s->zbits_cap < words) {
         CCM_HIP(hipStreamSynchronize(stream));
@@ -707,6 +878,65 @@ int run_canon(Slot* s, uint64_t n, uint32_t* L, hipStream_t stream) {
     k_canon<<<grid_for(n, kBlock, kGridCap), kBlock, 0, stream>>>(L, n, s->st);
     CCM_HIP(hipGetLastError());
     return CC_OK;
+}
+
+int run_solve_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, const uint32_t* adj,
+                  uint32_t* L, uint32_t flags, uint32_t hint, hipStream_t stream) {
+    if (n == 0) return CC_OK;
+    int rc;
+    const bool zr = flags & CC_F_ZROOT;
+    const bool split = !(flags & CC_F_NO_SPLIT);
+    const uint64_t ntiles = (m + kCsrTile - 1) / kCsrTile;
+    if (ntiles > 0x7FFFFFFFull) return fail(CC_EINVAL, "entry count too large for one launch");
+    if (s->csr_tiles_cap < ntiles + 1) {
+        CCM_HIP(hipStreamSynchronize(stream));
+        if (s->csr_tiles) CCM_HIP(hipFree(s->csr_tiles));
+        s->csr_tiles = nullptr;
+        s->csr_tiles_cap = 0;
+        if (hipMalloc(&s->csr_tiles, (ntiles + 1) * sizeof(uint32_t)) != hipSuccess) {
+            (void)hipGetLastError();
+            s->csr_tiles = nullptr;
+            return fail(CC_ENOMEM, "CSR tile table allocation failed");
+        }
+        s->csr_tiles_cap = ntiles + 1;
+    }
+    if ((rc = run_init(s, n, L, stream))) return rc;
+    const uint32_t gn = grid_for(n, kBlock, kGridCap);
+    k_csr_tiles<<<gn, kBlock, 0, stream>>>(off, n, m, s->csr_tiles, ntiles, s->st);
+    CCM_HIP(hipGetLastError());
+    if (zr) {
+        if (flags & CC_F_ZROOT_HINT) {
+            k_zfinish<<<1, 64, 0, stream>>>(s->st, 1, hint);
+        } else {
+            k_zsel_reset<<<1, 64, 0, stream>>>(s->st);
+            if ((rc = cohere(stream))) return rc;
+            k_csr_zmax<<<gn, kBlock, 0, stream>>>(off, n, s->st);
+            if ((rc = cohere(stream))) return rc;
+            k_zfinish<<<1, 64, 0, stream>>>(s->st, 0, 0);
+        }
+        CCM_HIP(hipGetLastError());
+        if ((rc = zbits_reset(s, n, stream))) return rc;
+        k_csr_push<<<64, kBlock, 0, stream>>>(off, adj, n, m, L, s->zbits, s->st);
+        CCM_HIP(hipGetLastError());
+    }
+    if ((rc = cohere(stream))) return rc;
+    if (ntiles) {
+        const uint32_t g = (uint32_t)ntiles;
+        const uint32_t n32 = (uint32_t)n;
+        uint32_t* zb = s->zbits;
+        if (zr && split) k_csr_hook<true, 1><<<g, kBlock, 0, stream>>>(off, adj, n32, m, s->csr_tiles, ntiles, L, zb, s->st);
+        else if (zr) k_csr_hook<true, 0><<<g, kBlock, 0, stream>>>(off, adj, n32, m, s->csr_tiles, ntiles, L, zb, s->st);
+        else if (split) k_csr_hook<false, 1><<<g, kBlock, 0, stream>>>(off, adj, n32, m, s->csr_tiles, ntiles, L, zb, s->st);
+        else k_csr_hook<false, 0><<<g, kBlock, 0, stream>>>(off, adj, n32, m, s->csr_tiles, ntiles, L, zb, s->st);
+        CCM_HIP(hipGetLastError());
+    }
+    if ((rc = cohere(stream))) return rc;
+    if ((rc = run_compress(s, n, L, flags, stream))) return rc;
+    if (zr) {
+        if ((rc = cohere(stream))) return rc;
+        if ((rc = run_canon(s, n, L, stream))) return rc;
+    }
+    return cohere(stream);
 }
 
 int run_solve(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* L,
