@@ -232,3 +232,21 @@ def zroot_csr(offsets) -> int:
     d = np.diff(np.asarray(offsets, dtype=np.int64))
     return int(np.argmax(d)) if d.size and d.max() > 0 else 0
 
+
+# ---- 64-bit vertex IDs (Sec. V: 8-byte IDs at 2^32 vertices and beyond) ----------------
+
+def cc_labels_sparse64(edges) -> tuple[np.ndarray, np.ndarray]:
+    """Labels of a graph whose IDs may exceed 32 bits, on the vertices that occur in
+    an entry: returns (ids, labels), ids sorted ascending, labels[i] = the smallest
+    ID connected to ids[i]. Every other vertex is alone (its label is itself).
+    The occurring IDs are renumbered 0..k-1 in increasing order, labelled by
+    cc_labels, and mapped back; renumbering in order keeps each component's
+    smallest member the smallest."""
+    e = np.asarray(edges, dtype=np.uint64).reshape(-1, 2)
+    ids = np.unique(e)
+    if ids.size >= 2 ** 32:
+        raise OracleError(EINVAL)
+    dense = np.searchsorted(ids, e).astype(np.uint32)
+    lab = cc_labels(ids.size, dense)
+    return ids, ids[lab.astype(np.int64)]
+

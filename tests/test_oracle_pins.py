@@ -319,6 +319,32 @@ def test_csr_star_and_isolated_run():
     np.testing.assert_array_equal(L, want)
 
 
+# ---- 64-bit IDs ---------------------------------------------------------------------
+
+def test_sparse64_by_hand():
+    big = 1 << 40
+    e = [[big + 5, 7], [7, big], [3 << 33, 3 << 33], [(3 << 33) + 1, 1 << 32]]
+    ids, lab = oracle.cc_labels_sparse64(e)
+    got = dict(zip(ids.tolist(), lab.tolist()))
+    assert got == {7: 7, big: 7, big + 5: 7, 1 << 32: 1 << 32, 3 << 33: 3 << 33,
+                   (3 << 33) + 1: 1 << 32}
+
+
+def test_sparse64_against_closure():
+    """Random small graphs on IDs spread over 2^48: labels equal the closure's on the
+    same graph with the IDs written in increasing order as 0..k-1, mapped back."""
+    rng = np.random.default_rng(51)
+    for _ in range(200):
+        k = int(rng.integers(1, 25))
+        pool = np.sort(rng.choice(1 << 48, size=k, replace=False).astype(np.uint64))
+        idx = rng.integers(0, k, size=(int(rng.integers(1, 2 * k)), 2))
+        ids, lab = oracle.cc_labels_sparse64(pool[idx])
+        used = np.unique(idx)
+        np.testing.assert_array_equal(ids, pool[used])
+        L = closure_labels(k, idx.tolist())
+        np.testing.assert_array_equal(lab, pool[L[used]])
+
+
 # ---- Algorithm 3 with the root function R (Formulas 1-2) ----------------------
 
 def test_root_function_jt_closed_form():
