@@ -425,6 +425,33 @@ def bench_csr(cc, torch, ed, n, L_ref, steps=3):
     return out
 
 
+def bench_u64(cc, torch, ed, n, L_ref, steps=3):
+    """8-byte IDs (cc_solve_u64, plain path): the same workload with every ID
+    widened to uint64 (16 B per entry, 8 B per vertex)."""
+    m = ed.shape[0]
+    e64 = ed.to(torch.int64) & 0xFFFFFFFF
+    ctx = cc.Context()
+    stream = torch.cuda.current_stream()
+    L = torch.empty(n, dtype=torch.int64, device="cuda")
+    ctx.solve_u64_async(e64, n, L, stream=stream)
+    assert ctx.sync(stream) == cc.CC_OK
+    ts = []
+    for _ in range(steps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        ctx.solve_u64_async(e64, n, L, stream=stream)
+        b.record(stream)
+        assert ctx.sync(stream) == cc.CC_OK
+        ts.append(a.elapsed_time(b))
+    same = bool(torch.equal(L, L_ref.to(torch.int64) & 0xFFFFFFFF))
+    ctx.close()
+    del e64, L
+    torch.cuda.empty_cache()
+    ms = float(np.median(ts))
+    return {"variant": "plain", "ms_per_step": round(ms, 3),
+            "GTEPS": round(m / (ms * 1e-3) / 1e9, 3), "identical_labels": same}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -472,7 +499,7 @@ def main():
                                      0 if flags else cc.F_ZROOT)
     assert torch.equal(L, L_o), "variants disagree"
     del L_o
-    reducer = upd = csr = None
+    reducer = upd = csr = u64 = None
     if not args.no_extras:
         t1 = time.time()
         reducer = bench_reducer(cc, torch, ed, n, L)
@@ -483,6 +510,9 @@ def main():
         t1 = time.time()
         csr = bench_csr(cc, torch, ed, n, L)
         log(f"csr done in {time.time() - t1:.1f} s")
+        t1 = time.time()
+        u64 = bench_u64(cc, torch, ed, n, L)
+        log(f"u64 done in {time.time() - t1:.1f} s")
 
     alg_bytes = 8 * m + 12 * n
     gteps = m / (ms * 1e-3) / 1e9
@@ -517,6 +547,8 @@ def main():
         line["update_log"] = upd
     if csr is not None:
         line["csr"] = csr
+    if u64 is not None:
+        line["u64_ids"] = u64
     del ed, L
     torch.cuda.empty_cache()
     if not args.no_extras:

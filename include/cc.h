@@ -145,6 +145,18 @@ int cc_solve_async(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edge_lis
 int cc_solve_csr(cc_ctx* ctx, uint64_t n, const uint64_t* offsets, const uint32_t* adj, uint32_t* L,
                  uint32_t flags, uint32_t zroot_hint, void* stream);
 
+/* The plain path (Algorithm 1: init, hook with path splitting, pointer
+   jumping) with 8-byte vertex IDs, for vertex counts at and beyond 2^32
+   (Sec. V switches to 8-byte IDs there).
+     n      vertices, < 2^62 (P takes 8n bytes of device memory)
+     edges  device, 2*m uint64 as (u_i, v_i) pairs, each < n (others set
+            CC_ERANGE at cc_sync and are skipped)
+     L      device, n uint64, written: L_v = smallest ID of v's component
+     flags  0 or CC_F_NO_SPLIT (anything else: CC_EINVAL)
+   Asynchronous on `stream`; status through cc_sync. */
+int cc_solve_u64(cc_ctx* ctx, uint64_t n, uint64_t m, const uint64_t* edges, uint64_t* L,
+                 uint32_t flags, void* stream);
+
 /* Wait for `stream`, then return (and clear) the status accumulated by the
    context's work since the previous cc_sync: CC_OK, CC_ERANGE, CC_ENOMEM
    (an update log of cc_hook_log ran out of capacity) or CC_EINVAL (CSR

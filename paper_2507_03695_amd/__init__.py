@@ -69,6 +69,7 @@ SIGNATURES = {
     "cc_solve_async": (_I32, [_P, _U64, _U64, _P, _P, _U32, _U32, _P]),
     "cc_sync": (_I32, [_P, _P]),
     "cc_solve_csr": (_I32, [_P, _U64, _P, _P, _P, _U32, _U32, _P]),
+    "cc_solve_u64": (_I32, [_P, _U64, _U64, _P, _P, _U32, _P]),
     "cc_init": (_I32, [_P, _U64, _P, _P]),
     "cc_zroot": (_I32, [_P, _U64, _U64, _P, _U32, _U32, _P]),
     "cc_push": (_I32, [_P, _U64, _U64, _P, _P, _P]),
@@ -203,6 +204,19 @@ class Context:
             out = torch.empty(n, dtype=adj.dtype, device=adj.device)
         self.solve_csr_async(offsets, adj, n, out, flags, zroot_hint, stream)
         _check(self.sync(stream), "solve_csr")
+        return out
+
+    def solve_u64_async(self, edges, n, L, flags=0, stream=None):
+        """cc_solve_u64: edges (m, 2) and L (n,) int64 device tensors (IDs as uint64 bits)."""
+        _W = (torch.int64, torch.uint64)
+        _check(self.lib.cc_solve_u64(self._h, n, edges.shape[0], _dptr(edges, _W), _dptr(L, _W),
+                                     flags, _stream(stream)), "cc_solve_u64")
+
+    def solve_u64(self, edges, n, flags=0, out=None, stream=None):
+        if out is None:
+            out = torch.empty(n, dtype=torch.int64, device=edges.device)
+        self.solve_u64_async(edges, n, out, flags, stream)
+        _check(self.sync(stream), "solve_u64")
         return out
 
     def sync(self, stream=None) -> int:

@@ -257,6 +257,17 @@ extern "C" int cc_solve_csr(cc_ctx* ctx, uint64_t n, const uint64_t* offsets, co
     return run_solve_csr(&ctx->slot, n, m, offsets, adj, L, flags, zroot_hint, st);
 }
 
+extern "C" int cc_solve_u64(cc_ctx* ctx, uint64_t n, uint64_t m, const uint64_t* edges, uint64_t* L,
+                            uint32_t flags, void* stream) {
+    if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    if (n >> 62) return fail(CC_EINVAL, "n must be < 2^62");
+    if (n == 0) return CC_OK;
+    if (!L || (m && !edges)) return fail(CC_EINVAL, "NULL L, or NULL edges with m > 0");
+    int rc = set_dev(ctx);
+    if (rc) return rc;
+    return run_solve_w(&ctx->slot, n, m, edges, L, flags, (hipStream_t)stream);
+}
+
 extern "C" int cc_sync(cc_ctx* ctx, void* stream) {
     if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
     int rc = set_dev(ctx);

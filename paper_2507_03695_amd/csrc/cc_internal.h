@@ -117,6 +117,9 @@ int run_solve(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* 
 // Whole path on CSR input (m = off[n], read by the caller).
 int run_solve_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, const uint32_t* adj,
                   uint32_t* L, uint32_t flags, uint32_t hint, hipStream_t stream);
+// Plain path with 64-bit IDs (cc_wide.hip).
+int run_solve_w(Slot* s, uint64_t n, uint64_t m, const uint64_t* edges, uint64_t* L,
+                uint32_t flags, hipStream_t stream);
 // Size the zero-root membership bitmap for n and clear it (only z set).
 int zbits_reset(Slot* s, uint64_t n, hipStream_t stream);
 // Copy the status word to the host, clear it, wait for the stream; CC_OK,
