@@ -131,6 +131,9 @@ bool tiled_eligible(uint64_t n, uint64_t m);
 int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
                    hipStream_t stream);
 void tiled_free(TiledScratch* t);
+// The same on CSR input, where the rows already are the first-endpoint buckets.
+int run_hook_tiled_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, const uint32_t* adj,
+                       uint32_t* P, hipStream_t stream);
 
 // Batched path (cc_batch.hip).
 // Enqueue one persistent launch over G graphs described on the host.

@@ -920,7 +920,19 @@ int run_solve_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, const ui
         CCM_HIP(hipGetLastError());
     }
     if ((rc = cohere(stream))) return rc;
-    if (ntiles) {
+    if (zr && split && !(flags & CC_F_NO_TILE) && tiled_eligible(n, m)) {
+        // as on COO input: a warm-up over the first 1/1024 of the tiles seeds the
+        // bitmap, then the regrouped hook covers every position (the warm-up's
+        // entries again too, which finds them joined)
+        const uint64_t w = ntiles >> 10;
+        if (w) {
+            k_csr_hook<true, 1><<<(uint32_t)w, kBlock, 0, stream>>>(off, adj, (uint32_t)n, m,
+                                                                   s->csr_tiles, ntiles, L,
+                                                                   s->zbits, s->st);
+            CCM_HIP(hipGetLastError());
+        }
+        if ((rc = run_hook_tiled_csr(s, n, m, off, adj, L, stream))) return rc;
+    } else if (ntiles) {
         const uint32_t g = (uint32_t)ntiles;
         const uint32_t n32 = (uint32_t)n;
         uint32_t* zb = s->zbits;

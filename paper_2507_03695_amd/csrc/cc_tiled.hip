@@ -322,6 +322,32 @@ __global__ __launch_bounds__(256) void k_t2_bounds(const uint32_t* __restrict__ 
 // ---- 4b. level-2 partition by the second endpoint's slice ----------------------------------
 constexpr int kWin2 = 256;   // level-1 chunks per gather window (owner index fits a byte)
 
+// The chunk's cnt entries (entry i in e[i / kPartBlock] of thread i % kPartBlock,
+// hist zeroed beforehand) sorted by the second endpoint's slice through LDS and
+// written contiguously to out, with the start of every slice's run in run2T.
+__device__ __forceinline__ void t2_sort_write(const u32x2 (&e)[kPartEPT], uint32_t cnt, int R,
+                                              uint32_t* hist, uint32_t* start, u32x2* stage,
+                                              u32x2* __restrict__ out,
+                                              uint16_t* __restrict__ run2T, uint64_t nch2,
+                                              uint32_t g) {
+    uint16_t rank[kPartEPT];
+#pragma unroll
+    for (int k = 0; k < kPartEPT; ++k) {
+        const uint32_t i = (uint32_t)k * kPartBlock + threadIdx.x;
+        rank[k] = 0xFFFF;
+        if (i < cnt) rank[k] = (uint16_t)atomicAdd(&hist[e[k].y >> kSliceBits], 1u);
+    }
+    __syncthreads();
+    wave_scan_256(hist, start, R);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPartEPT; ++k)
+        if (rank[k] != 0xFFFF) stage[start[e[k].y >> kSliceBits] + rank[k]] = e[k];
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < cnt; i += kPartBlock) out[i] = stage[i];
+    for (int d = threadIdx.x; d <= R; d += kPartBlock) run2T[(uint64_t)d * nch2 + g] = (uint16_t)start[d];
+}
+
 __global__ __launch_bounds__(kPartBlock) void k_t2_part(const uint32_t* __restrict__ t1w,
                                                         const uint16_t* __restrict__ t1h,
                                                         const uint16_t* __restrict__ segT,
@@ -386,23 +412,201 @@ __global__ __launch_bounds__(kPartBlock) void k_t2_part(const uint32_t* __restri
             }
         __syncthreads();
     }
-    uint16_t rank[kPartEPT];
+    t2_sort_write(e, cnt, R, hist, start, stage, tmp2 + obase, run2T, nch2, g);
+}
+
+// ---- CSR input: the rows are the level-1 buckets ---------------------------------
+// On CSR input the entries are already grouped by first endpoint: bucket a is
+// the contiguous range of adj that holds the rows of slice a, so steps 1-3 are
+// replaced by reading the offsets, and the level-2 pass reads adj directly and
+// recovers each position's row (as the CSR hook does). The level-2 buffer uses
+// adj's positions (base2[a] = start of slice a's rows), so steps 5-6 run
+// unchanged. Every bound below is clamped to a monotone sequence inside
+// [0, m], so offsets that are not a valid row index (reported separately) can
+// change the result but never make an access leave its array.
+
+// base2[a] = running maximum of off[a * 2^19] clamped to m (base2[R] = m);
+// cbase = prefix of the chunk counts. One block, R <= 256.
+__global__ __launch_bounds__(256) void k_c_bases(const uint64_t* __restrict__ off, uint64_t n,
+                                                 uint64_t m, int R, uint64_t* __restrict__ base2,
+                                                 uint32_t* __restrict__ cbase) {
+    __shared__ uint64_t s_b[257];
+    __shared__ uint32_t s_c[256];
+    const int a = threadIdx.x;
+    uint64_t lo = 0;
+    if (a < R) {
+        lo = off[(uint64_t)a << kSliceBits];
+        lo = lo < m ? lo : m;
+    }
+    s_b[a] = lo;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {                 // inclusive running maximum
+        const uint64_t x = a >= o ? s_b[a - o] : 0ull;
+        __syncthreads();
+        s_b[a] = s_b[a] > x ? s_b[a] : x;
+        __syncthreads();
+    }
+    if (a == 0) s_b[256] = m;
+    __syncthreads();
+    const uint64_t hi = a + 1 < R ? s_b[a + 1] : m;
+    const uint32_t chunks = a < R ? (uint32_t)((hi - s_b[a] + kC2 - 1) / kC2) : 0u;
+    s_c[a] = chunks;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const uint32_t x = a >= o ? s_c[a - o] : 0u;
+        __syncthreads();
+        s_c[a] += x;
+        __syncthreads();
+    }
+    if (a < R) {
+        base2[a] = s_b[a];
+        cbase[a] = s_c[a] - chunks;
+    }
+    if (a == R - 1) {
+        base2[R] = m;
+        cbase[R] = s_c[a];
+    }
+}
+
+// cfirst[g]: the row holding the first position of level-2 chunk g. One thread
+// per row: it writes the chunks of its slice that start inside it.
+__global__ __launch_bounds__(256) void k_c_first(const uint64_t* __restrict__ off, uint64_t n,
+                                                 const uint64_t* __restrict__ base2,
+                                                 const uint32_t* __restrict__ cbase,
+                                                 uint32_t* __restrict__ cfirst) {
+    for (uint64_t v = (uint64_t)blockIdx.x * 256 + threadIdx.x; v < n;
+         v += (uint64_t)gridDim.x * 256) {
+        const uint64_t a = v >> kSliceBits;
+        const uint64_t B0 = base2[a], B1 = base2[a + 1];
+        uint64_t lo = off[v], hi = off[v + 1];
+        lo = lo > B0 ? lo : B0;
+        hi = hi < B1 ? hi : B1;
+        if (hi <= lo) continue;
+        const uint32_t cb = cbase[a];
+        for (uint64_t t = (lo - B0 + kC2 - 1) / kC2; B0 + t * kC2 < hi; ++t)
+            cfirst[cb + t] = (uint32_t)v;
+    }
+}
+
+constexpr uint32_t kSweepMax2 = 4 * kC2;   // rows a chunk sweeps before it searches instead
+
+__global__ __launch_bounds__(kPartBlock) void k_t2_csr(const uint64_t* __restrict__ off,
+                                                       const uint32_t* __restrict__ adj,
+                                                       uint64_t n, int R,
+                                                       const uint64_t* __restrict__ base2,
+                                                       const uint32_t* __restrict__ cbase,
+                                                       const uint32_t* __restrict__ cfirst,
+                                                       u32x2* __restrict__ tmp2,
+                                                       uint16_t* __restrict__ run2T,
+                                                       uint64_t nch2, DevState* st) {
+    __shared__ u32x2 stage[kC2];
+    __shared__ uint32_t head[kC2];
+    __shared__ uint32_t hist[kMaxSlices + 1];
+    __shared__ uint32_t start[kMaxSlices + 1];
+    __shared__ uint32_t s_w[kPartBlock / 64];
+    __shared__ int s_a;
+    const uint32_t g = blockIdx.x;
+    if (g >= cbase[R]) return;                  // the grid is an upper bound
+    if (threadIdx.x == 0) {                     // the slice whose chunks hold g
+        int lo = 0, hi = R - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (cbase[mid] <= g) lo = mid;
+            else hi = mid - 1;
+        }
+        s_a = lo;
+    }
+    for (int i = threadIdx.x; i <= kMaxSlices; i += kPartBlock) hist[i] = 0;
+    for (int i = threadIdx.x; i < kC2; i += kPartBlock) head[i] = 0;
+    __syncthreads();
+    const int a = s_a;
+    const uint64_t pos0 = base2[a] + (uint64_t)(g - cbase[a]) * kC2;
+    const uint64_t pend = base2[a + 1];
+    const uint32_t cnt = (uint32_t)min<uint64_t>((uint64_t)kC2, pend - pos0);
+    const uint32_t vlo = (uint32_t)a << kSliceBits;
+    const uint32_t vhi = (uint32_t)min<uint64_t>(((uint64_t)a + 1) << kSliceBits, n) - 1;
+    auto clampv = [&](uint32_t x) { return x < vlo ? vlo : (x > vhi ? vhi : x); };
+    const uint32_t ua = clampv(cfirst[g]);
+    uint32_t ub = (g + 1 < cbase[a + 1]) ? clampv(cfirst[g + 1]) : vhi;
+    if (ub < ua) ub = ua;
+    uint32_t v[kPartEPT];
 #pragma unroll
     for (int k = 0; k < kPartEPT; ++k) {
         const uint32_t i = (uint32_t)k * kPartBlock + threadIdx.x;
-        rank[k] = 0xFFFF;
-        if (i < cnt) rank[k] = (uint16_t)atomicAdd(&hist[e[k].y >> kSliceBits], 1u);
+        v[k] = i < cnt ? __builtin_nontemporal_load(adj + pos0 + i) : 0u;
     }
-    __syncthreads();
-    wave_scan_256(hist, start, R);
-    __syncthreads();
+    uint32_t u[kPartEPT];
+    if (ub - ua <= kSweepMax2) {
+        if (threadIdx.x == 0) head[0] = ua;
+        for (uint64_t x0 = (uint64_t)ua + 1; x0 <= ub; x0 += 4 * kPartBlock) {
+            uint64_t lo[4], hi[4];
 #pragma unroll
-    for (int k = 0; k < kPartEPT; ++k)
-        if (rank[k] != 0xFFFF) stage[start[e[k].y >> kSliceBits] + rank[k]] = e[k];
-    __syncthreads();
-    u32x2* out = tmp2 + obase;
-    for (uint32_t i = threadIdx.x; i < cnt; i += kPartBlock) out[i] = stage[i];
-    for (int d = threadIdx.x; d <= R; d += kPartBlock) run2T[(uint64_t)d * nch2 + g] = (uint16_t)start[d];
+            for (int r = 0; r < 4; ++r) {
+                const uint64_t x = x0 + r * kPartBlock + threadIdx.x;
+                const uint64_t xs = x <= ub ? x : ub;
+                lo[r] = off[xs];
+                hi[r] = off[xs + 1];
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint64_t x = x0 + r * kPartBlock + threadIdx.x;
+                if (x <= ub && lo[r] < hi[r] && lo[r] >= pos0 && lo[r] < pos0 + cnt)
+                    head[lo[r] - pos0] = (uint32_t)x;
+            }
+        }
+        __syncthreads();
+        // inclusive max-scan of head: thread i owns head[8i .. 8i + 7]
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        uint32_t h[kPartEPT];
+#pragma unroll
+        for (int r = 0; r < kPartEPT; ++r) h[r] = head[kPartEPT * threadIdx.x + r];
+#pragma unroll
+        for (int r = 1; r < kPartEPT; ++r) h[r] = max(h[r], h[r - 1]);
+        uint32_t incl = h[kPartEPT - 1];
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl = max(incl, y);
+        }
+        if (lane == 63) s_w[wave] = incl;
+        uint32_t before = __shfl_up(incl, 1, 64);
+        if (lane == 0) before = 0;
+        __syncthreads();
+        for (int w = 0; w < wave; ++w) before = max(before, s_w[w]);
+#pragma unroll
+        for (int r = 0; r < kPartEPT; ++r) head[kPartEPT * threadIdx.x + r] = max(h[r], before);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kPartEPT; ++k) u[k] = head[k * kPartBlock + threadIdx.x];
+    } else {
+        // the last row x in [ua, ub] with off[x] <= p owns position p
+#pragma unroll
+        for (int k = 0; k < kPartEPT; ++k) {
+            const uint64_t p = pos0 + (uint64_t)k * kPartBlock + threadIdx.x;
+            uint32_t lo = ua, hi = ub;
+            while (lo < hi) {
+                const uint32_t mid = lo + (hi - lo + 1) / 2;
+                if (off[mid] <= p) lo = mid;
+                else hi = mid - 1;
+            }
+            u[k] = lo;
+        }
+    }
+    bool bad = false;
+    u32x2 e[kPartEPT];
+#pragma unroll
+    for (int k = 0; k < kPartEPT; ++k) {
+        const uint32_t uu = clampv(u[k]);
+        uint32_t vv = v[k];
+        if ((uint32_t)k * kPartBlock + threadIdx.x < cnt && vv >= n) {
+            bad = true;
+            vv = uu;                              // skipped as a self-loop
+        }
+        e[k].x = uu;
+        e[k].y = vv;
+    }
+    if (bad) atomicOr(&st->status, kStatusRange);
+    t2_sort_write(e, cnt, R, hist, start, stage, tmp2 + pos0, run2T, nch2, g);
 }
 
 // ---- 5. the filter over bucket (a, b) with both slices' bitmap words in LDS ---------------
@@ -923,6 +1127,59 @@ int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint3
     k_t4_scan<<<1, kPackBlock, 0, stream>>>(wgcnt, nwg, ipref);
     if ((rc1 = cohere(stream))) return rc1;
     k_t4_hook<<<kHook4Grid, kHook4Block, 0, stream>>>(t1w, t1h, wgoff, wgcnt, ipref, nwg, (int)nbg,
+                                                      P, s->st);
+    CCM_HIP(hipGetLastError());
+    return CC_OK;
+}
+
+// The regrouped zero-root hook on CSR input (steps 4-6 on adj's own buckets).
+int run_hook_tiled_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, const uint32_t* adj,
+                       uint32_t* P, hipStream_t stream) {
+    const int R = (int)((n + (1ull << kSliceBits) - 1) >> kSliceBits);
+    const uint64_t nch2 = m / kC2 + (uint64_t)R + 1;
+    auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
+    const uint64_t b_sw = al(4 * m), b_sh = al(2 * m), b_tmp2 = al(8 * m);
+    const uint64_t b_base2 = al(8 * (R + 1)), b_cbase = al(4 * (R + 1));
+    const uint64_t b_cfirst = al(4 * nch2), b_run2 = al(2 * nch2 * (R + 1));
+    const uint32_t nbg = (uint32_t)((R + kBPerBlock - 1) / kBPerBlock);
+    const uint32_t nwg = (uint32_t)R * nbg;
+    const uint64_t b_wgoff = al(8 * ((uint64_t)nwg + 1)), b_wgcnt = al(4 * (uint64_t)nwg);
+    const uint64_t b_ipref = al(4 * ((uint64_t)nwg + 1));
+    const uint64_t total = b_sw + b_sh + b_tmp2 + b_base2 + b_cbase + b_cfirst + b_run2 + b_wgoff +
+                           b_wgcnt + b_ipref;
+    int rc = grow(reinterpret_cast<void**>(&s->tiled.buf), &s->tiled.cap, total, stream);
+    if (rc) return rc;
+    char* q = s->tiled.buf;
+    uint32_t* sw = reinterpret_cast<uint32_t*>(q); q += b_sw;
+    uint16_t* sh = reinterpret_cast<uint16_t*>(q); q += b_sh;
+    u32x2* tmp2 = reinterpret_cast<u32x2*>(q); q += b_tmp2;
+    uint64_t* base2 = reinterpret_cast<uint64_t*>(q); q += b_base2;
+    uint32_t* cbase = reinterpret_cast<uint32_t*>(q); q += b_cbase;
+    uint32_t* cfirst = reinterpret_cast<uint32_t*>(q); q += b_cfirst;
+    uint16_t* run2 = reinterpret_cast<uint16_t*>(q); q += b_run2;
+    uint64_t* wgoff = reinterpret_cast<uint64_t*>(q); q += b_wgoff;
+    uint32_t* wgcnt = reinterpret_cast<uint32_t*>(q); q += b_wgcnt;
+    uint32_t* ipref = reinterpret_cast<uint32_t*>(q);
+    int rc1;
+    if ((rc1 = cohere(stream))) return rc1;
+    k_c_bases<<<1, 256, 0, stream>>>(off, n, m, R, base2, cbase);
+    if ((rc1 = cohere(stream))) return rc1;
+    const uint64_t gv = std::min<uint64_t>((n + 255) / 256, 8192);
+    k_c_first<<<(uint32_t)gv, 256, 0, stream>>>(off, n, base2, cbase, cfirst);
+    if ((rc1 = cohere(stream))) return rc1;
+    k_t2_csr<<<(uint32_t)nch2, kPartBlock, 0, stream>>>(off, adj, n, R, base2, cbase, cfirst, tmp2,
+                                                       run2, nch2, s->st);
+    if ((rc1 = cohere(stream))) return rc1;
+    k_t3_regions<<<nwg, 256, 0, stream>>>(run2, nch2, R, cbase, wgcnt);
+    if ((rc1 = cohere(stream))) return rc1;
+    k_t3_offsets<<<(uint32_t)((R + 255) / 256), 256, 0, stream>>>(wgcnt, R, base2, wgoff);
+    if ((rc1 = cohere(stream))) return rc1;
+    k_t3_filter<<<nwg, kHook3Block, 0, stream>>>(tmp2, run2, nch2, R, base2, cbase, s->zbits,
+                                                (n + 31) / 32, sw, sh, wgoff, wgcnt, s->st);
+    if ((rc1 = cohere(stream))) return rc1;
+    k_t4_scan<<<1, kPackBlock, 0, stream>>>(wgcnt, nwg, ipref);
+    if ((rc1 = cohere(stream))) return rc1;
+    k_t4_hook<<<kHook4Grid, kHook4Block, 0, stream>>>(sw, sh, wgoff, wgcnt, ipref, nwg, (int)nbg,
                                                       P, s->st);
     CCM_HIP(hipGetLastError());
     return CC_OK;
