@@ -433,20 +433,38 @@ __global__ __launch_bounds__(kBlock) void k_csr_tiles(const uint64_t* __restrict
 }
 
 // Exact maximum degree from the row lengths (Algorithm 4 reads it from CSR),
-// ties to the lowest ID; one atomic per wave on the packed (count, ~ID) key.
+// ties to the lowest ID: the packed (count, ~ID) key is reduced over the
+// workgroup first and takes one atomic per workgroup (atomics on one word
+// serialise), four rows in flight per thread.
 __global__ __launch_bounds__(kBlock) void k_csr_zmax(const uint64_t* __restrict__ off, uint64_t n,
                                                      DevState* st) {
+    __shared__ uint64_t s_best[kBlock / 64];
     uint64_t best = 0;
-    for (uint64_t v = (uint64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
-         v += (uint64_t)gridDim.x * kBlock) {
-        const uint64_t lo = off[v], hi = off[v + 1];
-        const uint64_t d = hi > lo ? hi - lo : 0;
-        const uint64_t sel = pack_sel(d > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)d, (uint32_t)v);
-        best = sel > best ? sel : best;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t v0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x; v0 < n; v0 += 4 * stride) {
+        uint64_t lo[4], hi[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint64_t v = v0 + r * stride;
+            const uint64_t vs = v < n ? v : n - 1;
+            lo[r] = off[vs];
+            hi[r] = off[vs + 1];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint64_t v = v0 + r * stride;
+            const uint64_t d = (v < n && hi[r] > lo[r]) ? hi[r] - lo[r] : 0;
+            const uint64_t sel = pack_sel(d > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)d, (uint32_t)v);
+            best = sel > best ? sel : best;
+        }
     }
     best = wave_max_u64(best);
-    if ((threadIdx.x & 63) == 0 && best)
-        atomicMax((unsigned long long*)&st->zsel, (unsigned long long)best);
+    if ((threadIdx.x & 63) == 0) s_best[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) best = s_best[w] > best ? s_best[w] : best;
+        if (best) atomicMax((unsigned long long*)&st->zsel, (unsigned long long)best);
+    }
 }
 
 __global__ void k_zsel_reset(DevState* st) {
@@ -910,7 +928,7 @@ int run_solve_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, const ui
         } else {
             k_zsel_reset<<<1, 64, 0, stream>>>(s->st);
             if ((rc = cohere(stream))) return rc;
-            k_csr_zmax<<<gn, kBlock, 0, stream>>>(off, n, s->st);
+            k_csr_zmax<<<grid_for(n, 4 * kBlock, 2048), kBlock, 0, stream>>>(off, n, s->st);
             if ((rc = cohere(stream))) return rc;
             k_zfinish<<<1, 64, 0, stream>>>(s->st, 0, 0);
         }

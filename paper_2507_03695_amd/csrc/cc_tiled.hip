@@ -500,7 +500,10 @@ __global__ __launch_bounds__(kPartBlock) void k_t2_csr(const uint64_t* __restric
                                                        uint16_t* __restrict__ run2T,
                                                        uint64_t nch2, DevState* st) {
     __shared__ u32x2 stage[kC2];
-    __shared__ uint32_t head[kC2];
+    // the rows of the positions live in the first half of the sort's staging
+    // area: they are read into registers before t2_sort_write first writes it
+    // (after two barriers), so both fit with two workgroups per CU
+    uint32_t* head = reinterpret_cast<uint32_t*>(stage);
     __shared__ uint32_t hist[kMaxSlices + 1];
     __shared__ uint32_t start[kMaxSlices + 1];
     __shared__ uint32_t s_w[kPartBlock / 64];
