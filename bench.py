@@ -452,6 +452,41 @@ def bench_u64(cc, torch, ed, n, L_ref, steps=3):
             "GTEPS": round(m / (ms * 1e-3) / 1e9, 3), "identical_labels": same}
 
 
+def bench_share30(cc, torch, steps=2):
+    """One machine's share of R-MAT-30 ef16 (entries whose first endpoint lies in the
+    first of 16 equal vertex ranges; n = 2^30 stays global, about 2^30 entries),
+    generated on the device; whole solves on both paths."""
+    import graphgen
+    ed, n = graphgen.rmat30_share_dev()
+    m = ed.shape[0]
+    ctx = cc.Context()
+    stream = torch.cuda.current_stream()
+    out = {"n": n, "m": m}
+    Ls = {}
+    for name, flags in (("zroot", cc.F_ZROOT), ("plain", 0)):
+        L = torch.empty(n, dtype=torch.int32, device="cuda")
+        ctx.solve_async(ed, n, L, flags=flags, stream=stream)
+        assert ctx.sync(stream) == cc.CC_OK
+        ts = []
+        for _ in range(steps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            ctx.solve_async(ed, n, L, flags=flags, stream=stream)
+            b.record(stream)
+            assert ctx.sync(stream) == cc.CC_OK
+            ts.append(a.elapsed_time(b))
+        ms = float(np.median(ts))
+        out[name] = {"ms_per_step": round(ms, 3), "GTEPS": round(m / (ms * 1e-3) / 1e9, 3),
+                     "hbm_roofline_frac_whole_path":
+                         round((8 * m + 12 * n) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+        Ls[name] = L
+    out["identical_labels"] = bool(torch.equal(Ls["zroot"], Ls["plain"]))
+    ctx.close()
+    del ed, Ls
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -552,6 +587,9 @@ def main():
     del ed, L
     torch.cuda.empty_cache()
     if not args.no_extras:
+        t1 = time.time()
+        line["share_rmat30"] = bench_share30(cc, torch)
+        log(f"share done in {time.time() - t1:.1f} s")
         t1 = time.time()
         line["batch"] = bench_batch(cc, torch)
         log(f"batch done in {time.time() - t1:.1f} s")
