@@ -42,7 +42,8 @@ HOOK_KERNELS = {
     "zroot": "cc_hook step: k_hook<ZR> on 1/1024 of the entries, k_t1_part, k_t1_tsum, k_t1_scan, "
              "k_t1_bases, k_t2_bounds, k_t2_part, k_t3_regions, k_t3_offsets, k_t3_filter, k_t4_scan, "
              "k_t4_hook",
-    "plain": "cc_hook step: k_hook<plain>",
+    "plain": "cc_hook step: k_t1_part, k_t1_tsum, k_t1_scan, k_t1_bases, k_t2_bounds, "
+             "k_t2_hookplain",
 }
 
 
@@ -313,9 +314,9 @@ def bench_serve(cc, torch, count=2000, seed=0x2507036950000005):
             "identical_to_fifo": same}
 
 
-def bench_update_log(cc, torch, ed, n, L_ref, hook_plain_ms, g=16, reps=3):
-    """SiskinCC's update log (Sec. III, Algorithm 2). (1) The plain hook over the
-    whole workload with every link appended to a log, against the same hook
+def bench_update_log(cc, torch, ed, n, L_ref, g=16, reps=3):
+    """SiskinCC's update log (Sec. III, Algorithm 2). (1) The direct plain hook over
+    the whole workload with every link appended to a log, against the same hook
     without it; the message count must be n minus the number of components.
     (2) SiskinCC over g shares: each share hooks into its own parent array and
     appends its links to one receive buffer (no compress, no export); the
@@ -328,18 +329,27 @@ def bench_update_log(cc, torch, ed, n, L_ref, hook_plain_ms, g=16, reps=3):
     P = torch.empty(n, dtype=torch.int32, device="cuda")
     buf = torch.empty((n, 2), dtype=torch.int32, device="cuda")
     cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
-    t_log = []
+    t_log, t_direct = [], []
     for rep in range(reps + 1):
+        # the logged hook is the direct (entry-order) hook; its cost is compared
+        # with the same hook without the log
         ctx.init(n, P, stream)
-        cnt.zero_()
         a, b = ev(), ev()
         a.record(stream)
-        ctx.hook_log(ed, n, P, buf, cnt, stream=stream)
+        ctx.hook(ed, n, P, flags=cc.F_NO_TILE, stream=stream)
         b.record(stream)
+        ctx.init(n, P, stream)
+        cnt.zero_()
+        c_, d_ = ev(), ev()
+        c_.record(stream)
+        ctx.hook_log(ed, n, P, buf, cnt, stream=stream)
+        d_.record(stream)
         assert ctx.sync(stream) == cc.CC_OK
         assert int(cnt.item()) == want, (int(cnt.item()), want)
         if rep:
-            t_log.append(a.elapsed_time(b))
+            t_direct.append(a.elapsed_time(b))
+            t_log.append(c_.elapsed_time(d_))
+    hook_plain_ms = float(np.median(t_direct))
     ctx.compress(n, P, stream=stream)
     assert ctx.sync(stream) == cc.CC_OK
     same_single = bool(torch.equal(P, L_ref))
@@ -540,7 +550,7 @@ def main():
         reducer = bench_reducer(cc, torch, ed, n, L)
         log(f"reducer emulation done in {time.time() - t1:.1f} s")
         t1 = time.time()
-        upd = bench_update_log(cc, torch, ed, n, L, hook_o if flags else hook_ms)
+        upd = bench_update_log(cc, torch, ed, n, L)
         log(f"update log done in {time.time() - t1:.1f} s")
         t1 = time.time()
         csr = bench_csr(cc, torch, ed, n, L)

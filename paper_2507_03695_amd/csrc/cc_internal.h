@@ -128,8 +128,10 @@ int slot_sync(Slot* s, hipStream_t stream);
 
 // Tiled zero-root hook (cc_tiled.hip): both membership tests in LDS.
 bool tiled_eligible(uint64_t n, uint64_t m);
+// plain = true: the plain path (key = ID) hooks the first-endpoint buckets in
+// order instead (better locality for the first endpoints' parent reads).
 int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
-                   hipStream_t stream);
+                   hipStream_t stream, bool plain = false);
 void tiled_free(TiledScratch* t);
 // The same on CSR input, where the rows already are the first-endpoint buckets.
 int run_hook_tiled_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, const uint32_t* adj,

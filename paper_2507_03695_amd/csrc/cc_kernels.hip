@@ -797,8 +797,8 @@ int run_hook(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P
     const bool split = !(flags & CC_F_NO_SPLIT);
     if (zr && (!s->zr_ready || s->cur_n != n))
         return fail(CC_EINVAL, "a CC_F_ZROOT hook needs cc_init then cc_zroot on the same n");
-    if (zr && split && !(flags & CC_F_NO_TILE) && tiled_eligible(n, m))
-        return run_hook_tiled(s, n, m, edges, P, stream);
+    if (split && !(flags & CC_F_NO_TILE) && tiled_eligible(n, m))
+        return run_hook_tiled(s, n, m, edges, P, stream, /*plain=*/!zr);
     const uint32_t n32 = (uint32_t)n;
     uint32_t* zb = s->zbits;
     const uint32_t g = (uint32_t)blocks;

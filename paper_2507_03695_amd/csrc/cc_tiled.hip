@@ -348,36 +348,28 @@ __device__ __forceinline__ void t2_sort_write(const u32x2 (&e)[kPartEPT], uint32
     for (int d = threadIdx.x; d <= R; d += kPartBlock) run2T[(uint64_t)d * nch2 + g] = (uint16_t)start[d];
 }
 
-__global__ __launch_bounds__(kPartBlock) void k_t2_part(const uint32_t* __restrict__ t1w,
-                                                        const uint16_t* __restrict__ t1h,
-                                                        const uint16_t* __restrict__ segT,
-                                                        const uint32_t* __restrict__ pre1,
-                                                        uint64_t nch1, int R,
-                                                        const uint32_t* __restrict__ cbase,
-                                                        const uint32_t* __restrict__ desc,
-                                                        u32x2* __restrict__ tmp2,
-                                                        uint16_t* __restrict__ run2T,
-                                                        uint64_t nch2) {
-    __shared__ u32x2 stage[kC2];
-    __shared__ uint8_t owner[kC2];
-    __shared__ uint32_t s_pre[kWin2 + 1];
-    __shared__ uint32_t s_seg[kWin2];
-    __shared__ uint32_t hist[kMaxSlices + 1];
-    __shared__ uint32_t start[kMaxSlices + 1];
-    const uint32_t g = blockIdx.x;
-    if (g >= cbase[R]) return;                  // the grid is an upper bound
+// Gathers level-2 chunk g of slice a from the slice's level-1 segments: entry i
+// of the chunk lands in e[i / kPartBlock] of thread i % kPartBlock as (u, v).
+// Returns the entry count; a and the output offset come back through a_out and
+// obase. Every thread of the block calls it (it uses barriers).
+__device__ __forceinline__ uint32_t t2_gather(uint32_t g, const uint32_t* __restrict__ t1w,
+                                              const uint16_t* __restrict__ t1h,
+                                              const uint16_t* __restrict__ segT,
+                                              const uint32_t* __restrict__ pre1, uint64_t nch1,
+                                              const uint32_t* __restrict__ desc, uint8_t* owner,
+                                              uint32_t* s_pre, uint32_t* s_seg,
+                                              u32x2 (&e)[kPartEPT], int& a_out, uint64_t& obase) {
     const uint4 d0 = reinterpret_cast<const uint4*>(desc)[2 * (uint64_t)g];
     const uint4 d1 = reinterpret_cast<const uint4*>(desc)[2 * (uint64_t)g + 1];
-    for (int i = threadIdx.x; i <= kMaxSlices; i += kPartBlock) hist[i] = 0;
     const uint64_t c0 = d0.x, c1 = d0.y;
     const int a = (int)(d0.z & 0xFFu);
     const uint32_t cnt = d0.z >> 8;
     const uint32_t t = d0.w;
-    const uint64_t obase = (uint64_t)d1.x | ((uint64_t)d1.y << 32);
+    obase = (uint64_t)d1.x | ((uint64_t)d1.y << 32);
+    a_out = a;
     const uint32_t* pre = pre1 + (uint64_t)a * (nch1 + 1);
     const uint32_t vlo = t * (uint32_t)kC2;
     const uint32_t vhi = vlo + cnt;
-    u32x2 e[kPartEPT];
     for (uint64_t cw = c0; cw <= c1; cw += kWin2) {
         const uint32_t nw = (uint32_t)min<uint64_t>((uint64_t)kWin2, c1 - cw + 1);
         for (uint32_t i = threadIdx.x; i <= nw; i += kPartBlock) s_pre[i] = pre[cw + i];
@@ -412,7 +404,78 @@ __global__ __launch_bounds__(kPartBlock) void k_t2_part(const uint32_t* __restri
             }
         __syncthreads();
     }
+    return cnt;
+}
+
+__global__ __launch_bounds__(kPartBlock) void k_t2_part(const uint32_t* __restrict__ t1w,
+                                                        const uint16_t* __restrict__ t1h,
+                                                        const uint16_t* __restrict__ segT,
+                                                        const uint32_t* __restrict__ pre1,
+                                                        uint64_t nch1, int R,
+                                                        const uint32_t* __restrict__ cbase,
+                                                        const uint32_t* __restrict__ desc,
+                                                        u32x2* __restrict__ tmp2,
+                                                        uint16_t* __restrict__ run2T,
+                                                        uint64_t nch2) {
+    __shared__ u32x2 stage[kC2];
+    __shared__ uint8_t owner[kC2];
+    __shared__ uint32_t s_pre[kWin2 + 1];
+    __shared__ uint32_t s_seg[kWin2];
+    __shared__ uint32_t hist[kMaxSlices + 1];
+    __shared__ uint32_t start[kMaxSlices + 1];
+    const uint32_t g = blockIdx.x;
+    if (g >= cbase[R]) return;                  // the grid is an upper bound
+    for (int i = threadIdx.x; i <= kMaxSlices; i += kPartBlock) hist[i] = 0;
+    u32x2 e[kPartEPT];
+    int a;
+    uint64_t obase;
+    const uint32_t cnt = t2_gather(g, t1w, t1h, segT, pre1, nch1, desc, owner, s_pre, s_seg, e, a,
+                                   obase);
     t2_sort_write(e, cnt, R, hist, start, stage, tmp2 + obase, run2T, nch2, g);
+}
+
+// Plain path (key = ID) on the level-1 buckets: each workgroup gathers one
+// level-2 chunk, whose first endpoints all lie in one slice of 2^19 vertices,
+// and hooks it. The workgroups running at one time mostly take consecutive
+// chunks of one slice, so their first endpoints' parent entries (2 MB) stay in
+// L2; only the second endpoints' reads are random over the whole array.
+__global__ __launch_bounds__(kPartBlock) void k_t2_hookplain(const uint32_t* __restrict__ t1w,
+                                                             const uint16_t* __restrict__ t1h,
+                                                             const uint16_t* __restrict__ segT,
+                                                             const uint32_t* __restrict__ pre1,
+                                                             uint64_t nch1, int R,
+                                                             const uint32_t* __restrict__ cbase,
+                                                             const uint32_t* __restrict__ desc,
+                                                             uint32_t* P) {
+    __shared__ uint8_t owner[kC2];
+    __shared__ uint32_t s_pre[kWin2 + 1];
+    __shared__ uint32_t s_seg[kWin2];
+    const uint32_t g = blockIdx.x;
+    if (g >= cbase[R]) return;                  // the grid is an upper bound
+    u32x2 e[kPartEPT];
+    int a;
+    uint64_t obase;
+    const uint32_t cnt = t2_gather(g, t1w, t1h, segT, pre1, nch1, desc, owner, s_pre, s_seg, e, a,
+                                   obase);
+    bool h[kPartEPT];
+    uint32_t pu[kPartEPT], pv[kPartEPT];
+#pragma unroll
+    for (int k = 0; k < kPartEPT; ++k) {
+        h[k] = (uint32_t)k * kPartBlock + threadIdx.x < cnt;
+        if (!h[k]) e[k].x = e[k].y = 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kPartEPT; ++k) {
+        pu[k] = P[e[k].x];
+        pv[k] = P[e[k].y];
+    }
+#pragma unroll
+    for (int k = 0; k < kPartEPT; ++k) {
+        const uint32_t u = e[k].x, v = e[k].y;
+        if (!h[k] || u == v) continue;
+        if (pu[k] == pv[k] || pu[k] == v || pv[k] == u) continue;   // same tree already
+        (void)t_link(P, u, pu[k], v, pv[k], kEmpty);               // no zero root: key = ID
+    }
 }
 
 // ---- CSR input: the rows are the level-1 buckets ---------------------------------
@@ -1048,13 +1111,13 @@ void tiled_free(TiledScratch* t) {
 }
 
 int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
-                   hipStream_t stream) {
-    // Warm-up: the first 1/1024 of the entries go through the direct hook, so
-    // the membership bitmap already holds the core of the zero root's tree when
-    // the first tiles load their slices. (Measured on R-MAT-26: from 1/64 to
-    // 1/4096 the step time barely moves; a longer warm-up trades its own random
-    // accesses for marks the filter would otherwise set.)
-    const uint64_t m0 = m >> 10;
+                   hipStream_t stream, bool plain) {
+    // Warm-up (zero root): the first 1/1024 of the entries go through the direct
+    // hook, so the membership bitmap already holds the core of the zero root's
+    // tree when the first tiles load their slices. (Measured on R-MAT-26: from
+    // 1/64 to 1/4096 the step time barely moves; a longer warm-up trades its own
+    // random accesses for marks the filter would otherwise set.)
+    const uint64_t m0 = plain ? 0 : m >> 10;
     if (m0) {
         int rc0 = run_hook(s, n, m0, edges, P, CC_F_ZROOT | CC_F_NO_TILE, stream);
         if (rc0) return rc0;
@@ -1116,6 +1179,13 @@ int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint3
     k_t2_bounds<<<(uint32_t)((pairs + 255) / 256), 256, 0, stream>>>(pre1, pl.nch1, R, cbase, base2,
                                                                     desc);
     if ((rc1 = cohere(stream))) return rc1;
+    if (plain) {
+        // the plain path hooks the level-2 chunks as they are gathered
+        k_t2_hookplain<<<(uint32_t)pl.nch2_max, kPartBlock, 0, stream>>>(t1w, t1h, segT, pre1,
+                                                                        pl.nch1, R, cbase, desc, P);
+        CCM_HIP(hipGetLastError());
+        return CC_OK;
+    }
     k_t2_part<<<(uint32_t)pl.nch2_max, kPartBlock, 0, stream>>>(t1w, t1h, segT, pre1, pl.nch1, R,
                                                                cbase, desc, tmp2, run2, pl.nch2_max);
     if ((rc1 = cohere(stream))) return rc1;
