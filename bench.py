@@ -34,8 +34,8 @@ PEAK_HBM_GBS = 8000.0
 # each counter scaled by what it reads for a 4 GiB device copy. Keyed by
 # (workload, variant); valid only for the kernel sources they were taken on.
 TRAFFIC = {
-    ("rmat26", "zroot"): {"bytes": 51695070147,
-                          "src_sha256": "934c3b7615ead04f24e0e70ef6f32b43ae621e238bbf59b90a9dcc5e999a2ff6"},
+    ("rmat26", "zroot"): {"bytes": 51679331168,
+                          "src_sha256": "c718aeae1f9d8d495d51f10427dccc0bd473cb819e532bfc2830fe602879e865"},
 }
 
 HOOK_KERNELS = {
