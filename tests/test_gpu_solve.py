@@ -261,7 +261,8 @@ def test_tiled_hook_parity(case):
     want = oracle.cc_labels(n, e)
     ed = to_dev(e)
     with cc.Context() as c:
-        for name, fl in [("tiled", cc.F_ZROOT), ("direct", cc.F_ZROOT | cc.F_NO_TILE)]:
+        for name, fl in [("tiled", cc.F_ZROOT), ("direct", cc.F_ZROOT | cc.F_NO_TILE),
+                         ("plain bucketed", 0), ("plain direct", cc.F_NO_TILE)]:
             L = c.solve(ed, n, flags=fl)
             assert_same_labels(to_host_u32(L), want, f"{case} [{name}]")
 
@@ -272,8 +273,9 @@ def test_tiled_hook_out_of_range():
     e[12345] = (n + 5, 3)
     with cc.Context() as c:
         L = torch.empty(n, dtype=torch.int32, device="cuda")
-        c.solve_async(to_dev(e), n, L, flags=cc.F_ZROOT)
-        assert c.sync() == cc.CC_ERANGE
+        for fl in (cc.F_ZROOT, 0):                 # the zero-root and the plain bucketed hook
+            c.solve_async(to_dev(e), n, L, flags=fl)
+            assert c.sync() == cc.CC_ERANGE, fl
 
 
 def test_compress_never_trusts_a_stale_root():
