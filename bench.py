@@ -374,7 +374,9 @@ def bench_update_log(cc, torch, ed, n, L_ref, g=16, reps=3):
         assert ctx.sync(stream) == cc.CC_OK
         sent = int(cnt.item())
         ctx.init(n, P, stream)
-        ctx.hook(recv[:sent], n, P, stream=stream)
+        # a message list: every vertex recurs once per share, so it is hooked in
+        # the given order (grouping it by first endpoint makes the links contend)
+        ctx.hook(recv[:sent], n, P, flags=cc.F_NO_TILE, stream=stream)
         ctx.compress(n, P, stream=stream)
         e2.record(stream)
         assert ctx.sync(stream) == cc.CC_OK

@@ -72,10 +72,16 @@ int cc_version(void);
 #define CC_F_ZROOT_HINT   0x4u
 /* Plain root walks without path splitting (Algorithm 1's finds as printed). */
 #define CC_F_NO_SPLIT     0x8u
-/* With CC_F_ZROOT: keep the direct hook (bitmap tests in L2) even where the
-   tiled hook applies (2 <= ceil(n / 2^19) <= 256 and 2^24 <= m < 2^32), which
-   first regroups the entries by the vertex ranges of both endpoints so that
-   both membership tests read LDS. Labels are identical either way. */
+/* Keep the direct hook, which takes the entries in their given order, where
+   the regrouped hooks would apply (2 <= ceil(n / 2^19) <= 256 and
+   2^24 <= m < 2^32, path splitting on). With CC_F_ZROOT the regrouped hook
+   sorts the entries by the vertex ranges of both endpoints so that both
+   membership tests read LDS; without it, the plain hook takes the entries
+   grouped by their first endpoint's range, so that those parent reads stay in
+   L2. Labels are identical either way. Pass it for lists in which a vertex
+   recurs in many entries at once, such as a Reducer's messages from several
+   shares: grouped, their links contend for the same roots (R-MAT-26's 165 M
+   SiskinCC messages: 4.6 ms in the given order, 13 ms grouped). */
 #define CC_F_NO_TILE      0x10u
 
 /* ---- context ----------------------------------------------------------- */
