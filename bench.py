@@ -507,7 +507,12 @@ def main():
     ap.add_argument("--workload", default="rmat26", choices=["rmat26", "rmat22", "er65k"])
     ap.add_argument("--variant", default="zroot", choices=["zroot", "plain"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batch and serve lines")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip every section after the headline and the other variant")
+    ap.add_argument("--only", default=None,
+                    choices=["reducer", "update_log", "csr", "u64_ids", "share_rmat30", "batch",
+                             "serve"],
+                    help="run just this one further section (for profiling it)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 4 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -546,17 +551,23 @@ def main():
                                      0 if flags else cc.F_ZROOT)
     assert torch.equal(L, L_o), "variants disagree"
     del L_o
+    def want(section):
+        return not args.no_extras and args.only in (None, section)
+
     reducer = upd = csr = u64 = None
-    if not args.no_extras:
+    if want("reducer"):
         t1 = time.time()
         reducer = bench_reducer(cc, torch, ed, n, L)
         log(f"reducer emulation done in {time.time() - t1:.1f} s")
+    if want("update_log"):
         t1 = time.time()
         upd = bench_update_log(cc, torch, ed, n, L)
         log(f"update log done in {time.time() - t1:.1f} s")
+    if want("csr"):
         t1 = time.time()
         csr = bench_csr(cc, torch, ed, n, L)
         log(f"csr done in {time.time() - t1:.1f} s")
+    if want("u64_ids"):
         t1 = time.time()
         u64 = bench_u64(cc, torch, ed, n, L)
         log(f"u64 done in {time.time() - t1:.1f} s")
@@ -598,13 +609,15 @@ def main():
         line["u64_ids"] = u64
     del ed, L
     torch.cuda.empty_cache()
-    if not args.no_extras:
+    if want("share_rmat30"):
         t1 = time.time()
         line["share_rmat30"] = bench_share30(cc, torch)
         log(f"share done in {time.time() - t1:.1f} s")
+    if want("batch"):
         t1 = time.time()
         line["batch"] = bench_batch(cc, torch)
         log(f"batch done in {time.time() - t1:.1f} s")
+    if want("serve"):
         t1 = time.time()
         line["serve"] = bench_serve(cc, torch)
         log(f"serve done in {time.time() - t1:.1f} s")
