@@ -145,7 +145,8 @@ def bench_single(cc, torch, ed, n, m, steps, warmup, flags):
 
 
 def bench_batch(cc, torch, reps=5):
-    """4,096 graphs: one persistent cc_batch launch vs one cc_solve_async per graph."""
+    """4,096 graphs: one persistent cc_batch launch (and its captured graph replayed)
+    vs one cc_solve_async per graph."""
     import graphgen
     b = graphgen.batch_4096()
     vo = torch.from_numpy(b.vtx_off).cuda()
@@ -163,6 +164,21 @@ def bench_batch(cc, torch, reps=5):
         torch.cuda.synchronize()
         ts.append(time.perf_counter() - t0)
     t_batch = float(np.median(ts))
+    # the same batch captured once (host work done at capture) and replayed
+    Lg = torch.empty_like(L)
+    stg = torch.empty_like(st)
+    gr = ctx.batch_graph(vo, eo, ed, Lg, stg)
+    gr.launch()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        gr.launch()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    t_graph = float(np.median(ts))
+    same_graph = bool(torch.equal(Lg, L)) and bool(torch.equal(stg, st))
+    gr.close()
     # per-graph launches on one stream
     L2 = torch.empty_like(L)
     views = [(ed[b.edge_off[g]:b.edge_off[g + 1]], int(b.vtx_off[g + 1] - b.vtx_off[g]),
@@ -185,6 +201,7 @@ def bench_batch(cc, torch, reps=5):
     return {"graphs": b.G, "sum_n": int(b.vtx_off[-1]), "sum_m": m,
             "batched_graphs_per_s": round(b.G / t_batch, 1),
             "batched_ms": round(t_batch * 1e3, 3),
+            "graph_replay_ms": round(t_graph * 1e3, 3), "graph_replay_identical": same_graph,
             "per_graph_launch_graphs_per_s": round(b.G / t_loop, 1),
             "per_graph_launch_ms": round(t_loop * 1e3, 3),
             "speedup": round(t_loop / t_batch, 2), "identical_labels": same}

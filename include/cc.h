@@ -329,6 +329,24 @@ int cc_unpack_ids(cc_ctx* ctx, uint64_t count, const uint8_t* in, uint32_t id_by
 int cc_batch(cc_ctx* ctx, uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,
              const int32_t* edges, int32_t* L, int32_t* status, void* stream);
 
+/* The same batch captured once and replayed. Creation does everything of
+   cc_batch that needs the host (reads and checks the offsets, builds the
+   largest-first work list in its own pinned and device buffers) and captures
+   the rest (the upload of the work list, which also resets the work ticket,
+   and the persistent launch) into a hipGraph; each cc_batch_graph_launch
+   replays it on `stream` asynchronously, with no host work. The graph keeps
+   the pointers it was created with: edges, L and status must stay allocated
+   (their contents may change between launches: a replay labels whatever the
+   edges hold then) until cc_batch_graph_destroy. Launches of one graph must
+   not overlap (they share its work ticket). Errors: as cc_batch at creation;
+   CC_EDEVICE if capture or instantiation fails. */
+typedef struct cc_batch_graph cc_batch_graph;
+int cc_batch_graph_create(cc_ctx* ctx, uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,
+                          const int32_t* edges, int32_t* L, int32_t* status, void* stream,
+                          cc_batch_graph** out);
+int cc_batch_graph_launch(cc_batch_graph* graph, void* stream);
+void cc_batch_graph_destroy(cc_batch_graph* graph);
+
 /* ---- continuous-batching server ------------------------------------------- */
 typedef struct cc_server cc_server;
 

@@ -85,6 +85,9 @@ SIGNATURES = {
     "cc_pack_ids": (_I32, [_P, _U64, _P, _U32, _P, _P]),
     "cc_unpack_ids": (_I32, [_P, _U64, _P, _U32, _P, _P]),
     "cc_batch": (_I32, [_P, _U32, _P, _P, _P, _P, _P, _P]),
+    "cc_batch_graph_create": (_I32, [_P, _U32, _P, _P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
+    "cc_batch_graph_launch": (_I32, [_P, _P]),
+    "cc_batch_graph_destroy": (None, [_P]),
     "cc_serve_open": (_I32, [_P, ctypes.POINTER(_ServeOpts), ctypes.POINTER(_P)]),
     "cc_serve_submit": (_I32, [_P, _U64, _U64, _P, _P, _U32, ctypes.POINTER(_U64)]),
     "cc_serve_wait": (_I32, [_P, _U64, _I64, ctypes.POINTER(ReqStats)]),
@@ -326,6 +329,17 @@ class Context:
         return out
 
     # batch
+    def batch_graph(self, vtx_off, edge_off, edges, L, status, stream=None):
+        """cc_batch_graph_create: capture the batch once; BatchGraph.launch replays it."""
+        h = ctypes.c_void_p()
+        _check(self.lib.cc_batch_graph_create(self._h, vtx_off.numel() - 1,
+                                              _dptr(vtx_off, (torch.int64,)),
+                                              _dptr(edge_off, (torch.int64,)),
+                                              _dptr(edges, (torch.int32,)), _dptr(L, (torch.int32,)),
+                                              _dptr(status, (torch.int32,)), _stream(stream),
+                                              ctypes.byref(h)), "cc_batch_graph_create")
+        return BatchGraph(self, h, (vtx_off, edge_off, edges, L, status))
+
     def batch(self, vtx_off, edge_off, edges, L=None, status=None, stream=None):
         G = vtx_off.numel() - 1
         if L is None:
@@ -337,6 +351,37 @@ class Context:
                                  _dptr(L, (torch.int32,)), _dptr(status, (torch.int32,)),
                                  _stream(stream)), "cc_batch")
         return L, status
+
+
+class BatchGraph:
+    """A captured cc_batch (cc_batch_graph_*). Keeps the tensors it was captured
+    with alive; launch() replays the batch on a stream."""
+
+    def __init__(self, ctx, handle, keep):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self._h = handle
+        self._keep = keep
+
+    def launch(self, stream=None):
+        _check(self.lib.cc_batch_graph_launch(self._h, _stream(stream)), "cc_batch_graph_launch")
+
+    def close(self):
+        if self._h:
+            self.lib.cc_batch_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
 
 class Server:

@@ -436,6 +436,33 @@ extern "C" int cc_get_zroot(cc_ctx* ctx, void* stream, uint32_t* zroot_out) {
 
 // ---- batch -------------------------------------------------------------------------------------
 
+extern "C" int cc_batch_graph_create(cc_ctx* ctx, uint32_t G, const int64_t* vtx_off,
+                                     const int64_t* edge_off, const int32_t* edges, int32_t* L,
+                                     int32_t* status, void* stream, cc_batch_graph** out) {
+    if (!out) return fail(CC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    if (G == 0) return fail(CC_EINVAL, "G must be > 0");
+    if (!vtx_off || !edge_off || !status) return fail(CC_EINVAL, "NULL offsets or status");
+    int rc = set_dev(ctx);
+    if (rc) return rc;
+    void* h = nullptr;
+    rc = batch_graph_create(&ctx->slot, G, vtx_off, edge_off, edges, L, status, (hipStream_t)stream,
+                            &h);
+    if (rc) return rc;
+    *out = reinterpret_cast<cc_batch_graph*>(h);
+    return CC_OK;
+}
+
+extern "C" int cc_batch_graph_launch(cc_batch_graph* g, void* stream) {
+    if (!g) return fail(CC_EINVAL, "graph is NULL");
+    return batch_graph_launch(g, (hipStream_t)stream);
+}
+
+extern "C" void cc_batch_graph_destroy(cc_batch_graph* g) {
+    if (g) batch_graph_destroy(g);
+}
+
 extern "C" int cc_batch(cc_ctx* ctx, uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,
                         const int32_t* edges, int32_t* L, int32_t* status, void* stream) {
     if (!ctx) return fail(CC_EINVAL, "ctx is NULL");

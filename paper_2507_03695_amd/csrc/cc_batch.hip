@@ -246,6 +246,61 @@ static int lds_capacity(int device, size_t* bytes, uint32_t* entries16) {
     return CC_OK;
 }
 
+static int batch_alloc(BatchScratch* bs, uint64_t G) {
+    uint64_t cap = std::max<uint64_t>(G, 1024);
+    if (hipMalloc(&bs->dev, batch_bytes(cap)) != hipSuccess ||
+        hipHostMalloc(&bs->host, batch_bytes(cap), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        batch_scratch_free(bs);
+        return fail(CC_ENOMEM, "batch scratch allocation failed");
+    }
+    bs->cap = cap;
+    return CC_OK;
+}
+
+// Host staging of one launch: the zeroed ticket, the largest-first order (by
+// entries + vertices) and the descriptors, in the device layout.
+static void batch_prepare(BatchScratch* bs, uint32_t G, const GraphDesc* descs) {
+    std::vector<uint32_t> order(G);
+    std::iota(order.begin(), order.end(), 0u);
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        return descs[a].m + (int64_t)descs[a].n > descs[b].m + (int64_t)descs[b].n;
+    });
+    char* h = bs->host;
+    std::memset(h, 0, kTicketBytes);
+    uint32_t* h_order = reinterpret_cast<uint32_t*>(h + kTicketBytes);
+    GraphDesc* h_desc = reinterpret_cast<GraphDesc*>(h + kTicketBytes + ((4 * (uint64_t)G + 63) & ~63ull));
+    std::copy(order.begin(), order.end(), h_order);
+    std::copy(descs, descs + G, h_desc);
+}
+
+// The device part of one launch: upload of the staging (which also zeroes the
+// ticket, so a captured copy of this sequence replays correctly), the
+// persistent kernel, and the coherence points around it. Only stream work: it
+// can be captured into a graph.
+static int batch_enqueue(int device, BatchScratch* bs, uint32_t G, hipStream_t stream) {
+    const size_t bytes = batch_bytes(G);
+    CCM_HIP(hipMemcpyAsync(bs->dev, bs->host, bytes, hipMemcpyHostToDevice, stream));
+    size_t lds_bytes = 0;
+    uint32_t lds_cap = 0;
+    int rc = lds_capacity(device, &lds_bytes, &lds_cap);
+    if (rc) return rc;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    (void)hipGetLastError();
+    const int cus = device_cu_count(device);
+    const uint32_t grid = (uint32_t)std::min<int64_t>((int64_t)cus, (int64_t)G);
+    char* d = bs->dev;
+    const uint64_t desc_off = kTicketBytes + ((4 * (uint64_t)G + 63) & ~63ull);
+    rc = cohere(stream);
+    if (rc) return rc;
+    k_batch<<<grid, kBatchBlock, lds_bytes, stream>>>(
+        G, reinterpret_cast<const GraphDesc*>(d + desc_off),
+        reinterpret_cast<const uint32_t*>(d + kTicketBytes), reinterpret_cast<uint32_t*>(d), lds_cap);
+    CCM_HIP(hipGetLastError());
+    return cohere(stream);
+}
+
 // The host staging is reused per call: the caller waits for the previous launch
 // on this slot (its upload) before the next one.
 int launch_batch(Slot* s, uint32_t G, const GraphDesc* descs, hipStream_t stream) {
@@ -255,50 +310,17 @@ int launch_batch(Slot* s, uint32_t G, const GraphDesc* descs, hipStream_t stream
         // the previous launch on this slot must be done with the staging
         CCM_HIP(hipStreamSynchronize(stream));
         batch_scratch_free(&bs);
-        uint64_t cap = std::max<uint64_t>(G, 1024);
-        if (hipMalloc(&bs.dev, batch_bytes(cap)) != hipSuccess ||
-            hipHostMalloc(&bs.host, batch_bytes(cap), hipHostMallocDefault) != hipSuccess) {
-            (void)hipGetLastError();
-            batch_scratch_free(&bs);
-            return fail(CC_ENOMEM, "batch scratch allocation failed");
-        }
-        bs.cap = cap;
+        int rc = batch_alloc(&bs, G);
+        if (rc) return rc;
     }
-    // largest-first by work (entries + vertices)
-    std::vector<uint32_t> order(G);
-    std::iota(order.begin(), order.end(), 0u);
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
-        return descs[a].m + (int64_t)descs[a].n > descs[b].m + (int64_t)descs[b].n;
-    });
-    char* h = bs.host;
-    std::memset(h, 0, kTicketBytes);
-    uint32_t* h_order = reinterpret_cast<uint32_t*>(h + kTicketBytes);
-    GraphDesc* h_desc = reinterpret_cast<GraphDesc*>(h + kTicketBytes + ((4 * (uint64_t)G + 63) & ~63ull));
-    std::copy(order.begin(), order.end(), h_order);
-    std::copy(descs, descs + G, h_desc);
-    const size_t bytes = batch_bytes(G);
-    CCM_HIP(hipMemcpyAsync(bs.dev, h, bytes, hipMemcpyHostToDevice, stream));
-    size_t lds_bytes = 0;
-    uint32_t lds_cap = 0;
-    int rc = lds_capacity(s->device, &lds_bytes, &lds_cap);
-    if (rc) return rc;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-    (void)hipGetLastError();
-    const int cus = device_cu_count(s->device);
-    const uint32_t grid = (uint32_t)std::min<int64_t>((int64_t)cus, (int64_t)G);
-    char* d = bs.dev;
-    rc = cohere(stream);
-    if (rc) return rc;
-    k_batch<<<grid, kBatchBlock, lds_bytes, stream>>>(
-        G, reinterpret_cast<const GraphDesc*>(d + ((char*)h_desc - h)),
-        reinterpret_cast<const uint32_t*>(d + kTicketBytes), reinterpret_cast<uint32_t*>(d), lds_cap);
-    CCM_HIP(hipGetLastError());
-    return cohere(stream);
+    batch_prepare(&bs, G, descs);
+    return batch_enqueue(s->device, &bs, G, stream);
 }
 
-int run_batch(Slot* s, uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,
-              const int32_t* edges, int32_t* L, int32_t* status, hipStream_t stream) {
+// Offsets read back and checked, descriptors built (cc_batch's arguments).
+static int batch_descs(uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,
+                       const int32_t* edges, int32_t* L, int32_t* status, hipStream_t stream,
+                       std::vector<GraphDesc>* out) {
     std::vector<int64_t> vo(G + 1), eo(G + 1);
     CCM_HIP(hipMemcpyAsync(vo.data(), vtx_off, (G + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, stream));
     CCM_HIP(hipMemcpyAsync(eo.data(), edge_off, (G + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, stream));
@@ -310,17 +332,97 @@ int run_batch(Slot* s, uint32_t G, const int64_t* vtx_off, const int64_t* edge_o
     }
     if (eo[G] && !edges) return fail(CC_EINVAL, "edges is NULL");
     if (vo[G] && !L) return fail(CC_EINVAL, "L is NULL");
-    std::vector<GraphDesc> descs(G);
+    out->resize(G);
     for (uint32_t g = 0; g < G; ++g) {
-        descs[g].edges = edges + 2 * eo[g];
-        descs[g].L = L + vo[g];
-        descs[g].status = status + g;
-        descs[g].n = (uint32_t)(vo[g + 1] - vo[g]);
-        descs[g].pad = 0;
-        descs[g].m = eo[g + 1] - eo[g];
+        GraphDesc& d = (*out)[g];
+        d.edges = edges + 2 * eo[g];
+        d.L = L + vo[g];
+        d.status = status + g;
+        d.n = (uint32_t)(vo[g + 1] - vo[g]);
+        d.pad = 0;
+        d.m = eo[g + 1] - eo[g];
     }
-    int rc = launch_batch(s, G, descs.data(), stream);
+    return CC_OK;
+}
+
+// A captured batch: its own staging and device copy of the work list (so later
+// cc_batch calls on the context cannot change what a replay uploads), and the
+// instantiated graph of batch_enqueue.
+struct BatchGraph {
+    int device = 0;
+    BatchScratch bs;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+int batch_graph_create(Slot* s, uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,
+                       const int32_t* edges, int32_t* L, int32_t* status, hipStream_t stream,
+                       void** out) {
+    *out = nullptr;
+    std::vector<GraphDesc> descs;
+    int rc = batch_descs(G, vtx_off, edge_off, edges, L, status, stream, &descs);
     if (rc) return rc;
+    BatchGraph* bg = new BatchGraph;
+    bg->device = s->device;
+    if ((rc = batch_alloc(&bg->bs, G))) {
+        delete bg;
+        return rc;
+    }
+    batch_prepare(&bg->bs, G, descs.data());
+    // capture on a private stream of default priority (the null stream cannot be
+    // captured); nothing else runs on it
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        batch_scratch_free(&bg->bs);
+        delete bg;
+        return fail(CC_EDEVICE, "capture stream creation failed");
+    }
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        rc = batch_enqueue(bg->device, &bg->bs, G, cs);
+        hipGraph_t gr = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(cs, &gr);
+        bg->graph = gr;
+        if (!rc && e2 != hipSuccess) rc = hip_fail(e2, "hipStreamEndCapture");
+        if (!rc && hipGraphInstantiate(&bg->exec, bg->graph, nullptr, nullptr, 0) != hipSuccess)
+            rc = fail(CC_EDEVICE, "graph instantiation failed");
+    } else {
+        rc = hip_fail(e, "hipStreamBeginCapture");
+    }
+    (void)hipStreamDestroy(cs);
+    if (rc) {
+        (void)hipGetLastError();
+        batch_graph_destroy(bg);
+        return rc;
+    }
+    *out = bg;
+    return CC_OK;
+}
+
+int batch_graph_launch(void* h, hipStream_t stream) {
+    BatchGraph* bg = static_cast<BatchGraph*>(h);
+    CCM_HIP(hipSetDevice(bg->device));
+    CCM_HIP(hipGraphLaunch(bg->exec, stream));
+    return CC_OK;
+}
+
+void batch_graph_destroy(void* h) {
+    BatchGraph* bg = static_cast<BatchGraph*>(h);
+    if (!bg) return;
+    (void)hipSetDevice(bg->device);
+    if (bg->exec) (void)hipGraphExecDestroy(bg->exec);
+    if (bg->graph) (void)hipGraphDestroy(bg->graph);
+    batch_scratch_free(&bg->bs);
+    delete bg;
+}
+
+int run_batch(Slot* s, uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,
+              const int32_t* edges, int32_t* L, int32_t* status, hipStream_t stream) {
+    std::vector<GraphDesc> descs;
+    int rc = batch_descs(G, vtx_off, edge_off, edges, L, status, stream, &descs);
+    if (rc) return rc;
+    if ((rc = launch_batch(s, G, descs.data(), stream))) return rc;
     CCM_HIP(hipStreamSynchronize(stream));
     return CC_OK;
 }

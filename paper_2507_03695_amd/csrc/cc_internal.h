@@ -144,6 +144,13 @@ int launch_batch(Slot* s, uint32_t G, const GraphDesc* descs, hipStream_t stream
 int run_batch(Slot* s, uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,
               const int32_t* edges, int32_t* L, int32_t* status, hipStream_t stream);
 void batch_scratch_free(BatchScratch* b);
+// A captured cc_batch (opaque handle): creation reads and checks the offsets
+// like cc_batch and captures the upload and the launch into a graph.
+int batch_graph_create(Slot* s, uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,
+                       const int32_t* edges, int32_t* L, int32_t* status, hipStream_t stream,
+                       void** out);
+int batch_graph_launch(void* g, hipStream_t stream);
+void batch_graph_destroy(void* g);
 
 // Error reporting.
 int fail(int code, const std::string& detail);

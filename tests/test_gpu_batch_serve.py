@@ -38,6 +38,52 @@ def test_batch_small_mix(ctx):
     assert_same_labels(L.cpu().numpy().view(np.uint32), want.view(np.uint32), "batch small mix")
 
 
+def test_batch_graph_replays(ctx):
+    """A captured batch replayed three times, with eager work between replays
+    (labels and status clobbered, another batch run eagerly, the edges changed
+    in place): every replay equals the oracle on the edges it saw."""
+    graphs = [(graphgen.rmat(17, 1 << 19, 31), 90_000),           # above 2^16: HBM path
+              (np.zeros((0, 2), np.uint32), 7)]
+    graphs[0] = (graphs[0][0] % 90_000, 90_000)
+    small = graphgen.batch(200, 18, lg_n_lo=0, lg_n_hi=14, deg_lo=0, deg_hi=24)
+    for g in range(small.G):
+        e = small.edges[small.edge_off[g]:small.edge_off[g + 1]]
+        graphs.append((e, int(small.vtx_off[g + 1] - small.vtx_off[g])))
+    b = graphgen.batch_from_graphs(graphs)
+    vo, eo, ed = batch_to_dev(b)
+    L = torch.empty(int(b.vtx_off[-1]), dtype=torch.int32, device="cuda")
+    st = torch.empty(b.G, dtype=torch.int32, device="cuda")
+    host_edges = b.edges.copy()
+    with ctx.batch_graph(vo, eo, ed, L, st) as gr:
+        other = graphgen.batch(50, 19, lg_n_lo=4, lg_n_hi=12)
+        for rep in range(3):
+            if rep == 1:                               # graph 5 loses its entries (self-loops)
+                lo, hi = int(b.edge_off[5]), int(b.edge_off[6])
+                host_edges[lo:hi] = 0
+                ed[lo:hi] = 0
+            if rep == 2:                               # graph 9 gets an out-of-range entry
+                lo, hi = int(b.edge_off[9]), int(b.edge_off[10])
+                n9 = int(b.vtx_off[10] - b.vtx_off[9])
+                if hi > lo:
+                    host_edges[lo] = (n9 + 3, 0)
+                    ed[lo, 0] = n9 + 3
+            L.fill_(-1)
+            st.fill_(7)
+            ovo, oeo, oed = batch_to_dev(other)
+            ctx.batch(ovo, oeo, oed)                   # eager work in between
+            torch.cuda.synchronize()
+            gr.launch()
+            torch.cuda.synchronize()
+            want, wst = oracle.cc_labels_batch(b.vtx_off, b.edge_off, host_edges)
+            got_st = st.cpu().numpy()
+            assert np.array_equal(got_st, wst), f"replay {rep}: status"
+            ok = np.repeat(wst == 0, np.diff(b.vtx_off))
+            assert_same_labels(L.cpu().numpy().view(np.uint32)[ok], want.view(np.uint32)[ok],
+                               f"replay {rep}")
+        if int(b.edge_off[10]) > int(b.edge_off[9]):
+            assert got_st[9] == cc.CC_ERANGE
+
+
 def test_batch_handles_hbm_resident_graphs(ctx):
     """Graphs above the LDS capacity keep their parent array in HBM."""
     graphs = [(graphgen.rmat(17, 1 << 19, 3 + i) % (90_000 + i), 90_000 + i) for i in range(3)]
