@@ -137,3 +137,17 @@ def test_csr_regrouped_zero_root_path():
         for f in (0x1, 0x1 | 0x10):
             assert_same_labels(solve(c, off, adj, n, f), want, f"csr flags {f:#x}")
             assert c.get_zroot() == oracle.zroot_csr(off)
+
+
+def test_csr_regrouped_at_256_slices():
+    """n = 256 * 2^19 (the most slices the regrouped hook takes), 2^24 entries of an
+    R-MAT-27 graph as CSR rows: the regrouped and direct zero-root paths equal the
+    oracle."""
+    n = 256 << 19
+    e = graphgen.rmat(27, 1 << 24, 109)
+    want = oracle.cc_labels(n, e)
+    log("oracle done")
+    off, adj = to_csr(n, e)
+    with cc.Context() as c:
+        for f in (0x1, 0x1 | 0x10):
+            assert_same_labels(solve(c, off, adj, n, f), want, f"csr R=256 flags {f:#x}")
