@@ -592,15 +592,29 @@ __global__ __launch_bounds__(kBlock) void k_csr_hook(const uint64_t* __restrict_
 // cc_tiled.hip), so a tree that holds a marked vertex belongs to z's component.
 // Here every marked vertex passes its mark on to its root; k_resolve then
 // relabels the members of marked trees.
+// Each thread takes kVPT vertices per step of its grid-stride loop and issues
+// their first reads together (one read in flight per thread would leave these
+// whole-array passes latency-bound).
+constexpr int kVPT = 4;
+
 template <bool ZR>
 __global__ __launch_bounds__(kBlock) void k_compress(uint32_t* P, uint64_t n, DevState* st,
                                                      uint32_t* zbits) {
     const uint32_t z = ZR ? ld_agent(&st->zroot) : 0u;
-    for (uint64_t v = (uint64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
-         v += (uint64_t)gridDim.x * kBlock) {
-        const uint32_t p = ld_agent(&P[v]);
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t v0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x; v0 < n; v0 += kVPT * stride) {
+        uint32_t pv[kVPT];
+#pragma unroll
+        for (int i = 0; i < kVPT; ++i) {
+            const uint64_t v = v0 + i * stride;
+            pv[i] = v < n ? ld_agent(&P[v]) : (uint32_t)v;
+        }
+#pragma unroll
+        for (int i = 0; i < kVPT; ++i) {
+        const uint64_t v = v0 + i * stride;
+        const uint32_t p = pv[i];
         uint32_t r = (uint32_t)v;
-        if (p != (uint32_t)v) {
+        if (v < n && p != (uint32_t)v) {
             r = p;
             while (true) {
                 uint32_t q = P[r];
@@ -614,6 +628,7 @@ __global__ __launch_bounds__(kBlock) void k_compress(uint32_t* P, uint64_t n, De
             if (ZR && r != z && ((ld_agent(&zbits[v >> 5]) >> (v & 31)) & 1u))
                 atomicOr(&zbits[r >> 5], 1u << (r & 31));
         }
+        }
     }
 }
 
@@ -625,16 +640,29 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t* P, uint64_t n, Dev
     __shared__ uint32_t s_min[kBlock / 64];
     const uint32_t z = ld_agent(&st->zroot);
     uint32_t local_min = kEmpty;
-    for (uint64_t v = (uint64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
-         v += (uint64_t)gridDim.x * kBlock) {
-        const uint32_t r = ld_agent(&P[v]);
-        bool inz = r == z;
-        if (!inz) {
-            inz = ((ld_agent(&zbits[v >> 5]) >> (v & 31)) & 1u) ||
-                  (r != (uint32_t)v && ((ld_agent(&zbits[r >> 5]) >> (r & 31)) & 1u));
-            if (inz) st_agent(&P[v], z);
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t v0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x; v0 < n; v0 += kVPT * stride) {
+        uint32_t rr[kVPT], bv[kVPT];
+#pragma unroll
+        for (int i = 0; i < kVPT; ++i) {
+            const uint64_t v = v0 + i * stride;
+            const uint64_t vs = v < n ? v : v0;          // v0 < n
+            rr[i] = ld_agent(&P[vs]);
+            bv[i] = ld_agent(&zbits[vs >> 5]);
         }
-        if (inz && (uint32_t)v < local_min) local_min = (uint32_t)v;
+#pragma unroll
+        for (int i = 0; i < kVPT; ++i) {
+            const uint64_t v = v0 + i * stride;
+            if (v >= n) continue;
+            const uint32_t r = rr[i];
+            bool inz = r == z;
+            if (!inz) {
+                inz = ((bv[i] >> (v & 31)) & 1u) ||
+                      (r != (uint32_t)v && ((ld_agent(&zbits[r >> 5]) >> (r & 31)) & 1u));
+                if (inz) st_agent(&P[v], z);
+            }
+            if (inz && (uint32_t)v < local_min) local_min = (uint32_t)v;
+        }
     }
     // the block's smallest member of z's component; k_minz reduces over blocks
     // (one atomic per block on a single word would serialise)
@@ -667,9 +695,17 @@ __global__ __launch_bounds__(1024) void k_minz(const uint32_t* __restrict__ bmin
 __global__ __launch_bounds__(kBlock) void k_canon(uint32_t* L, uint64_t n, const DevState* st) {
     const uint32_t z = ld_agent(&st->zroot), mz = ld_agent(&st->minz);
     if (mz == z || mz == kEmpty) return;
-    for (uint64_t v = (uint64_t)blockIdx.x * kBlock + threadIdx.x; v < n;
-         v += (uint64_t)gridDim.x * kBlock) {
-        if (ld_agent(&L[v]) == z) st_agent(&L[v], mz);
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t v0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x; v0 < n; v0 += kVPT * stride) {
+        uint32_t l[kVPT];
+#pragma unroll
+        for (int i = 0; i < kVPT; ++i) {
+            const uint64_t v = v0 + i * stride;
+            l[i] = v < n ? ld_agent(&L[v]) : kEmpty;
+        }
+#pragma unroll
+        for (int i = 0; i < kVPT; ++i)
+            if (l[i] == z) st_agent(&L[v0 + i * stride], mz);
     }
 }
 
