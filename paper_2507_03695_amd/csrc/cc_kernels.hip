@@ -129,8 +129,10 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
 
 // argmax over (count desc, id asc); ids come from a table (keys != nullptr) or
 // are the indices of a dense count array.
+// One atomic per workgroup on the packed key (atomics on one word serialise).
 __global__ __launch_bounds__(kBlock) void k_zargmax(const uint32_t* keys, const uint32_t* counts,
                                                     uint64_t T, DevState* st) {
+    __shared__ uint64_t s_best[kBlock / 64];
     uint64_t best = 0;
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < T;
          i += (uint64_t)gridDim.x * kBlock) {
@@ -142,8 +144,12 @@ __global__ __launch_bounds__(kBlock) void k_zargmax(const uint32_t* keys, const 
         }
     }
     best = wave_max_u64(best);
-    if ((threadIdx.x & 63) == 0 && best) atomicMax((unsigned long long*)&st->zsel,
-                                                   (unsigned long long)best);
+    if ((threadIdx.x & 63) == 0) s_best[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) best = s_best[w] > best ? s_best[w] : best;
+        if (best) atomicMax((unsigned long long*)&st->zsel, (unsigned long long)best);
+    }
 }
 
 __global__ void k_zfinish(DevState* st, int use_hint, uint32_t hint) {
