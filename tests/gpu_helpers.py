@@ -1,5 +1,6 @@
 """Helpers shared by the GPU tests: moving seeded inputs to the device and
 checking labels against the oracle and against properties that hold at any size."""
+import functools
 import sys
 
 import numpy as np
@@ -41,3 +42,17 @@ def check_properties_on_device(edges_dev: torch.Tensor, L_dev: torch.Tensor, n: 
     ar = torch.arange(n, device=L.device, dtype=torch.int64)
     assert bool((L <= ar).all()), "a label exceeds its vertex"
     assert torch.equal(L[L], L), "a label is not a fixed point"
+
+
+@functools.lru_cache(maxsize=1)
+def rmat26_extras_with_labels():
+    """The R-MAT-26 + extras workload (the bench's) and the oracle's labels of it,
+    computed once per test process and shared by the full-size tests."""
+    import graphgen
+    import oracle
+    g = graphgen.rmat26_extras()
+    log(f"rmat26 generated: n={g.n} m={len(g.edges)}")
+    want = oracle.cc_labels(g.n, g.edges)
+    log("rmat26 oracle done")
+    return g, want
+

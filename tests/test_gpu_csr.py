@@ -8,7 +8,7 @@ import torch
 
 import graphgen
 import oracle
-from gpu_helpers import assert_same_labels, log, to_host_u32
+from gpu_helpers import assert_same_labels, log, rmat26_extras_with_labels, to_dev, to_host_u32
 
 pytestmark = pytest.mark.gpu
 
@@ -151,3 +151,26 @@ def test_csr_regrouped_at_256_slices():
     with cc.Context() as c:
         for f in (0x1, 0x1 | 0x10):
             assert_same_labels(solve(c, off, adj, n, f), want, f"csr R=256 flags {f:#x}")
+
+
+def test_csr_rmat26_extras_full():
+    """The bench's R-MAT-26 + extras workload as CSR rows (built on the device by a
+    stable sort on the first endpoint): both zero-root paths and the plain path
+    equal the oracle's labels."""
+    g, want = rmat26_extras_with_labels()
+    n = g.n
+    ed = to_dev(g.edges)
+    u = ed[:, 0]
+    order = torch.argsort(u, stable=True)
+    adj = ed[:, 1][order].contiguous()
+    del order
+    off = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
+    off[1:] = torch.cumsum(torch.bincount(u, minlength=n), 0)
+    del ed, u
+    with cc.Context() as c:
+        for f in (0x1, 0x1 | 0x10, 0):
+            L = c.solve_csr(off, adj, n, flags=f)
+            assert_same_labels(to_host_u32(L), want, f"csr rmat26 flags {f:#x}")
+            if f & 1:
+                assert c.get_zroot() == oracle.zroot_csr(off.cpu().numpy())
+

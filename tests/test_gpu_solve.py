@@ -7,7 +7,8 @@ import torch
 
 import graphgen
 import oracle
-from gpu_helpers import assert_same_labels, check_properties_on_device, log, to_dev, to_host_u32
+from gpu_helpers import (assert_same_labels, check_properties_on_device, log,
+                         rmat26_extras_with_labels, to_dev, to_host_u32)
 
 pytestmark = pytest.mark.gpu
 
@@ -215,14 +216,16 @@ def test_rmat22_sym_full():
 
 def test_rmat26_extras_full():
     """The RMAT-26 + isolated + paths workload in the bench's launch configuration."""
-    g = graphgen.rmat26_extras()
-    log(f"rmat26 generated: n={g.n} m={len(g.edges)}")
+    g, want = rmat26_extras_with_labels()
     ed = to_dev(g.edges)
     with cc.Context() as c:
         Lz = c.solve(ed, g.n, flags=cc.F_ZROOT)
-        Lp = c.solve(ed, g.n, flags=0)
+        Lp = c.solve(ed, g.n, flags=0)                    # first-endpoint buckets
+        Ld = c.solve(ed, g.n, flags=cc.F_NO_TILE)         # direct entry-order hook
         torch.cuda.synchronize()
         log("rmat26 GPU done")
+        assert torch.equal(Ld, Lp), "direct and bucketed plain hooks disagree"
+        del Ld
         check_properties_on_device(ed, Lz, g.n)
         assert torch.equal(Lz, Lp), "plain and zero-root paths disagree"
         Lh = to_host_u32(Lz)
@@ -231,8 +234,6 @@ def test_rmat26_extras_full():
     assert np.array_equal(Lh[lo:hi], np.arange(lo, hi, dtype=np.uint32))
     for s, ln in zip(g.path_starts[:2000], g.path_lens[:2000]):
         assert np.all(Lh[int(s):int(s) + int(ln)] == s)
-    want = oracle.cc_labels(g.n, g.edges)
-    log("rmat26 oracle done")
     assert_same_labels(Lh, want, "rmat26 extras")
 
 

@@ -8,7 +8,7 @@ import torch
 
 import graphgen
 import oracle
-from gpu_helpers import assert_same_labels, log
+from gpu_helpers import assert_same_labels, log, rmat26_extras_with_labels
 
 pytestmark = pytest.mark.gpu
 
@@ -69,3 +69,14 @@ def test_wide_edges_and_errors():
         with pytest.raises(cc.CCError) as ei:
             c.solve_u64_async(e, 10, L, flags=cc.F_ZROOT)
         assert ei.value.code == cc.CC_EINVAL
+
+
+def test_wide_rmat26_extras_full():
+    """The bench's R-MAT-26 + extras workload with every ID widened to 64 bits."""
+    g, want = rmat26_extras_with_labels()
+    e64 = torch.from_numpy(g.edges.view(np.int32)).cuda().to(torch.int64) & 0xFFFFFFFF
+    with cc.Context() as c:
+        L = c.solve_u64(e64, g.n)
+        got = L.cpu().numpy().view(np.uint64)
+    assert_same_labels(got, want.astype(np.uint64), "u64 rmat26")
+
