@@ -12,7 +12,7 @@ import torch
 
 import graphgen
 import oracle
-from gpu_helpers import assert_same_labels, log, to_dev, to_host_u32
+from gpu_helpers import assert_same_labels, log, rmat26_extras_with_labels, to_dev, to_host_u32
 
 pytestmark = pytest.mark.gpu
 
@@ -126,3 +126,40 @@ def test_siskin_reducer_16_shares():
         c.compress(n, R)
         assert c.sync() == cc.CC_OK
         assert_same_labels(to_host_u32(R), want, "Reducer over the update logs")
+
+
+def test_log_rmat26_extras_full():
+    """The bench's workload: the linked vertices are exactly the oracle's
+    non-minimal vertices (compared as sorted lists on the device), and a Reducer
+    over 16 shares' logs, hooked in their given order, gives the oracle's labels."""
+    g, want = rmat26_extras_with_labels()
+    n = g.n
+    ed = to_dev(g.edges)
+    wd = torch.from_numpy(want.view(np.int32)).cuda()
+    nonmin = torch.nonzero(wd != torch.arange(n, device="cuda", dtype=torch.int32)).flatten()
+    with cc.Context() as c:
+        P, L, cnt = run_log(c, ed, n)
+        assert c.sync() == cc.CC_OK
+        k = int(cnt.item())
+        assert k == nonmin.numel()
+        kids = torch.sort(L[:k, 0].to(torch.int64) & 0xFFFFFFFF).values
+        assert torch.equal(kids, nonmin.to(torch.int64))
+        del P, L
+        g16 = 16
+        u = ed[:, 0].to(torch.int64) & 0xFFFFFFFF
+        share = (u * g16) // n
+        recv = torch.empty((ed.shape[0], 2), dtype=torch.int32, device="cuda")
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        P = torch.empty(n, dtype=torch.int32, device="cuda")
+        for s in range(g16):
+            c.init(n, P)
+            c.hook_log(ed[share == s].contiguous(), n, P, recv, cnt)
+        assert c.sync() == cc.CC_OK
+        sent = int(cnt.item())
+        log(f"siskin messages at full size: {sent}")
+        c.init(n, P)
+        c.hook(recv[:sent], n, P, flags=cc.F_NO_TILE)
+        c.compress(n, P)
+        assert c.sync() == cc.CC_OK
+        assert_same_labels(to_host_u32(P), want, "SiskinCC Reducer, rmat26")
+

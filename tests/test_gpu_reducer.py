@@ -14,7 +14,7 @@ import torch
 
 import graphgen
 import oracle
-from gpu_helpers import assert_same_labels, log, to_dev, to_host_u32
+from gpu_helpers import assert_same_labels, log, rmat26_extras_with_labels, to_dev, to_host_u32
 
 pytestmark = pytest.mark.gpu
 
@@ -149,3 +149,40 @@ def test_hook_ids_plain_and_out_of_range():
         c.init(n, L)
         c.hook_ids(bad, 0, n, L)
         assert c.sync() == cc.CC_ERANGE
+
+
+def test_reducer_rmat26_extras_full():
+    """RobinCC's exchange at the bench's size: 16 shares solved with the global zero
+    root, exported, sent through 4-byte compact IDs, merged by a Reducer; the
+    labels equal the oracle's."""
+    g, want = rmat26_extras_with_labels()
+    n = g.n
+    ed = to_dev(g.edges)
+    u = ed[:, 0].to(torch.int64) & 0xFFFFFFFF
+    share = (u * 16) // n
+    with cc.Context() as c:
+        Pz = torch.empty(n, dtype=torch.int32, device="cuda")
+        c.init(n, Pz)
+        c.zroot(ed, n)
+        z = c.get_zroot()
+        k = c.id_bytes(n)
+        pairs_all, zero_all = [], []
+        for s in range(16):
+            es = ed[share == s].contiguous()
+            solve_share(c, es, n, Pz, z)
+            p, q = c.export_lists(Pz, n, z)
+            pairs_all.append(c.unpack_ids(c.pack_ids(p, k), p.numel(), k).view(-1, 2))
+            zero_all.append(c.unpack_ids(c.pack_ids(q, k), q.numel(), k))
+        pairs = torch.cat(pairs_all)
+        zero = torch.cat(zero_all)
+        log(f"pairs {pairs.shape[0]}, zero IDs {zero.shape[0]}")
+        L = torch.empty(n, dtype=torch.int32, device="cuda")
+        c.init(n, L)
+        c.zroot(pairs, n, flags=cc.F_ZROOT | cc.F_ZROOT_HINT, zroot_hint=z)
+        c.hook(pairs, n, L, flags=cc.F_ZROOT)
+        c.hook_ids(zero, z, n, L, flags=cc.F_ZROOT)
+        c.compress(n, L, flags=cc.F_ZROOT)
+        c.canon(n, L)
+        assert c.sync() == cc.CC_OK
+        assert_same_labels(to_host_u32(L), want, "RobinCC Reducer, rmat26")
+
