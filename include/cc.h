@@ -31,7 +31,7 @@
  *    and change nothing. The input need not be symmetric (Sec. II: processing
  *    (u,v) makes (v,u) a no-op).
  *  - Vertex IDs are 32-bit (Sec. V uses 4-byte IDs below 2^32 vertices), so
- *    n <= 2^32 - 1.
+ *    n <= 2^32 - 1, except in cc_solve_u64, which takes 8-byte IDs.
  *  - Every function returns a status code; on failure a thread-local
  *    description is available from cc_last_error_detail().
  */
@@ -95,8 +95,11 @@ typedef struct cc_ctx_opts {
 } cc_ctx_opts;
 
 /* Create a context on a device: it owns scratch memory (status word, zero
-   root selection state, a sampled-degree hash table), pinned host staging
-   and nothing else. opts may be NULL (defaults). */
+   root selection state, a sampled-degree hash table, per-block minima) and
+   pinned host staging, and grows on demand what larger solves need: the
+   zero-root membership bitmap (n/8 bytes), the buffers of the regrouped hooks
+   (about 14 bytes per entry), the CSR tile tables and the batch work list.
+   opts may be NULL (defaults). */
 int cc_create(cc_ctx** out, const cc_ctx_opts* opts);
 /* Release a context and everything it owns. Waits for its work to finish. */
 void cc_destroy(cc_ctx* ctx);
@@ -137,7 +140,10 @@ int cc_solve_async(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edge_lis
    with the longest row, ties to the lowest ID (Algorithm 4 reads degrees from
    CSR; CC_F_ZROOT_HINT uses zroot_hint instead), and the Initial Push covers
    its whole row. Rows are hooked in order, so runs of entries share their
-   first endpoint's parent reads.
+   first endpoint's parent reads; within the limits of CC_F_NO_TILE's
+   regrouped hooks, the zero-root solve instead takes the regrouped hook with
+   the rows of each vertex range as its first-endpoint buckets (CC_F_NO_TILE
+   keeps the direct one).
      n        vertices, < 2^32
      offsets  device, n+1 uint64, non-decreasing, offsets[0] = 0; m =
               offsets[n] is read back (the call waits for `stream` once, before
