@@ -86,3 +86,26 @@ def test_id_bytes_without_gpu():
     for n in [0, 1, 2, 255, 256, 257, 65535, 65536, 65537, (1 << 24) - 1, 1 << 24, (1 << 24) + 1,
               68109812, 1 << 30, (1 << 32) - 1, 1 << 32]:
         assert lib.cc_id_bytes(n) == oracle.id_bytes(n), n
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus 2 exits with status 2 and says why, before
+    touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_bench_traffic_is_keyed_to_the_hook_sources():
+    """The HBM traffic figure is reported only for the sources it was measured on."""
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    import bench
+    t = bench.TRAFFIC[("rmat26", "zroot")]
+    assert bench.measured_traffic("rmat26", "zroot") in (None, t["bytes"])
+    assert bench.measured_traffic("rmat22", "zroot") is None
