@@ -16,6 +16,8 @@
 // Every store to P is an agent-scope atomic store: plain stores have been
 // observed to leave copies in the writing XCD's L2 that outlive later kernels'
 // writes from other XCDs, so that a later reader on that XCD sees an old value.
+#include <algorithm>
+
 #include "cc_internal.h"
 
 namespace ccm {
@@ -406,6 +408,37 @@ __global__ __launch_bounds__(kBlock) void k_hook(const uint32_t* __restrict__ ed
     hook_entries<ZR, SPLIT, LOG>(u, v, n, z, P, zbits, st, log, log_cap, log_count);
 }
 
+// The same hook confined to one XCD, for parent arrays small enough to live in
+// one XCD's L2. Workgroups are dealt to the eight XCDs in turn (workgroup i runs
+// on XCD i mod 8); here only every eighth workgroup works, so all working
+// workgroups share one L2 and see each other's parent updates there, instead of
+// following copies of the whole (small, hot) array that other XCDs' L2s keep.
+// The working workgroups walk the tiles in a grid-stride loop.
+constexpr uint32_t kXcds = 8;
+
+template <bool ZR, int SPLIT>
+__global__ __launch_bounds__(kBlock) void k_hook_xcd(const uint32_t* __restrict__ edges, uint64_t m,
+                                                     uint32_t n, uint32_t* P, uint32_t* zbits,
+                                                     DevState* st) {
+    if (blockIdx.x % kXcds != 0) return;
+    const uint64_t workers = gridDim.x / kXcds;
+    const uint32_t z = ZR ? ld_agent(&st->zroot) : 0u;
+    const u32x2* E = reinterpret_cast<const u32x2*>(edges);
+    constexpr uint64_t per = (uint64_t)kBlock * kEPT;
+    for (uint64_t t = blockIdx.x / kXcds; t * per < m; t += workers) {
+        uint32_t u[kEPT], v[kEPT];
+#pragma unroll
+        for (int k = 0; k < kEPT; ++k) {
+            const uint64_t e = t * per + (uint64_t)k * kBlock + threadIdx.x;
+            u32x2 uv = {0u, 0u};
+            if (e < m) uv = __builtin_nontemporal_load(E + e);
+            u[k] = uv.x;
+            v[k] = uv.y;
+        }
+        hook_entries<ZR, SPLIT, false>(u, v, n, z, P, zbits, st, nullptr, 0, nullptr);
+    }
+}
+
 // ---- CSR input -------------------------------------------------------------------
 // Row u of a CSR graph holds the entries (u, adj[j]) for j in [off[u], off[u+1]);
 // these are the same unordered pairs as a COO list, sorted by first endpoint,
@@ -733,6 +766,9 @@ int cohere(hipStream_t stream) {
 
 // ---- host-side launchers ---------------------------------------------------------------
 
+constexpr uint64_t kOneXcdMaxN = 1u << 18;   // parent arrays of at most 1 MB
+constexpr uint64_t kOneXcdMinM = 1u << 18;   // and at least this many entries
+
 static uint32_t grid_for(uint64_t work, uint64_t per_block, uint32_t cap) {
     uint64_t g = (work + per_block - 1) / per_block;
     if (g < 1) g = 1;
@@ -844,6 +880,17 @@ int run_hook(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P
     const uint32_t n32 = (uint32_t)n;
     uint32_t* zb = s->zbits;
     const uint32_t g = (uint32_t)blocks;
+    if (!zr && n <= kOneXcdMaxN && m >= kOneXcdMinM && !(flags & CC_F_NO_TILE)) {
+        // plain path, parent array of at most 1 MB, enough entries to keep one XCD
+        // busy (32 CUs, 8 workgroups each): measured 2-3x faster than spreading
+        // the hot array over eight L2s (the zero-root hook gains nothing: its
+        // bitmap tests drop most entries before they touch P)
+        const uint32_t gx = kXcds * (uint32_t)std::min<uint64_t>(blocks, 256);
+        if (split) k_hook_xcd<false, 1><<<gx, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st);
+        else k_hook_xcd<false, 0><<<gx, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st);
+        CCM_HIP(hipGetLastError());
+        return CC_OK;
+    }
     if (zr && split) k_hook<true, 1><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st);
     else if (zr) k_hook<true, 0><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st);
     else if (split) k_hook<false, 1><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st);
