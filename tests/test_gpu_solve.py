@@ -327,3 +327,22 @@ def test_labels_read_back_by_the_next_kernel():
             if want is None:
                 want = host
             assert np.array_equal(host, want), f"rep {rep}: labels changed between solves"
+
+
+@pytest.mark.parametrize("case", ["er_16", "er_18", "rmat_17"])
+def test_small_array_one_xcd_hook(case):
+    """The plain hook on small parent arrays (n <= 2^18, m >= 2^18) runs on one XCD;
+    with and without splitting, ragged entry counts, it equals the oracle and the
+    spread launch (CC_F_NO_TILE)."""
+    if case == "er_16":
+        n, e = 1 << 16, graphgen.er(1 << 16, (1 << 18) + 123, 121)
+    elif case == "er_18":
+        n, e = 1 << 18, graphgen.er(1 << 18, (1 << 20) + 7, 122)
+    else:
+        n, e = 1 << 17, graphgen.rmat(17, (1 << 19) + 999, 123)
+    want = oracle.cc_labels(n, e)
+    ed = to_dev(e)
+    with cc.Context() as c:
+        for fl in (0, cc.F_NO_SPLIT, cc.F_NO_TILE):
+            L = c.solve(ed, n, flags=fl)
+            assert_same_labels(to_host_u32(L), want, f"{case} flags {fl:#x}")
