@@ -530,7 +530,11 @@ __global__ __launch_bounds__(kBlock) void k_csr_push(const uint64_t* __restrict_
     if (bad) atomicOr(&st->status, kStatusRange);
 }
 
-template <bool ZR, int SPLIT>
+// ONE_XCD: the launch has 8 workgroups per working one and only those of XCD 0
+// work, walking the tiles in a grid-stride loop (small parent arrays, as
+// k_hook_xcd); otherwise workgroup t takes tile t only (a launch may cover a
+// prefix of the tiles, as the warm-up does).
+template <bool ZR, int SPLIT, bool ONE_XCD = false>
 __global__ __launch_bounds__(kBlock) void k_csr_hook(const uint64_t* __restrict__ off,
                                                      const uint32_t* __restrict__ adj, uint32_t n,
                                                      uint64_t m, const uint32_t* __restrict__ tstart,
@@ -539,7 +543,13 @@ __global__ __launch_bounds__(kBlock) void k_csr_hook(const uint64_t* __restrict_
     __shared__ uint32_t head[kCsrTile];
     __shared__ uint32_t s_wmax[kBlock / 64];
     const uint32_t z = ZR ? ld_agent(&st->zroot) : 0u;
-    const uint64_t t = blockIdx.x;
+    uint64_t t0 = blockIdx.x, tstep = ntiles;           // one tile per workgroup
+    if (ONE_XCD) {
+        if (blockIdx.x % kXcds != 0) return;
+        t0 = blockIdx.x / kXcds;
+        tstep = gridDim.x / kXcds;
+    }
+    for (uint64_t t = t0; t < ntiles; t += tstep) {
     const uint64_t p0 = t * kCsrTile;
     uint32_t ua = tstart[t];
     uint32_t ub = (t + 1 < ntiles) ? tstart[t + 1] : n - 1;
@@ -616,6 +626,8 @@ __global__ __launch_bounds__(kBlock) void k_csr_hook(const uint64_t* __restrict_
         if (p >= m) u[k] = v[k] = 0;
     }
     hook_entries<ZR, SPLIT, false>(u, v, n, z, P, zbits, st, nullptr, 0, nullptr);
+    __syncthreads();                                    // head of this tile fully used
+    }
 }
 
 // ---- compress (pointer jumping) ----------------------------------------------------
@@ -1039,6 +1051,17 @@ int run_solve_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, const ui
             CCM_HIP(hipGetLastError());
         }
         if ((rc = run_hook_tiled_csr(s, n, m, off, adj, L, stream))) return rc;
+    } else if (ntiles && !zr && n <= kOneXcdMaxN && m >= kOneXcdMinM && !(flags & CC_F_NO_TILE)) {
+        // plain hook of a small parent array: one XCD (see k_hook_xcd)
+        const uint32_t gx = kXcds * (uint32_t)std::min<uint64_t>(ntiles, 256);
+        const uint32_t n32 = (uint32_t)n;
+        if (split)
+            k_csr_hook<false, 1, true><<<gx, kBlock, 0, stream>>>(off, adj, n32, m, s->csr_tiles, ntiles,
+                                                                 L, s->zbits, s->st);
+        else
+            k_csr_hook<false, 0, true><<<gx, kBlock, 0, stream>>>(off, adj, n32, m, s->csr_tiles, ntiles,
+                                                                 L, s->zbits, s->st);
+        CCM_HIP(hipGetLastError());
     } else if (ntiles) {
         const uint32_t g = (uint32_t)ntiles;
         const uint32_t n32 = (uint32_t)n;
