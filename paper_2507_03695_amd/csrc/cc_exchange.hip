@@ -15,6 +15,7 @@ namespace ccm {
 
 constexpr int kXBlock = 256;
 constexpr int kXWaves = kXBlock / 64;
+constexpr int kXRounds = 4;
 
 __global__ __launch_bounds__(kXBlock) void k_export_count(const uint32_t* P, uint64_t n,
                                                           uint64_t span, uint32_t zroot,
@@ -24,11 +25,22 @@ __global__ __launch_bounds__(kXBlock) void k_export_count(const uint32_t* P, uin
     const uint64_t lo = (uint64_t)blockIdx.x * span;
     const uint64_t hi = lo + span < n ? lo + span : n;
     uint32_t cp = 0, cz = 0;
-    for (uint64_t v = lo + threadIdx.x; v < hi; v += kXBlock) {
-        const uint32_t p = ld_agent(&P[v]);
-        if (p != (uint32_t)v) {
-            if (p == zroot) ++cz;
-            else ++cp;
+    // kXRounds reads in flight per thread (one at a time would leave the pass
+    // latency-bound)
+    for (uint64_t v0 = lo + threadIdx.x; v0 < hi; v0 += kXRounds * kXBlock) {
+        uint32_t p[kXRounds];
+#pragma unroll
+        for (int r = 0; r < kXRounds; ++r) {
+            const uint64_t v = v0 + (uint64_t)r * kXBlock;
+            p[r] = v < hi ? ld_agent(&P[v]) : (uint32_t)v;
+        }
+#pragma unroll
+        for (int r = 0; r < kXRounds; ++r) {
+            const uint64_t v = v0 + (uint64_t)r * kXBlock;
+            if (v < hi && p[r] != (uint32_t)v) {
+                if (p[r] == zroot) ++cz;
+                else ++cp;
+            }
         }
     }
     for (int off = 32; off > 0; off >>= 1) {
@@ -95,10 +107,20 @@ __global__ __launch_bounds__(kXBlock) void k_export_write(const uint32_t* P, uin
     const uint64_t lo = (uint64_t)blockIdx.x * span;
     const uint64_t hi = lo + span < n ? lo + span : n;
     uint32_t bp = off[blockIdx.x], bz = off[nb + 1 + blockIdx.x];   // running block offsets
-    for (uint64_t v0 = lo; v0 < hi; v0 += kXBlock) {
+    for (uint64_t g0 = lo; g0 < hi; g0 += kXRounds * kXBlock) {
+    // the reads of kXRounds consecutive 256-vertex rounds first, then the
+    // order-preserving compaction of each round in turn
+    uint32_t pr[kXRounds];
+#pragma unroll
+    for (int r = 0; r < kXRounds; ++r) {
+        const uint64_t v = g0 + (uint64_t)r * kXBlock + threadIdx.x;
+        pr[r] = v < hi ? ld_agent(&P[v]) : (uint32_t)v;
+    }
+#pragma unroll
+    for (int r = 0; r < kXRounds; ++r) {
+        const uint64_t v0 = g0 + (uint64_t)r * kXBlock;
         const uint64_t v = v0 + threadIdx.x;
-        uint32_t p = (uint32_t)v;
-        if (v < hi) p = ld_agent(&P[v]);
+        const uint32_t p = pr[r];
         const bool nonroot = v < hi && p != (uint32_t)v;
         const bool fz = nonroot && p == zroot;
         const bool fp = nonroot && p != zroot;
@@ -130,6 +152,7 @@ __global__ __launch_bounds__(kXBlock) void k_export_write(const uint32_t* P, uin
         bp += tp;
         bz += tz;
         __syncthreads();                          // s_p / s_z of this chunk consumed
+    }
     }
 }
 
