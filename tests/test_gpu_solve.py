@@ -126,6 +126,51 @@ def test_metamorphic(ctx):
         run_all_variants(ctx, ev, n, want, name)
 
 
+def test_vertex_permutation(ctx):
+    """Relabelling the vertices by a permutation pi maps the partition: on the
+    permuted graph each vertex pi(v) is labelled with the smallest pi(w) over
+    the component of v in the original graph (labels derived from the original
+    graph's oracle labels, not from a second oracle call)."""
+    n = 40_000
+    e = graphgen.rmat(16, 200_000, 63) % n
+    want = oracle.cc_labels(n, e)
+    pi = np.random.default_rng(64).permutation(n).astype(np.uint32)
+    low = np.full(n, n, np.int64)
+    np.minimum.at(low, want, pi)
+    expect = np.empty(n, np.uint32)
+    expect[pi] = low[want]
+    run_all_variants(ctx, pi[e], n, expect, "permuted")
+
+
+@pytest.mark.parametrize("size", ["direct", "regrouped"])
+def test_zero_root_choice_does_not_change_labels(ctx, size):
+    """Variant Z: any vertex may be the zero root (the max-degree choice only
+    saves work, Sec. IV), so forcing it through the hint leaves the labels
+    equal to the oracle's: z = 0, n - 1, the true max-degree vertex, a random
+    vertex and an isolated one. "regrouped": 2^24 entries over two vertex
+    slices, the size at which the zero-root hook regroups its entries; with
+    CC_F_NO_SPLIT it takes the direct hook instead."""
+    if size == "direct":
+        n = 50_000
+        e = graphgen.rmat(16, 400_000, 61) % n
+    else:
+        n = 1 << 20
+        e = graphgen.rmat(20, 1 << 24, 62)
+    want = oracle.cc_labels(n, e)
+    deg = np.bincount(e.ravel(), minlength=n)
+    iso = np.flatnonzero(deg == 0)
+    assert len(iso), "the case needs an isolated vertex"
+    rng = np.random.default_rng(65)
+    hints = [0, n - 1, int(np.argmax(deg)), int(rng.integers(n)), int(iso[len(iso) // 2])]
+    ed = to_dev(e)
+    for z in hints:
+        for extra in (0, cc.F_NO_SPLIT):
+            fl = cc.F_ZROOT | cc.F_ZROOT_HINT | extra
+            L = ctx.solve(ed, n, flags=fl, zroot_hint=z)
+            assert ctx.get_zroot() == z
+            assert_same_labels(to_host_u32(L), want, f"{size} z={z} flags={fl:#x}")
+
+
 def test_repeat_stress(ctx):
     """Same input, many runs: the schedule differs, the labels may not."""
     n = 1 << 16

@@ -1,0 +1,362 @@
+"""Interleavings of the hook's per-entry protocol, checked on the CPU.
+
+The hook kernels run Algorithm 1 (Algorithm 3 with the zero root's keys when a
+zero root is used, Sec. IV) with many threads on one parent array. This file
+models the steps one thread takes, in the order the kernels take them:
+
+- a thread holds a few entries; it tests all their bitmap bits, then reads all
+  their endpoints' parents, then hooks them one after the other;
+- the walks use path splitting;
+- a link is a CAS on the root's own entry, retried from the new parent when
+  it fails;
+- an entry found to end in the zero root's tree marks both endpoints in the
+  bitmap.
+
+Every access to the shared arrays is one step, and several such threads run
+under every interleaving (small cases), under every interleaving with few
+preemptions, or under many random schedules.
+
+Every schedule must:
+- give the oracle's labels;
+- link each vertex at most once, only while it is a root, and never one the
+  Initial Push already placed;
+- leave a forest whose parents have smaller keys;
+- set bitmap bits only for vertices in the zero root's tree.
+
+Planted mistakes in the model (a link that is a plain store, a failed CAS
+taken as done, the plain keys with a zero root) must each be caught by one of
+these checks.
+
+The model is sequentially consistent: each step sees every earlier write. The
+device's weaker ordering across its L2 caches is covered by the kernels'
+coherent stores and loads and tested on the device."""
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+
+
+class Shared:
+    """The parent array and the zero root's membership bitmap, plus counters of
+    what the protocol did (for the checks, not part of the method)."""
+
+    def __init__(self, n, z):
+        self.n = n
+        self.z = z                    # None: plain path (Algorithm 1 keys)
+        self.P = list(range(n))
+        self.bit = [False] * n
+        if z is not None:
+            self.bit[z] = True        # the bitmap starts with z alone
+        self.links = [0] * n          # successful link CASes per vertex
+        self.linked_nonroot = False
+        self.pushed = set()
+
+
+def key(x, z):
+    """Algorithm 3's Root-Function keys: the zero root first, then by ID."""
+    if z is None:
+        return x
+    return 0 if x == z else x + 1
+
+
+def find_root(sh, x, px, split):
+    """Root of x, given px read from P[x] earlier; splitting points each visited
+    vertex at its grandparent. Yields before every shared access."""
+    if px == x:
+        return x
+    yield
+    gp = sh.P[px]
+    while gp != px:
+        yield
+        ggp = sh.P[gp]
+        if split:
+            yield
+            sh.P[x] = gp
+        x, px, gp = px, gp, ggp
+    return px
+
+
+def link(sh, u, pu, v, pv, split, bug, keyz):
+    """Join the trees of u and v: the root with the greater key is linked under
+    the other by a CAS that expects it to still be a root."""
+    while True:
+        ru = yield from find_root(sh, u, pu, split)
+        rv = yield from find_root(sh, v, pv, split)
+        if ru == rv:
+            return ru
+        lo, hi = (ru, rv) if key(ru, keyz) < key(rv, keyz) else (rv, ru)
+        yield
+        old = sh.P[hi]                          # the CAS: one indivisible step
+        if bug == "store":
+            if old != hi:
+                sh.linked_nonroot = True
+            sh.P[hi] = lo
+            old = hi
+        elif old == hi:
+            sh.P[hi] = lo
+        if old == hi:
+            sh.links[hi] += 1
+            return lo
+        if bug == "no_retry":
+            return lo
+        u, pu, v, pv = hi, old, lo, lo
+
+
+def thread(sh, entries, split, bug=None):
+    """One thread's entries: bitmap tests, then parent reads, then the hooks."""
+    z = sh.z
+    keyz = None if bug == "plain_keys" else z
+    k = len(entries)
+    live = [u != v for u, v in entries]
+    inu, inv = [False] * k, [False] * k
+    if z is not None:
+        for i, (u, v) in enumerate(entries):
+            if live[i]:
+                yield
+                inu[i] = sh.bit[u]
+                yield
+                inv[i] = sh.bit[v]
+                live[i] = not (inu[i] and inv[i])
+    wu = [z if inu[i] else entries[i][0] for i in range(k)]
+    wv = [z if inv[i] else entries[i][1] for i in range(k)]
+    pu, pv = [0] * k, [0] * k
+    for i in range(k):
+        if not live[i]:
+            continue
+        if inu[i]:
+            pu[i] = z
+        else:
+            yield
+            pu[i] = sh.P[wu[i]]
+        if inv[i]:
+            pv[i] = z
+        else:
+            yield
+            pv[i] = sh.P[wv[i]]
+    for i in range(k):
+        if not live[i]:
+            continue
+        if pu[i] == pv[i]:
+            r = pu[i]
+        elif pu[i] == wv[i]:
+            r = wv[i]
+        elif pv[i] == wu[i]:
+            r = wu[i]
+        else:
+            r = yield from link(sh, wu[i], pu[i], wv[i], pv[i], split, bug, keyz)
+        if z is not None and r == z:
+            u, v = entries[i]
+            if not inu[i]:
+                yield
+                sh.bit[u] = True
+            if not inv[i]:
+                yield
+                sh.bit[v] = True
+
+
+def initial_push(sh, edges):
+    """Sec. IV's Initial Push before the hook: every neighbour of z is placed
+    directly under z and marked."""
+    z = sh.z
+    for u, v in edges:
+        if u == v:
+            continue
+        x = v if u == z else u if v == z else None
+        if x is not None:
+            sh.P[x] = z
+            sh.bit[x] = True
+            sh.pushed.add(x)
+
+
+class Run:
+    """A fresh shared state and its threads, advanced one step at a time."""
+
+    def __init__(self, n, z, per_thread, split, bug=None):
+        self.sh = Shared(n, z)
+        edges = [e for t in per_thread for e in t]
+        if z is not None:
+            initial_push(self.sh, edges)
+        self.gens = {}
+        for t, entries in enumerate(per_thread):
+            g = thread(self.sh, entries, split, bug)
+            try:
+                next(g)                     # up to the first shared access
+                self.gens[t] = g
+            except StopIteration:
+                pass
+
+    def enabled(self):
+        return sorted(self.gens)
+
+    def step(self, t):
+        try:
+            next(self.gens[t])
+        except StopIteration:
+            del self.gens[t]
+
+
+def root(P, x):
+    while P[x] != x:
+        x = P[x]
+    return x
+
+
+def problems(sh, n, edges):
+    """What is wrong with the final state, as a list of strings (empty: fine)."""
+    out = []
+    z = sh.z
+    P = sh.P
+    for x in range(n):
+        if P[x] != x and not key(P[x], z) < key(x, z):
+            out.append(f"parent of {x} is {P[x]}: key not smaller")
+    if out:
+        return out                      # not a forest: the walks below may not end
+    if sh.linked_nonroot or any(c > 1 for c in sh.links):
+        out.append(f"a vertex was linked twice or while not a root: {sh.links}")
+    if any(sh.links[x] for x in sh.pushed):
+        out.append("a pushed vertex was linked again")
+    want = oracle.cc_labels(n, np.asarray(edges, np.uint32).reshape(-1, 2))
+    ncomp = oracle.count_components(want)
+    if sum(sh.links) + len(sh.pushed) != n - ncomp:
+        out.append(f"{sum(sh.links)} links + {len(sh.pushed)} pushed != n - #components")
+    roots = [root(P, x) for x in range(n)]
+    for x in range(n):
+        if sh.bit[x] and roots[x] != z:
+            out.append(f"{x} is marked but its root is {roots[x]}, not z = {z}")
+    low = {}
+    for x in range(n):
+        low.setdefault(roots[x], x)     # x increasing: the first member is the least
+    got = np.array([low[r] for r in roots], np.uint32)
+    if not np.array_equal(got, want):
+        out.append(f"labels {got.tolist()} != oracle {want.tolist()}")
+    return out
+
+
+def replay(case, prefix):
+    r = Run(*case)
+    for t in prefix:
+        r.step(t)
+    return r
+
+
+def all_schedules(case, max_preempt=None):
+    """Every schedule of the case's threads (depth-first, each prefix replayed
+    from a fresh state), optionally only those with at most max_preempt
+    switches away from a thread that could have continued. Yields the final
+    state of each."""
+    stack = [((), None, 0)]
+    while stack:
+        prefix, last, pre = stack.pop()
+        r = replay(case, prefix)
+        en = r.enabled()
+        if not en:
+            yield prefix, r.sh
+            continue
+        for t in en:
+            cost = 1 if (last is not None and t != last and last in en) else 0
+            if max_preempt is not None and pre + cost > max_preempt:
+                continue
+            stack.append((prefix + (t,), t, pre + cost))
+
+
+def random_schedule(case, rng, stick=0.7):
+    r = Run(*case)
+    t = None
+    while True:
+        en = r.enabled()
+        if not en:
+            return r.sh
+        if t not in en or rng.random() > stick:
+            t = rng.choice(en)
+        r.step(t)
+
+
+def first_failure(case, schedules):
+    n, per_thread = case[0], case[2]
+    edges = [e for t in per_thread for e in t]
+    for prefix, sh in schedules:
+        bad = problems(sh, n, edges)
+        if bad:
+            return prefix, bad
+    return None
+
+
+# ---- exhaustive: two threads, tiny graphs ------------------------------------------
+
+TINY = [
+    # (n, z, per-thread entries): z None is the plain path
+    (3, None, [[(2, 0)], [(2, 1)]]),            # two threads link the same root
+    (4, None, [[(3, 1)], [(2, 0)], [(3, 2)]]),
+    (4, None, [[(1, 2), (3, 0)], [(2, 3)]]),
+    (5, None, [[(4, 3), (1, 0)], [(3, 1), (2, 4)]]),
+    (4, 2, [[(0, 1)], [(3, 1)]]),               # zero root with no neighbours pushed
+    (5, 2, [[(2, 0), (1, 3)], [(3, 4), (1, 0)]]),
+    (5, 4, [[(0, 1), (4, 3)], [(1, 3), (2, 0)]]),
+    (6, 0, [[(5, 4), (0, 3)], [(4, 3)], [(1, 2), (2, 5)]]),
+]
+
+
+@pytest.mark.parametrize("split", [True, False])
+@pytest.mark.parametrize("i", range(len(TINY)))
+def test_every_interleaving(i, split):
+    n, z, per_thread = TINY[i]
+    case = (n, z, per_thread, split)
+    bound = None if sum(len(t) for t in per_thread) <= 3 else 3
+    count = 0
+
+    def counted():
+        nonlocal count
+        for s in all_schedules(case, bound):
+            count += 1
+            yield s
+
+    assert first_failure(case, counted()) is None
+    assert count > 1
+
+
+# ---- random: three or four threads, random multigraphs ------------------------------
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_schedules(seed):
+    rng = random.Random(1000 + seed)
+    n = rng.randint(3, 9)
+    m = rng.randint(2, 12)
+    edges = [(rng.randrange(n), rng.randrange(n)) for _ in range(m)]
+    nt = rng.randint(3, 4)
+    per_thread = [edges[t::nt] for t in range(nt)]
+    for z in (None, rng.randrange(n)):
+        for split in (True, False):
+            case = (n, z, per_thread, split)
+            runs = ((None, random_schedule(case, rng)) for _ in range(150))
+            assert first_failure(case, runs) is None, (n, z, per_thread, split)
+
+
+# ---- the checks catch planted mistakes ---------------------------------------------
+
+@pytest.mark.parametrize("bug,case", [
+    ("store", (3, None, [[(2, 0)], [(2, 1)]], True)),
+    ("no_retry", (3, None, [[(2, 0)], [(2, 1)]], True)),
+    ("store", (5, 2, [[(4, 1)], [(4, 3)]], True)),
+    ("plain_keys", (3, 2, [[(2, 0)], [(0, 1)]], True)),
+])
+def test_planted_mistakes_are_caught(bug, case):
+    n, z, per_thread, split = case
+
+    def buggy():
+        stack = [()]
+        while stack:
+            prefix = stack.pop()
+            r = Run(n, z, per_thread, split, bug)
+            for t in prefix:
+                r.step(t)
+            en = r.enabled()
+            if not en:
+                yield prefix, r.sh
+            stack.extend(prefix + (t,) for t in en)
+
+    found = first_failure(case, buggy())
+    assert found is not None, f"{bug}: no schedule shows it"
+    prefix, bad = found
+    assert bad
