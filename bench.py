@@ -4,8 +4,9 @@
 A step is one pass of the whole single-graph path over the workload, with the
 edge list already resident in HBM: init, zero root (sampled), Initial Push,
 hook, compress and the zero-component relabelling (flags CC_F_ZROOT), i.e.
-cc_init / cc_zroot / cc_push / cc_hook / cc_compress / cc_canon enqueued on one
-stream. The hook step (one cc_hook call: on the zero-root path a short direct
+cc_init / cc_zroot / cc_push / cc_hook / cc_compress enqueued on one stream
+(cc_compress with CC_F_CANON relabels the zero root's component in the same
+pass, as cc_solve does). The hook step (one cc_hook call: on the zero-root path a short direct
 hook over 1/1024 of the entries, two partition passes, the membership filter and
 the hook of the surviving entries)
 is bracketed by its own HIP events on that stream inside the timed region; the
@@ -124,9 +125,9 @@ def bench_single(cc, torch, ed, n, m, steps, warmup, flags):
         ctx.hook(ed, n, L, flags=flags, stream=stream)
         if ev is not None:
             ev[1].record(stream)
-        ctx.compress(n, L, flags=flags, stream=stream)
-        if flags & cc.F_ZROOT:
-            ctx.canon(n, L, stream=stream)
+        # with a zero root, the relabelling of its component is done in the
+        # same pass (CC_F_CANON), as in cc_solve
+        ctx.compress(n, L, flags=flags | cc.F_CANON, stream=stream)
 
     for _ in range(warmup):
         one_step()

@@ -86,6 +86,10 @@ int cc_version(void);
    m >= 2^18), which otherwise run on one XCD so that their hot entries live
    in one L2. */
 #define CC_F_NO_TILE      0x10u
+/* cc_compress with CC_F_ZROOT: give the zero root's component its smallest ID
+   in the same pass (what cc_canon writes), so that no cc_canon is needed.
+   Ignored elsewhere; the whole-path entry points always do this. */
+#define CC_F_CANON        0x20u
 
 /* ---- context ----------------------------------------------------------- */
 typedef struct cc_ctx cc_ctx;
@@ -248,7 +252,7 @@ int cc_hook_log(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edges, uint
    (requires cc_init then cc_zroot on the same n, else CC_EINVAL) a tree that
    holds a vertex of the membership bitmap is z's component: its members get
    P_v = z, and the smallest member of z's component is recorded for
-   cc_canon. */
+   cc_canon; with CC_F_CANON as well they get that smallest ID at once. */
 int cc_compress(cc_ctx* ctx, uint64_t n, uint32_t* P, uint32_t flags, void* stream);
 
 /* Relabelling of the zero root's component (CC_F_ZROOT only): L_v == z is

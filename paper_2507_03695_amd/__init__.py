@@ -26,6 +26,7 @@ LIB_PATH = os.path.join(_PKG, "libccmi.so")
 CC_OK, CC_EINVAL, CC_ERANGE, CC_ENOMEM, CC_EDEVICE, CC_EAGAIN, CC_ECANCELED, CC_ETIMEDOUT = \
     0, -1, -2, -3, -4, -5, -6, -7
 F_ZROOT, F_ZROOT_EXACT, F_ZROOT_HINT, F_NO_SPLIT, F_NO_TILE = 0x1, 0x2, 0x4, 0x8, 0x10
+F_CANON = 0x20
 
 
 class CCError(RuntimeError):

@@ -94,7 +94,10 @@ int run_push(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P
              hipStream_t stream);
 int run_hook(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
              uint32_t flags, hipStream_t stream);
-int run_compress(Slot* s, uint64_t n, uint32_t* P, uint32_t flags, hipStream_t stream);
+// final_labels (zero root): z's component ends labelled with its smallest ID
+// directly, as run_canon would make it; otherwise it keeps the label z.
+int run_compress(Slot* s, uint64_t n, uint32_t* P, uint32_t flags, hipStream_t stream,
+                 bool final_labels = false);
 // Plain-path hook that appends its links to a caller-owned log (cc_hook_log).
 int run_hook_log(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
                  uint32_t flags, uint32_t* log, uint64_t log_cap, uint64_t* log_count,

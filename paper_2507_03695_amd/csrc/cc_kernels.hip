@@ -643,6 +643,12 @@ __global__ __launch_bounds__(kBlock) void k_csr_hook(const uint64_t* __restrict_
 // cc_tiled.hip), so a tree that holds a marked vertex belongs to z's component.
 // Here every marked vertex passes its mark on to its root; k_resolve then
 // relabels the members of marked trees.
+// The same pass finds the smallest member of z's component (minz, reduced over
+// the blocks by k_minz). Outside z's tree every tree is rooted at its smallest
+// ID (its keys are the IDs), so the candidates are: each member of z's tree
+// (z included), each root whose own bit is set, and the root of each marked
+// vertex. A root whose bit is set during this pass is the root of a marked
+// vertex, so it is counted through that vertex.
 // Each thread takes kVPT vertices per step of its grid-stride loop and issues
 // their first reads together (one read in flight per thread would leave these
 // whole-array passes latency-bound).
@@ -650,21 +656,26 @@ constexpr int kVPT = 4;
 
 template <bool ZR>
 __global__ __launch_bounds__(kBlock) void k_compress(uint32_t* P, uint64_t n, DevState* st,
-                                                     uint32_t* zbits) {
+                                                     uint32_t* zbits, uint32_t* bmin) {
     const uint32_t z = ZR ? ld_agent(&st->zroot) : 0u;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    uint32_t local_min = kEmpty;
     for (uint64_t v0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x; v0 < n; v0 += kVPT * stride) {
-        uint32_t pv[kVPT];
+        uint32_t pv[kVPT], bw[kVPT];
 #pragma unroll
         for (int i = 0; i < kVPT; ++i) {
             const uint64_t v = v0 + i * stride;
             pv[i] = v < n ? ld_agent(&P[v]) : (uint32_t)v;
+            if (ZR) bw[i] = v < n ? ld_agent(&zbits[v >> 5]) : 0u;
         }
 #pragma unroll
         for (int i = 0; i < kVPT; ++i) {
         const uint64_t v = v0 + i * stride;
         const uint32_t p = pv[i];
         uint32_t r = (uint32_t)v;
+        const bool marked = ZR && ((bw[i] >> (v & 31)) & 1u);
+        if (ZR && v < n && p == (uint32_t)v && ((uint32_t)v == z || marked))
+            local_min = min(local_min, (uint32_t)v);
         if (v < n && p != (uint32_t)v) {
             r = p;
             while (true) {
@@ -676,21 +687,39 @@ __global__ __launch_bounds__(kBlock) void k_compress(uint32_t* P, uint64_t n, De
                 r = q;
             }
             if (r != p) st_agent(&P[v], r);
-            if (ZR && r != z && ((ld_agent(&zbits[v >> 5]) >> (v & 31)) & 1u))
+            if (ZR && r == z) {
+                local_min = min(local_min, (uint32_t)v);
+            } else if (marked) {
                 atomicOr(&zbits[r >> 5], 1u << (r & 31));
+                local_min = min(local_min, r);
+            }
         }
+        }
+    }
+    if (ZR) {
+        // one value per block; k_minz reduces them (one atomic per block on a
+        // single word would serialise)
+        __shared__ uint32_t s_min[kBlock / 64];
+        local_min = wave_min_u32(local_min);
+        if ((threadIdx.x & 63) == 0) s_min[threadIdx.x >> 6] = local_min;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t b = s_min[0];
+            for (int w = 1; w < kBlock / 64; ++w) b = min(b, s_min[w]);
+            bmin[blockIdx.x] = b;
         }
     }
 }
 
-// Zero root only, after k_compress: P_v <- z when v or its root is marked (v's
-// tree is then connected to z), and the block's smallest member of z's
-// component for minz. Marks are read coherently: they were set by atomics.
+// Zero root only, after k_compress and k_minz: every member of z's component
+// (its root is z, or v or its root is marked) gets the label z, or with FINAL
+// the component's smallest ID minz at once (no k_canon pass needed). Marks are
+// read coherently: they were set by atomics.
+template <bool FINAL>
 __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t* P, uint64_t n, DevState* st,
-                                                    const uint32_t* zbits, uint32_t* bmin) {
-    __shared__ uint32_t s_min[kBlock / 64];
+                                                    const uint32_t* zbits) {
     const uint32_t z = ld_agent(&st->zroot);
-    uint32_t local_min = kEmpty;
+    const uint32_t lab = FINAL ? ld_agent(&st->minz) : z;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t v0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x; v0 < n; v0 += kVPT * stride) {
         uint32_t rr[kVPT], bv[kVPT];
@@ -706,24 +735,10 @@ __global__ __launch_bounds__(kBlock) void k_resolve(uint32_t* P, uint64_t n, Dev
             const uint64_t v = v0 + i * stride;
             if (v >= n) continue;
             const uint32_t r = rr[i];
-            bool inz = r == z;
-            if (!inz) {
-                inz = ((bv[i] >> (v & 31)) & 1u) ||
-                      (r != (uint32_t)v && ((ld_agent(&zbits[r >> 5]) >> (r & 31)) & 1u));
-                if (inz) st_agent(&P[v], z);
-            }
-            if (inz && (uint32_t)v < local_min) local_min = (uint32_t)v;
+            const bool inz = r == z || ((bv[i] >> (v & 31)) & 1u) ||
+                             (r != (uint32_t)v && ((ld_agent(&zbits[r >> 5]) >> (r & 31)) & 1u));
+            if (inz && r != lab) st_agent(&P[v], lab);
         }
-    }
-    // the block's smallest member of z's component; k_minz reduces over blocks
-    // (one atomic per block on a single word would serialise)
-    local_min = wave_min_u32(local_min);
-    if ((threadIdx.x & 63) == 0) s_min[threadIdx.x >> 6] = local_min;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t b = s_min[0];
-        for (int w = 1; w < kBlock / 64; ++w) b = min(b, s_min[w]);
-        bmin[blockIdx.x] = b;
     }
 }
 
@@ -932,21 +947,24 @@ int run_hook_log(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_
     return CC_OK;
 }
 
-int run_compress(Slot* s, uint64_t n, uint32_t* P, uint32_t flags, hipStream_t stream) {
+int run_compress(Slot* s, uint64_t n, uint32_t* P, uint32_t flags, hipStream_t stream,
+                 bool final_labels) {
     const uint32_t g = grid_for(n, kBlock, kGridCap);
+    final_labels = final_labels || (flags & CC_F_CANON);
     if (flags & CC_F_ZROOT) {
         if (!s->zr_ready || s->cur_n != n)
             return fail(CC_EINVAL, "a CC_F_ZROOT compress needs cc_init then cc_zroot on the same n");
-        k_compress<true><<<g, kBlock, 0, stream>>>(P, n, s->st, s->zbits);
+        k_compress<true><<<g, kBlock, 0, stream>>>(P, n, s->st, s->zbits, s->bmin);
         CCM_HIP(hipGetLastError());
         int rc = cohere(stream);
         if (rc) return rc;
-        k_resolve<<<g, kBlock, 0, stream>>>(P, n, s->st, s->zbits, s->bmin);
+        k_minz<<<1, 1024, 0, stream>>>(s->bmin, g, s->st);
         CCM_HIP(hipGetLastError());
         if ((rc = cohere(stream))) return rc;
-        k_minz<<<1, 1024, 0, stream>>>(s->bmin, g, s->st);
+        if (final_labels) k_resolve<true><<<g, kBlock, 0, stream>>>(P, n, s->st, s->zbits);
+        else k_resolve<false><<<g, kBlock, 0, stream>>>(P, n, s->st, s->zbits);
     } else {
-        k_compress<false><<<g, kBlock, 0, stream>>>(P, n, s->st, nullptr);
+        k_compress<false><<<g, kBlock, 0, stream>>>(P, n, s->st, nullptr, nullptr);
     }
     CCM_HIP(hipGetLastError());
     return CC_OK;
@@ -1073,11 +1091,7 @@ int run_solve_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, const ui
         CCM_HIP(hipGetLastError());
     }
     if ((rc = cohere(stream))) return rc;
-    if ((rc = run_compress(s, n, L, flags, stream))) return rc;
-    if (zr) {
-        if ((rc = cohere(stream))) return rc;
-        if ((rc = run_canon(s, n, L, stream))) return rc;
-    }
+    if ((rc = run_compress(s, n, L, flags, stream, true))) return rc;
     return cohere(stream);
 }
 
@@ -1093,11 +1107,7 @@ int run_solve(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* 
     if ((rc = cohere(stream))) return rc;
     if ((rc = run_hook(s, n, m, edges, L, flags, stream))) return rc;
     if ((rc = cohere(stream))) return rc;
-    if ((rc = run_compress(s, n, L, flags, stream))) return rc;
-    if (flags & CC_F_ZROOT) {
-        if ((rc = cohere(stream))) return rc;
-        if ((rc = run_canon(s, n, L, stream))) return rc;
-    }
+    if ((rc = run_compress(s, n, L, flags, stream, true))) return rc;
     return cohere(stream);
 }
 

@@ -172,17 +172,29 @@ def test_zero_root_choice_does_not_change_labels(ctx, size):
 
 
 def test_repeat_stress(ctx):
-    """Same input, many runs: the schedule differs, the labels may not."""
+    """Same graph, many runs: the schedule differs, the labels may not. Every run
+    takes the entries in a new seeded order, with a new random half of them
+    reversed, and the runs cycle through the plain and zero-root variants with
+    and without splitting and with a forced zero root."""
     n = 1 << 16
     e = graphgen.rmat(16, 16 << 16, 12)
     want = oracle.cc_labels(n, e)
     ed = to_dev(e)
     L = torch.empty(n, dtype=torch.int32, device="cuda")
-    for rep in range(40):
-        fl = [0, cc.F_ZROOT][rep % 2]
-        ctx.solve_async(ed, n, L, flags=fl)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(12)
+    flag_cycle = [0, cc.F_ZROOT, cc.F_NO_SPLIT, cc.F_ZROOT | cc.F_NO_SPLIT,
+                  cc.F_ZROOT | cc.F_ZROOT_HINT]
+    for rep in range(120):
+        order = torch.randperm(len(e), device="cuda", generator=gen)
+        er = ed[order]
+        flip = torch.rand(len(e), device="cuda", generator=gen) < 0.5
+        er[flip] = er[flip].flip(1)
+        er = er.contiguous()
+        fl = flag_cycle[rep % len(flag_cycle)]
+        ctx.solve_async(er, n, L, flags=fl, zroot_hint=(rep * 7919) % n)
         assert ctx.sync() == cc.CC_OK
-        assert_same_labels(to_host_u32(L), want, f"rep {rep}")
+        assert_same_labels(to_host_u32(L), want, f"rep {rep} flags {fl:#x}")
 
 
 # ---- the step entry points ----------------------------------------------------------
@@ -235,6 +247,40 @@ def test_hook_leaves_a_key_monotone_forest(ctx, flags):
         ctx.canon(n, P)
     assert ctx.sync() == cc.CC_OK
     assert_same_labels(to_host_u32(P), want, "steps")
+
+
+@pytest.mark.parametrize("size", ["direct", "regrouped"])
+def test_compress_relabels_with_or_without_canon(ctx, size):
+    """cc_compress with a zero root leaves z's component labelled z (the form the
+    share export reads) and cc_canon then gives each component its smallest ID;
+    with CC_F_CANON cc_compress gives those labels itself. Both equal the
+    oracle's, on the direct hook and on the regrouped one (whose links to z are
+    partly bitmap marks that compress resolves)."""
+    if size == "direct":
+        n, e = 1 << 17, graphgen.rmat(17, 1 << 20, 45)
+    else:
+        n, e = 1 << 20, graphgen.rmat(20, 1 << 24, 46)
+    want = oracle.cc_labels(n, e)
+    ed = to_dev(e)
+    P = torch.empty(n, dtype=torch.int32, device="cuda")
+    for canon_flag in (False, True):
+        ctx.init(n, P)
+        ctx.zroot(ed, n)
+        z = ctx.get_zroot()
+        ctx.push(ed, n, P)
+        ctx.hook(ed, n, P, flags=cc.F_ZROOT)
+        if canon_flag:
+            ctx.compress(n, P, flags=cc.F_ZROOT | cc.F_CANON)
+        else:
+            ctx.compress(n, P, flags=cc.F_ZROOT)
+            assert ctx.sync() == cc.CC_OK
+            Ph = to_host_u32(P)
+            inz = want == want[z]
+            assert np.all(Ph[inz] == z), "members of z's component not labelled z"
+            assert_same_labels(Ph[~inz], want[~inz], "labels outside z's component")
+            ctx.canon(n, P)
+        assert ctx.sync() == cc.CC_OK
+        assert_same_labels(to_host_u32(P), want, f"{size} CC_F_CANON={canon_flag}")
 
 
 # ---- the named workloads at full size ---------------------------------------------------
