@@ -35,8 +35,8 @@ PEAK_HBM_GBS = 8000.0
 # each counter scaled by what it reads for a 4 GiB device copy. Keyed by
 # (workload, variant); valid only for the kernel sources they were taken on.
 TRAFFIC = {
-    ("rmat26", "zroot"): {"bytes": 51663602339,
-                          "src_sha256": "c71a32424b48f339b7fc1c56cac69bd234d6f006267ecec4bc06f71331fb6c8a"},
+    ("rmat26", "zroot"): {"bytes": 51683022604,
+                          "src_sha256": "16c0b5483b99f2f45f124e6b986746ff7fe660efd748df6bce175bb029e11438"},
 }
 
 HOOK_KERNELS = {
