@@ -10,7 +10,8 @@ pass, as cc_solve does). The hook step (one cc_hook call: on the zero-root path 
 hook over 1/1024 of the entries, two partition passes, the membership filter and
 the hook of the surviving entries)
 is bracketed by its own HIP events on that stream inside the timed region; the
-roofline figure is its algorithmic bytes (8 per entry) over that duration.
+roofline figure is its algorithmic bytes (8 per entry) over that duration,
+against the 8 TB/s peak and against a 4 GiB device copy timed in the same run.
 
 Prints one JSON line. Default workload: R-MAT scale 26, edgefactor 16, permuted
 IDs, plus 1 % isolated vertices and 10,000 paths of 2..64 vertices.
@@ -522,6 +523,26 @@ def bench_share30(cc, torch, steps=2):
     return out
 
 
+def copy_ceiling_gbs(torch, reps=5):
+    """Measured HBM ceiling: a plain device copy of 4 GiB (4 GiB read and 4 GiB
+    written per launch), timed with HIP events on the current stream."""
+    src = torch.ones(1 << 30, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * (4 << 30) / (ms * 1e-3) / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -574,6 +595,8 @@ def main():
                                      0 if flags else cc.F_ZROOT)
     assert torch.equal(L, L_o), "variants disagree"
     del L_o
+    copy_gbs = copy_ceiling_gbs(torch)
+    log(f"copy ceiling {copy_gbs:.0f} GB/s")
     def want(section):
         return not args.no_extras and args.only in (None, section)
 
@@ -618,10 +641,16 @@ def main():
                      "frac": round(hook_gbs / PEAK_HBM_GBS, 4),
                      "traffic": measured_traffic(args.workload, args.variant),
                      "kernel": HOOK_KERNELS[args.variant],
-                     "algorithmic_bytes_per_launch": 8 * m, "avg_launch_ms": round(hook_ms, 4)},
+                     "algorithmic_bytes_per_launch": 8 * m, "avg_launch_ms": round(hook_ms, 4),
+                     "measured_copy_GBps": round(copy_gbs, 1),
+                     "frac_of_measured_copy": round(hook_gbs / copy_gbs, 4)},
         other: {"ms_per_step": round(ms_o, 4), "hook_ms": round(hook_o, 4),
                 "GTEPS": round(m / (ms_o * 1e-3) / 1e9, 3)},
     }
+    t = line["roofline"]["traffic"]
+    if t is not None:
+        # the rate at which the step moves its measured HBM bytes
+        line["roofline"]["traffic_GBps"] = round(t / (hook_ms * 1e-3) / 1e9, 1)
     if reducer is not None:
         line["reducer"] = reducer
     if upd is not None:
