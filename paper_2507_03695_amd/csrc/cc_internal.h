@@ -17,7 +17,7 @@ namespace ccm {
 // only through explicit copies.
 struct DevState {
     uint32_t status;    // kStatus* bits, reported and cleared by slot_sync
-    uint32_t minz;      // smallest vertex whose root is the zero root (compress)
+    uint32_t minz;      // smallest member of the zero root's component (compress, k_minz)
     uint32_t zroot;     // the zero root chosen for the current solve
     uint32_t pad0;
     uint64_t zsel;      // packed argmax (count << 32) | (0xFFFFFFFF - id); 0 = none
