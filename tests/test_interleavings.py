@@ -360,3 +360,159 @@ def test_planted_mistakes_are_caught(bug, case):
     assert found is not None, f"{bug}: no schedule shows it"
     prefix, bad = found
     assert bad
+
+
+# ---- the regrouped zero-root hook: marks as links, then compress and resolve -------
+#
+# The regrouped hook runs the direct hook (with the bitmap) over a short warm-up,
+# then a filter over the rest: an entry whose endpoints are both marked is
+# dropped; with one marked, the other is marked (its link to z) and the entry is
+# dropped; with neither, it is kept. A filter workgroup tests against its own
+# copy of the bitmap, loaded when it starts and updated with its own marks, so it
+# may miss marks set elsewhere meanwhile. The kept entries are then hooked with
+# Algorithm 3's keys and no bitmap. Compress passes each marked vertex's mark to
+# its root and collects the candidates for the smallest member of z's
+# component; resolve labels every member of z's component with that minimum.
+
+def warmup_thread(sh, entries, split):
+    yield from thread(sh, entries, split)
+
+
+def filter_thread(sh, entries, survivors, bug=None):
+    yield
+    seen = list(sh.bit)
+    for u, v in entries:
+        if u == v:
+            continue
+        mu, mv = seen[u], seen[v]
+        if mu and mv:
+            continue
+        if mu != mv:
+            if bug == "drop_unmarked":
+                continue
+            w = v if mu else u
+            seen[w] = True
+            yield
+            sh.bit[w] = True
+            continue
+        survivors.append((u, v))
+
+
+def survivor_thread(sh, entries, split):
+    for u, v in entries:
+        yield
+        pu = sh.P[u]
+        yield
+        pv = sh.P[v]
+        if pu == pv or pu == v or pv == u:
+            continue
+        yield from link(sh, u, pu, v, pv, split, None, sh.z)
+
+
+def run_threads(gens, rng, stick=0.7):
+    live = {}
+    for i, g in enumerate(gens):
+        try:
+            next(g)
+            live[i] = g
+        except StopIteration:
+            pass
+    t = None
+    while live:
+        if t not in live or rng.random() > stick:
+            t = rng.choice(sorted(live))
+        try:
+            next(live[t])
+        except StopIteration:
+            del live[t]
+
+
+def compress_resolve(sh, order, bug=None):
+    """Labels after compress (vertices visited in `order`: a root's own bit may
+    be read before or after another vertex marks it) and resolve."""
+    P, z = sh.P, sh.z
+    bit = sh.bit
+    cand = []
+    for v in order:
+        p = P[v]
+        marked = bit[v]
+        if p == v:
+            if v == z or (marked and bug != "no_own_bit"):
+                cand.append(v)
+            continue
+        r = root(P, v)
+        if r == z:
+            cand.append(v)
+        elif marked:
+            if bug != "no_propagation":
+                bit[r] = True
+            cand.append(r)
+    minz = min(cand)
+    out = []
+    for v in range(sh.n):
+        r = root(P, v)
+        inz = r == z or bit[v] or bit[r]
+        out.append(minz if inz else r)
+    return np.array(out, np.uint32)
+
+
+def regrouped_run(n, z, edges, rng, split=True, nwarm=1, nfilt=2, nsurv=2, bug=None):
+    sh = Shared(n, z)
+    initial_push(sh, edges)
+    w = max(1, len(edges) // 5)
+    warm, rest = edges[:w], edges[w:]
+    run_threads([warmup_thread(sh, warm[i::nwarm], split) for i in range(nwarm)], rng)
+    kept = [[] for _ in range(nfilt)]
+    run_threads([filter_thread(sh, rest[i::nfilt], kept[i], bug) for i in range(nfilt)], rng)
+    surv = [e for k in kept for e in k]
+    run_threads([survivor_thread(sh, surv[i::nsurv], split) for i in range(nsurv)], rng)
+    for x in range(n):
+        if sh.P[x] != x:
+            assert key(sh.P[x], z) < key(x, z), "parent with a greater key"
+    order = list(range(n))
+    rng.shuffle(order)
+    return sh, compress_resolve(sh, order, bug)
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_regrouped_marks_compress_resolve(seed):
+    """Random multigraphs and zero roots, random schedules of every phase and
+    random compress orders: the labels are the oracle's, and every marked vertex
+    lies in the zero root's component."""
+    rng = random.Random(2000 + seed)
+    for _ in range(40):
+        n = rng.randint(2, 10)
+        m = rng.randint(1, 16)
+        edges = [(rng.randrange(n), rng.randrange(n)) for _ in range(m)]
+        z = rng.randrange(n)
+        want = oracle.cc_labels(n, np.asarray(edges, np.uint32).reshape(-1, 2))
+        for split in (True, False):
+            sh, got = regrouped_run(n, z, edges, rng, split)
+            assert np.array_equal(got, want), (n, z, edges, got.tolist(), want.tolist())
+            marked = [x for x in range(n) if sh.bit[x]]
+            assert all(want[x] == want[z] for x in marked), (n, z, edges)
+
+
+# Each case is built so that one planted mistake changes its labels:
+# - a root marked by the filter whose tree has no other marked member is the
+#   component's minimum (only its own bit makes it a candidate);
+# - a vertex marked by the filter whose root is unmarked (only the mark passed
+#   on to the root joins that tree to z's component).
+REGROUPED_BUGS = [
+    ("no_own_bit", 4, 3, [(3, 1), (0, 2), (1, 0), (1, 0), (1, 0), (1, 0)]),
+    ("no_propagation", 5, 4, [(4, 3), (2, 1), (4, 0), (3, 2), (3, 2), (3, 2), (3, 2)]),
+    ("drop_unmarked", 5, 4, [(4, 3), (2, 1), (4, 0), (3, 2), (3, 2), (3, 2), (3, 2)]),
+]
+
+
+@pytest.mark.parametrize("bug,n,z,edges", REGROUPED_BUGS)
+def test_regrouped_planted_mistakes_are_caught(bug, n, z, edges):
+    want = oracle.cc_labels(n, np.asarray(edges, np.uint32).reshape(-1, 2))
+    rng = random.Random(7)
+    sh, good = regrouped_run(n, z, edges, rng, nwarm=1, nfilt=1, nsurv=1)
+    assert np.array_equal(good, want)
+    caught = False
+    for s in range(20):
+        sh, got = regrouped_run(n, z, edges, random.Random(s), nwarm=1, nfilt=1, nsurv=1, bug=bug)
+        caught |= not np.array_equal(got, want)
+    assert caught, f"{bug}: not caught"
