@@ -27,6 +27,13 @@ Planted mistakes in the model (a link that is a plain store, a failed CAS
 taken as done, the plain keys with a zero root) must each be caught by one of
 these checks.
 
+A second model, at the end of the file, covers the regrouped zero-root hook:
+- the filter's marks stand in for links to z;
+- the survivor hook follows;
+- compress passes marks to roots and finds the smallest member of z's
+  component, in any vertex order;
+- resolve gives the final labels.
+
 The model is sequentially consistent: each step sees every earlier write. The
 device's weaker ordering across its L2 caches is covered by the kernels'
 coherent stores and loads and tested on the device."""
