@@ -193,5 +193,15 @@ def test_serve_overlap_and_timestamps(ctx):
     log(f"300 requests in {time.monotonic() - t0:.3f} s")
     for s in sts:
         assert s.status == 0 and s.t_submit_ns <= s.t_admit_ns <= s.t_done_ns
+    # requests in flight together: the most admit-to-done intervals that cover
+    # one instant (a sweep over the interval ends)
+    ev = sorted([(s.t_admit_ns, 1) for s in sts] + [(s.t_done_ns, -1) for s in sts],
+                key=lambda x: (x[0], x[1]))
+    depth = peak = 0
+    for _, d in ev:
+        depth += d
+        peak = max(peak, depth)
+    log(f"at most {peak} requests in flight together")
+    assert peak >= 2, "no two requests were in flight together"
     for (e, n), L in zip(reqs[:40], outs[:40]):
         assert_same_labels(L, oracle.cc_labels(n, e), f"served n={n}")
