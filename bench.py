@@ -36,8 +36,8 @@ PEAK_HBM_GBS = 8000.0
 # each counter scaled by what it reads for a 4 GiB device copy. Keyed by
 # (workload, variant); valid only for the kernel sources they were taken on.
 TRAFFIC = {
-    ("rmat26", "zroot"): {"bytes": 51666768334,
-                          "src_sha256": "b6e5a5a7ce9d6f38a99f877f62aa46fde8b9d96a7978f356afc4751f7f1267b7"},
+    ("rmat26", "zroot"): {"bytes": 51670451975,
+                          "src_sha256": "86b83a4557ed63fcad2bb563c5dbb7d322337310a74986fe688e0b0a84b30551"},
 }
 
 HOOK_KERNELS = {

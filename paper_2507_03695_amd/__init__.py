@@ -21,7 +21,9 @@ import os
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libccmi.so")
+# CCMI_LIBRARY selects another build of the same library, such as the
+# race-testing build libccmi_stress.so next to this file.
+LIB_PATH = os.environ.get("CCMI_LIBRARY") or os.path.join(_PKG, "libccmi.so")
 
 CC_OK, CC_EINVAL, CC_ERANGE, CC_ENOMEM, CC_EDEVICE, CC_EAGAIN, CC_ECANCELED, CC_ETIMEDOUT = \
     0, -1, -2, -3, -4, -5, -6, -7

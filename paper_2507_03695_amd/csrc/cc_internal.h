@@ -189,6 +189,21 @@ __device__ __forceinline__ void st_agent64(uint64_t* p, uint64_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Race-testing builds (compiled with CCM_STRESS_DELAYS, a separate library):
+// before each link CAS and each path-splitting store a wave pauses for 0 to 7
+// short sleeps, drawn from the clock, the lane and `salt`. The pause widens the
+// windows in which other waves change the same entries. The ordinary build
+// compiles this to nothing.
+__device__ __forceinline__ void stress_delay(uint32_t salt) {
+#ifdef CCM_STRESS_DELAYS
+    uint32_t h = (salt ^ (threadIdx.x * 0x9E3779B9u) ^ (uint32_t)clock64()) * 0x85EBCA6Bu;
+    h ^= h >> 13;
+    for (uint32_t i = 0; i < (h & 7u); ++i) __builtin_amdgcn_s_sleep(2);
+#else
+    (void)salt;
+#endif
+}
+
 // Device, memory budget and zero-root sample count of a context.
 int ctx_info(cc_ctx* ctx, int* device, uint64_t* budget, uint32_t* samples);
 

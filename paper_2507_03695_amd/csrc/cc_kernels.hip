@@ -214,7 +214,10 @@ __device__ __forceinline__ uint32_t find_root(uint32_t* P, uint32_t x, uint32_t 
     uint32_t gp = P[px];
     while (gp != px) {
         const uint32_t ggp = P[gp];
-        if (SPLIT) st_agent(&P[x], gp);
+        if (SPLIT) {
+            stress_delay(x);
+            st_agent(&P[x], gp);
+        }
         x = px;
         px = gp;
         gp = ggp;
@@ -239,6 +242,7 @@ __device__ __forceinline__ uint32_t link(uint32_t* P, uint32_t u, uint32_t pu, u
         const bool u_low = key_less<ZR>(ru, rv, z);
         const uint32_t hi = u_low ? rv : ru;
         const uint32_t lo = u_low ? ru : rv;
+        stress_delay(hi);
         const uint32_t old = atomicCAS(&P[hi], hi, lo);
         if (old == hi) {
             if (linked) *linked = hi;

@@ -73,6 +73,7 @@ __device__ __forceinline__ uint32_t t_find(uint32_t* P, uint32_t x, uint32_t px)
     uint32_t gp = P[px];
     while (gp != px) {
         const uint32_t ggp = P[gp];
+        stress_delay(x);
         st_agent(&P[x], gp);
         x = px;
         px = gp;
@@ -90,6 +91,7 @@ __device__ __forceinline__ uint32_t t_link(uint32_t* P, uint32_t u, uint32_t pu,
         const bool u_low = t_key_less(ru, rv, z);
         const uint32_t hi = u_low ? rv : ru;
         const uint32_t lo = u_low ? ru : rv;
+        stress_delay(hi);
         const uint32_t old = atomicCAS(&P[hi], hi, lo);
         if (old == hi) return lo;
         u = hi; pu = old;

@@ -34,7 +34,10 @@ __device__ __forceinline__ uint64_t find_w(uint64_t* P, uint64_t x, uint64_t px)
     uint64_t gp = P[px];
     while (gp != px) {
         const uint64_t ggp = P[gp];
-        if (SPLIT) st_agent_w(&P[x], gp);
+        if (SPLIT) {
+            stress_delay((uint32_t)x);
+            st_agent_w(&P[x], gp);
+        }
         x = px;
         px = gp;
         gp = ggp;
@@ -80,6 +83,7 @@ __global__ __launch_bounds__(kWBlock) void k_hook_w(const uint64_t* __restrict__
             if (ra == rb) break;
             const uint64_t hi = ra < rb ? rb : ra;
             const uint64_t lo = ra < rb ? ra : rb;
+            stress_delay((uint32_t)hi);
             const uint64_t old = atomicCAS((unsigned long long*)&P[hi], (unsigned long long)hi,
                                            (unsigned long long)lo);
             if (old == hi) break;

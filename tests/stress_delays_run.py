@@ -1,0 +1,57 @@
+"""Parity under injected delays, run in a child process whose CCMI_LIBRARY is the
+race-testing build (libccmi_stress.so: every link CAS and path-splitting store
+is preceded by a varying pause of its wave). Every solve, each on the entries
+in a new seeded order, must give the oracle's labels; the direct, regrouped and
+one-XCD hooks and the 64-bit path are all exercised. Exit status 0 when every
+solve agrees. Started by tests/test_gpu_stress_delays.py."""
+import os
+import sys
+
+import numpy as np
+import torch
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import graphgen  # noqa: E402
+import oracle  # noqa: E402
+import paper_2507_03695_amd as cc  # noqa: E402
+
+
+def main() -> int:
+    assert os.path.basename(cc.LIB_PATH) == "libccmi_stress.so", cc.LIB_PATH
+    cc.load()
+    cases = [
+        ("er_2^14", 1 << 14, graphgen.er(1 << 14, 1 << 16, 301), 4),
+        ("rmat_2^16", 1 << 16, graphgen.rmat(16, 1 << 20, 302), 3),   # one-XCD plain hook
+        ("rmat_2^20_2^24", 1 << 20, graphgen.rmat(20, 1 << 24, 303), 2),  # regrouped hooks
+    ]
+    flagsets = {"plain": 0, "plain_nosplit": cc.F_NO_SPLIT, "plain_direct": cc.F_NO_TILE,
+                "zroot": cc.F_ZROOT, "zroot_direct": cc.F_ZROOT | cc.F_NO_TILE}
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(304)
+    with cc.Context() as c:
+        for name, n, e, reps in cases:
+            want = oracle.cc_labels(n, e)
+            ed = torch.from_numpy(e.view(np.int32)).cuda()
+            for fname, fl in flagsets.items():
+                for rep in range(reps):
+                    er = ed[torch.randperm(len(e), device="cuda", generator=gen)].contiguous()
+                    got = c.solve(er, n, flags=fl).cpu().numpy().view(np.uint32)
+                    if not np.array_equal(got, want):
+                        bad = np.flatnonzero(got != want)
+                        print(f"FAIL {name} {fname} rep {rep}: {len(bad)} labels differ, "
+                              f"first v={bad[0]}", flush=True)
+                        return 1
+                print(f"ok {name} {fname} x{reps}", flush=True)
+            if name == "er_2^14":
+                e64 = torch.from_numpy(np.ascontiguousarray(e.astype(np.uint64)).view(np.int64)).cuda()
+                for fl in (0, cc.F_NO_SPLIT):
+                    got = c.solve_u64(e64, n, flags=fl).cpu().numpy().view(np.uint64)
+                    if not np.array_equal(got, want.astype(np.uint64)):
+                        print(f"FAIL {name} 64-bit flags {fl}", flush=True)
+                        return 1
+                print(f"ok {name} 64-bit", flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

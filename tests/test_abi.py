@@ -42,6 +42,17 @@ def test_library_exports_every_declared_symbol():
     assert not missing, f"not exported: {missing}"
 
 
+def test_race_testing_build_exports_the_same_symbols():
+    """libccmi_stress.so (the sources built with CCM_STRESS_DELAYS, loaded by the
+    delay-injection GPU test through CCMI_LIBRARY) is the same ABI."""
+    from paper_2507_03695_amd import _build
+    if not os.path.exists(_build.STRESS_LIB):
+        _build.build(stress=True)
+    lib = ctypes.CDLL(_build.STRESS_LIB)
+    missing = [n for n in header_functions() if not hasattr(lib, n)]
+    assert not missing, f"not exported: {missing}"
+
+
 def test_binding_covers_the_header():
     import paper_2507_03695_amd as pkg
     assert sorted(pkg.SIGNATURES) == header_functions()
