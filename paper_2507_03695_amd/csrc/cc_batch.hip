@@ -43,6 +43,7 @@ __device__ __forceinline__ uint32_t bfind16(uint16_t* P, uint32_t x, uint32_t px
     while (px != x) {
         const uint32_t gp = P[px];
         if (gp == px) return px;
+        stress_delay(x);
         P[x] = (uint16_t)gp;
         x = px;
         px = gp;
@@ -77,6 +78,7 @@ __device__ __forceinline__ void blink16(uint16_t* P, uint32_t* P32, uint32_t u, 
         if (ru == rv) return;
         const uint32_t hi = ru < rv ? rv : ru;
         const uint32_t lo = ru < rv ? ru : rv;
+        stress_delay(hi);
         const uint32_t old = cas16(P32, hi, lo);
         if (old == hi) return;
         u = hi; pu = old;
@@ -139,6 +141,7 @@ __device__ __forceinline__ uint32_t bfind(glabel_t* P, uint32_t x, uint32_t px) 
     while (px != x) {
         const uint32_t gp = P[px];
         if (gp == px) return px;
+        stress_delay(x);
         gstore(&P[x], gp);
         x = px;
         px = gp;
@@ -158,6 +161,7 @@ __device__ __forceinline__ void blink(glabel_t* P, uint32_t u, uint32_t v) {
         const uint32_t hi = ru < rv ? rv : ru;
         const uint32_t lo = ru < rv ? ru : rv;
         uint32_t old = hi;
+        stress_delay(hi);
         if (__hip_atomic_compare_exchange_strong(&P[hi], &old, lo, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             return;

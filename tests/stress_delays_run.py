@@ -2,7 +2,8 @@
 race-testing build (libccmi_stress.so: every link CAS and path-splitting store
 is preceded by a varying pause of its wave). Every solve, each on the entries
 in a new seeded order, must give the oracle's labels; the direct, regrouped and
-one-XCD hooks and the 64-bit path are all exercised. Exit status 0 when every
+one-XCD hooks, the 64-bit path and the batched launch (parent arrays in LDS and
+in HBM) are all exercised. Exit status 0 when every
 solve agrees. Started by tests/test_gpu_stress_delays.py."""
 import os
 import sys
@@ -50,6 +51,23 @@ def main() -> int:
                         print(f"FAIL {name} 64-bit flags {fl}", flush=True)
                         return 1
                 print(f"ok {name} 64-bit", flush=True)
+        # many graphs in one launch: parent arrays in LDS (16-bit entries) and,
+        # above the LDS capacity, in HBM
+        graphs = [(graphgen.rmat(17, 1 << 19, 305 + i) % (90_000 + i), 90_000 + i) for i in range(2)]
+        graphs += [(graphgen.er(1 << 16, 1 << 18, 307), 1 << 16)]
+        graphs += [(graphgen.rmat(12, 1 << 15, 308 + i), 1 << 12) for i in range(200)]
+        b = graphgen.batch_from_graphs(graphs)
+        want, _ = oracle.cc_labels_batch(b.vtx_off, b.edge_off, b.edges)
+        vo = torch.from_numpy(b.vtx_off).cuda()
+        eo = torch.from_numpy(b.edge_off).cuda()
+        eb = torch.from_numpy(np.ascontiguousarray(b.edges)).cuda()
+        for rep in range(3):
+            L, st = c.batch(vo, eo, eb)
+            if not (np.all(st.cpu().numpy() == 0) and
+                    np.array_equal(L.cpu().numpy().view(np.uint32), want.view(np.uint32))):
+                print(f"FAIL batch rep {rep}", flush=True)
+                return 1
+        print("ok batch x3", flush=True)
     return 0
 
 
