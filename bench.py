@@ -205,9 +205,16 @@ def bench_batch(cc, torch, reps=5):
     same = bool(torch.equal(L, L2))
     ctx.close()
     m = int(b.edge_off[-1])
-    return {"graphs": b.G, "sum_n": int(b.vtx_off[-1]), "sum_m": m,
+    sum_n = int(b.vtx_off[-1])
+    # compulsory HBM bytes with parent arrays in LDS: the entries once (8 B) and
+    # the labels written once (4 B per vertex)
+    alg = 8 * m + 4 * sum_n
+    return {"graphs": b.G, "sum_n": sum_n, "sum_m": m,
             "batched_graphs_per_s": round(b.G / t_batch, 1),
             "batched_ms": round(t_batch * 1e3, 3),
+            "algorithmic_bytes": alg,
+            "achieved_GBps": round(alg / t_batch / 1e9, 1),
+            "hbm_roofline_frac": round(alg / t_batch / 1e9 / PEAK_HBM_GBS, 4),
             "graph_replay_ms": round(t_graph * 1e3, 3), "graph_replay_identical": same_graph,
             "per_graph_launch_graphs_per_s": round(b.G / t_loop, 1),
             "per_graph_launch_ms": round(t_loop * 1e3, 3),
