@@ -36,8 +36,8 @@ PEAK_HBM_GBS = 8000.0
 # each counter scaled by what it reads for a 4 GiB device copy. Keyed by
 # (workload, variant); valid only for the kernel sources they were taken on.
 TRAFFIC = {
-    ("rmat26", "zroot"): {"bytes": 51670451975,
-                          "src_sha256": "86b83a4557ed63fcad2bb563c5dbb7d322337310a74986fe688e0b0a84b30551"},
+    ("rmat26", "zroot"): {"bytes": 51687714128,
+                          "src_sha256": "8911e8486721e71d506b24368ddef6e51b4429da4f57ad9a92a18f6bc6594893"},
 }
 
 HOOK_KERNELS = {

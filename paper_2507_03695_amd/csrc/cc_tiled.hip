@@ -690,7 +690,7 @@ __global__ __launch_bounds__(kPartBlock) void k_t2_csr(const uint64_t* __restric
 // does not consult the bitmap.
 constexpr int kHook3Block = 1024;
 constexpr int kWaves3 = kHook3Block / 64;
-constexpr int kWin3 = 2048;      // level-2 chunks per window
+constexpr int kWin3 = 2000;      // level-2 chunks per window
 constexpr int kRunsInFlight = 16; // entries a lane loads at once (a wave: 16 x 64 consecutive)
 constexpr int kWaveQueue = 128;  // per-wave LDS staging of kept entries
 
@@ -825,7 +825,7 @@ __global__ __launch_bounds__(kHook3Block) void k_t3_filter(const u32x2* __restri
                                                            DevState* st) {
     __shared__ uint32_t sa[kSliceWords];
     __shared__ uint32_t sb[kSliceWords];
-    __shared__ uint16_t s_r0[kWin3];
+    __shared__ uint32_t s_off[kWin3];
     __shared__ uint32_t s_pre[kWin3 + 1];
     __shared__ u32x2 queue[kWaves3 * kWaveQueue];
     __shared__ uint32_t wsum[kWaves3 + 1];
@@ -890,11 +890,16 @@ __global__ __launch_bounds__(kHook3Block) void k_t3_filter(const u32x2* __restri
                 const uint64_t g = (uint64_t)cb + w0 + t;
                 const uint32_t r0 = run2T[(uint64_t)b * nch2 + g];
                 const uint32_t r1 = run2T[(uint64_t)(b + 1) * nch2 + g];
-                s_r0[t] = (uint16_t)r0;
+                s_off[t] = r0;
                 s_pre[t] = r1 - r0;
             }
             __syncthreads();
             block_scan_2048(s_pre, nw, wsum);        // run lengths -> starts; s_pre[nw] = total
+            // index of the window's j-th entry in run t: j + s_off[t] (mod 2^32;
+            // every index of a bucket is below 2^32)
+            for (uint32_t t = threadIdx.x; t < nw; t += kHook3Block)
+                s_off[t] = (w0 + t) * (uint32_t)kC2 + s_off[t] - s_pre[t];
+            __syncthreads();
             const uint32_t total = s_pre[nw];
             // The window's entries form one index space [0, total); each wave
             // takes ranges of kRange consecutive indices (lanes step through the
@@ -906,7 +911,7 @@ __global__ __launch_bounds__(kHook3Block) void k_t3_filter(const u32x2* __restri
             // index of this lane, advanced in place).
             auto addr = [&](uint32_t j, uint32_t& t) -> uint64_t {
                 while (t + 1 < nw && s_pre[t + 1] <= j) ++t;
-                return (uint64_t)(w0 + t) * kC2 + s_r0[t] + (j - s_pre[t]);
+                return (uint64_t)(j + s_off[t]);
             };
             // Software pipeline: e[k] holds entry k of the current range; right
             // after it is tested its register is reloaded with entry k of the
