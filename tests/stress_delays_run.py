@@ -4,7 +4,8 @@ is preceded by a varying pause of its wave). Every solve, each on the entries
 in a new seeded order, must give the oracle's labels; the direct, regrouped and
 one-XCD hooks, the 64-bit path and the batched launch (parent arrays in LDS and
 in HBM) are all exercised. Exit status 0 when every
-solve agrees. Started by tests/test_gpu_stress_delays.py."""
+solve agrees. Started by tests/test_gpu_stress_delays.py; with --full it also
+solves the bench's R-MAT-26 + extras workload (about a minute more)."""
 import os
 import sys
 
@@ -17,10 +18,14 @@ import oracle  # noqa: E402
 import paper_2507_03695_amd as cc  # noqa: E402
 
 
-def main() -> int:
+def main(full: bool = False) -> int:
     assert os.path.basename(cc.LIB_PATH) == "libccmi_stress.so", cc.LIB_PATH
     cc.load()
-    cases = [
+    cases = []
+    if full:
+        g = graphgen.rmat26_extras()
+        cases.append(("rmat26_extras", g.n, g.edges, 1))
+    cases += [
         ("er_2^14", 1 << 14, graphgen.er(1 << 14, 1 << 16, 301), 4),
         ("rmat_2^16", 1 << 16, graphgen.rmat(16, 1 << 20, 302), 3),   # one-XCD plain hook
         ("rmat_2^20_2^24", 1 << 20, graphgen.rmat(20, 1 << 24, 303), 2),  # regrouped hooks
@@ -72,4 +77,4 @@ def main() -> int:
 
 
 if __name__ == "__main__":
-    sys.exit(main())
+    sys.exit(main(full="--full" in sys.argv[1:]))
