@@ -458,7 +458,11 @@ def bench_csr(cc, torch, ed, n, L_ref, steps=3):
             assert ctx.sync(stream) == cc.CC_OK
             ts.append(a.elapsed_time(b))
         ms = float(np.median(ts))
+        # compulsory bytes: adj once (4 B per entry), the offsets once (8 B per
+        # row), and 12 B per vertex (init, compress, labels)
+        alg = 4 * m + 8 * (n + 1) + 12 * n
         out[name] = {"ms_per_step": round(ms, 3), "GTEPS": round(m / (ms * 1e-3) / 1e9, 3),
+                     "hbm_roofline_frac_whole_path": round(alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
                      "identical_labels": bool(torch.equal(L, L_ref))}
         if flags:
             out[name]["zero_root_exact"] = ctx.get_zroot()
