@@ -90,6 +90,14 @@ int cc_version(void);
    in the same pass (what cc_canon writes), so that no cc_canon is needed.
    Ignored elsewhere; the whole-path entry points always do this. */
 #define CC_F_CANON        0x20u
+/* The list holds every pair in both orders (a symmetrised COO list, or a
+   symmetric CSR graph): only the entries with u < v are hooked, so each edge
+   is processed once (Sec. II: once (u,v) has been processed, (v,u) changes
+   nothing; a symmetric graph needs one direction of each edge). The other
+   entries are still read (and range-checked), not hooked. On a list that is
+   not symmetric the labels are those of its u < v entries alone. Accepted by
+   the whole-path calls (also cc_solve_u64), cc_hook and cc_hook_log. */
+#define CC_F_SYMMETRIC    0x40u
 
 /* ---- context ----------------------------------------------------------- */
 typedef struct cc_ctx cc_ctx;
@@ -126,19 +134,50 @@ void cc_destroy(cc_ctx* ctx);
  */
 int cc_solve(uint64_t n, uint64_t m, const uint32_t* edge_list, uint32_t* L);
 
+/* ---- per-call status -------------------------------------------------------
+ * The outcome of one asynchronous whole-path call (cc_solve_async,
+ * cc_solve_csr, cc_solve_u64) that was given a cc_status_t. The caller owns
+ * the struct; the library fills it when the call is enqueued (its fields are
+ * the library's), and cc_status_wait resolves it. Each such call ends its
+ * stream work by moving the context's status word into one record of a ring
+ * of CC_STATUS_RING records kept by the context (pinned host memory), so the
+ * outcome belongs to that call alone even when several calls are queued on
+ * one stream before anyone waits. */
+#define CC_STATUS_RING 256
+typedef struct cc_status_t {
+    cc_ctx*  ctx;     /* the context of the call                                */
+    uint64_t seq;     /* the call's number on its context (from 1; 0 = unset)  */
+    uint32_t slot;    /* its record in the context's ring                      */
+    uint32_t pad;
+} cc_status_t;
+
+/* Wait until the stream work of the call that filled *st has completed and
+   return that call's outcome: CC_OK, CC_ERANGE (an endpoint >= n; its labels
+   are unspecified) or CC_EINVAL (CSR offsets that are not a valid row index).
+   The outcome covers what the call enqueued plus any step calls queued on the
+   same context since the previous outcome was taken (by another such call or
+   by cc_sync). timeout_us < 0 waits without limit; CC_ETIMEDOUT when the work
+   has not completed in time (wait again later). A status may be waited for
+   any number of times until CC_STATUS_RING later calls with a status on the
+   same context have reused its record (then CC_EINVAL). The context must
+   outlive the wait. */
+int cc_status_wait(cc_status_t* st, int64_t timeout_us);
+
 /*
  * Enqueue the whole path on `stream` and return without waiting:
  * init (Algorithm 1 / 3 initialisation), [zero root + Initial Push when
  * CC_F_ZROOT], hook (one pass over the entries), compress (pointer jumping)
  * and, with CC_F_ZROOT, the min-ID relabelling of the zero root's component.
- * Argument errors are returned at once; out-of-range endpoints are recorded
- * in the context's status word and reported by the next cc_sync.
+ * Argument errors are returned at once. Out-of-range endpoints are reported
+ * through `st` when it is not NULL (cc_status_wait), otherwise they stay in
+ * the context's status word for the next cc_sync.
  * Buffers must stay valid until the stream reaches the end of this work.
- * Solves queued on one context share its status word and zero-root state:
- * queue them on one stream, or use one context per concurrent stream.
+ * Solves queued on one context share its scratch and zero-root state: queue
+ * them on one stream, or use one context per concurrent stream.
  */
 int cc_solve_async(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edge_list,
-                   uint32_t* L, uint32_t flags, uint32_t zroot_hint, void* stream);
+                   uint32_t* L, uint32_t flags, uint32_t zroot_hint, void* stream,
+                   cc_status_t* st);
 
 /* The whole path on CSR input: row u of the graph holds the entries
    (u, adj[j]) for j in [offsets[u], offsets[u+1]), unordered pairs as in the
@@ -160,9 +199,10 @@ int cc_solve_async(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edge_lis
               component
    Offsets that are not a valid row index make the next cc_sync return
    CC_EINVAL (labels unspecified; no access leaves the arrays). Asynchronous
-   after the read-back; status through cc_sync. */
+   after the read-back; status through `st` (cc_status_wait) when it is not
+   NULL, else through cc_sync. */
 int cc_solve_csr(cc_ctx* ctx, uint64_t n, const uint64_t* offsets, const uint32_t* adj, uint32_t* L,
-                 uint32_t flags, uint32_t zroot_hint, void* stream);
+                 uint32_t flags, uint32_t zroot_hint, void* stream, cc_status_t* st);
 
 /* The plain path (Algorithm 1: init, hook with path splitting, pointer
    jumping) with 8-byte vertex IDs, for vertex counts at and beyond 2^32
@@ -171,13 +211,15 @@ int cc_solve_csr(cc_ctx* ctx, uint64_t n, const uint64_t* offsets, const uint32_
      edges  device, 2*m uint64 as (u_i, v_i) pairs, each < n (others set
             CC_ERANGE at cc_sync and are skipped)
      L      device, n uint64, written: L_v = smallest ID of v's component
-     flags  0 or CC_F_NO_SPLIT (anything else: CC_EINVAL)
-   Asynchronous on `stream`; status through cc_sync. */
+     flags  CC_F_NO_SPLIT and CC_F_SYMMETRIC (anything else: CC_EINVAL)
+   Asynchronous on `stream`; status through `st` (cc_status_wait) when it is
+   not NULL, else through cc_sync. */
 int cc_solve_u64(cc_ctx* ctx, uint64_t n, uint64_t m, const uint64_t* edges, uint64_t* L,
-                 uint32_t flags, void* stream);
+                 uint32_t flags, void* stream, cc_status_t* st);
 
 /* Wait for `stream`, then return (and clear) the status accumulated by the
-   context's work since the previous cc_sync: CC_OK, CC_ERANGE, CC_ENOMEM
+   context's work since the previous cc_sync (or since the last call whose
+   outcome went to a cc_status_t): CC_OK, CC_ERANGE, CC_ENOMEM
    (an update log of cc_hook_log ran out of capacity) or CC_EINVAL (CSR
    offsets of cc_solve_csr were not a valid row index). */
 int cc_sync(cc_ctx* ctx, void* stream);

@@ -28,7 +28,8 @@ LIB_PATH = os.environ.get("CCMI_LIBRARY") or os.path.join(_PKG, "libccmi.so")
 CC_OK, CC_EINVAL, CC_ERANGE, CC_ENOMEM, CC_EDEVICE, CC_EAGAIN, CC_ECANCELED, CC_ETIMEDOUT = \
     0, -1, -2, -3, -4, -5, -6, -7
 F_ZROOT, F_ZROOT_EXACT, F_ZROOT_HINT, F_NO_SPLIT, F_NO_TILE = 0x1, 0x2, 0x4, 0x8, 0x10
-F_CANON = 0x20
+F_CANON, F_SYMMETRIC = 0x20, 0x40
+STATUS_RING = 256
 
 
 class CCError(RuntimeError):
@@ -51,6 +52,13 @@ class _ServeOpts(ctypes.Structure):
                 ("hbm_budget", ctypes.c_uint64)]
 
 
+class Status(ctypes.Structure):
+    """cc_status_t: the outcome of one asynchronous whole-path call; pass it as
+    `status=` and resolve it with Context.status_wait."""
+    _fields_ = [("ctx", ctypes.c_void_p), ("seq", ctypes.c_uint64), ("slot", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32)]
+
+
 class ReqStats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("batched", ctypes.c_uint32),
                 ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
@@ -69,10 +77,11 @@ SIGNATURES = {
     "cc_create": (_I32, [ctypes.POINTER(_P), ctypes.POINTER(_CtxOpts)]),
     "cc_destroy": (None, [_P]),
     "cc_solve": (_I32, [_U64, _U64, _P, _P]),
-    "cc_solve_async": (_I32, [_P, _U64, _U64, _P, _P, _U32, _U32, _P]),
+    "cc_solve_async": (_I32, [_P, _U64, _U64, _P, _P, _U32, _U32, _P, ctypes.POINTER(Status)]),
+    "cc_status_wait": (_I32, [ctypes.POINTER(Status), _I64]),
     "cc_sync": (_I32, [_P, _P]),
-    "cc_solve_csr": (_I32, [_P, _U64, _P, _P, _P, _U32, _U32, _P]),
-    "cc_solve_u64": (_I32, [_P, _U64, _U64, _P, _P, _U32, _P]),
+    "cc_solve_csr": (_I32, [_P, _U64, _P, _P, _P, _U32, _U32, _P, ctypes.POINTER(Status)]),
+    "cc_solve_u64": (_I32, [_P, _U64, _U64, _P, _P, _U32, _P, ctypes.POINTER(Status)]),
     "cc_init": (_I32, [_P, _U64, _P, _P]),
     "cc_zroot": (_I32, [_P, _U64, _U64, _P, _U32, _U32, _P]),
     "cc_push": (_I32, [_P, _U64, _U64, _P, _P, _P]),
@@ -146,6 +155,10 @@ def _stream(stream) -> int | None:
     return int(stream) or None
 
 
+def _st(status):
+    return None if status is None else ctypes.byref(status)
+
+
 def solve(edges: torch.Tensor, n: int, out: torch.Tensor | None = None) -> torch.Tensor:
     """cc_solve: labels L (n entries, dtype of `edges`) with L_v = min ID of v's component.
 
@@ -194,16 +207,26 @@ class Context:
         self.close()
 
     # whole path
-    def solve_async(self, edges, n, L, flags=0, zroot_hint=0, stream=None):
+    def solve_async(self, edges, n, L, flags=0, zroot_hint=0, stream=None, status=None):
+        """cc_solve_async; with status (a Status), the call's own outcome goes there
+        (Context.status_wait) instead of to the context's status word."""
         m = edges.shape[0] if edges.dim() == 2 else edges.numel() // 2
         _check(self.lib.cc_solve_async(self._h, n, m, _dptr(edges, _ID), _dptr(L, _ID), flags,
-                                       zroot_hint, _stream(stream)), "cc_solve_async")
+                                       zroot_hint, _stream(stream), _st(status)), "cc_solve_async")
 
-    def solve_csr_async(self, offsets, adj, n, L, flags=0, zroot_hint=0, stream=None):
+    def status_wait(self, status, timeout_us: int = -1) -> int:
+        """cc_status_wait: the outcome of the call that filled `status` (CC_OK,
+        CC_ERANGE, CC_EINVAL or CC_ETIMEDOUT), without raising for those."""
+        rc = self.lib.cc_status_wait(ctypes.byref(status), timeout_us)
+        if rc not in (CC_OK, CC_ERANGE, CC_EINVAL, CC_ETIMEDOUT):
+            _check(rc, "cc_status_wait")
+        return rc
+
+    def solve_csr_async(self, offsets, adj, n, L, flags=0, zroot_hint=0, stream=None, status=None):
         """cc_solve_csr: offsets (n+1,) int64 and adj (m,) ID tensors on the device."""
         _check(self.lib.cc_solve_csr(self._h, n, _dptr(offsets, (torch.int64, torch.uint64)),
                                      _dptr(adj, _ID), _dptr(L, _ID), flags, zroot_hint,
-                                     _stream(stream)), "cc_solve_csr")
+                                     _stream(stream), _st(status)), "cc_solve_csr")
 
     def solve_csr(self, offsets, adj, n, flags=0, zroot_hint=0, out=None, stream=None):
         if out is None:
@@ -212,11 +235,11 @@ class Context:
         _check(self.sync(stream), "solve_csr")
         return out
 
-    def solve_u64_async(self, edges, n, L, flags=0, stream=None):
+    def solve_u64_async(self, edges, n, L, flags=0, stream=None, status=None):
         """cc_solve_u64: edges (m, 2) and L (n,) int64 device tensors (IDs as uint64 bits)."""
         _W = (torch.int64, torch.uint64)
         _check(self.lib.cc_solve_u64(self._h, n, edges.shape[0], _dptr(edges, _W), _dptr(L, _W),
-                                     flags, _stream(stream)), "cc_solve_u64")
+                                     flags, _stream(stream), _st(status)), "cc_solve_u64")
 
     def solve_u64(self, edges, n, flags=0, out=None, stream=None):
         if out is None:

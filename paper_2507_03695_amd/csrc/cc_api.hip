@@ -1,17 +1,33 @@
 // cc_api.hip — the C ABI of include/cc.h: contexts, argument checks, the
 // single-graph entry points and the step entry points.
-#include <mutex>
+#include <time.h>
+
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "cc_internal.h"
+
+// One record of a context's per-call status ring (pinned host memory): the
+// status bits the call's work produced, then the call's number, both written by
+// the device at the end of the call's stream work.
+struct StatusRec {
+    uint32_t bits;
+    uint32_t pad;
+    uint64_t seq;
+};
 
 struct cc_ctx {
     int device = 0;
     ccm::Slot slot;
     uint64_t hbm_budget = 0;
     uint32_t samples = 0;
+    // per-call status (cc_status_t): created on first use
+    std::mutex st_mu;
+    StatusRec* st_ring = nullptr;
+    hipEvent_t st_ev[CC_STATUS_RING] = {};
+    uint64_t st_seq = 0;
 };
 
 namespace ccm {
@@ -96,17 +112,33 @@ __global__ void k_status_take(DevState* st, uint32_t* out) {
     }
 }
 
+// The status code of a word of kStatus* bits (the most severe one first).
+int status_code(uint32_t w) {
+    if (w & kStatusInternal) return fail(CC_EDEVICE, "internal scratch bound exceeded");
+    if (w & kStatusRange) return fail(CC_ERANGE, "an endpoint is >= n");
+    if (w & kStatusBadOffsets) return fail(CC_EINVAL, "CSR offsets are not a valid row index");
+    if (w & kStatusLogFull) return fail(CC_ENOMEM, "update log capacity exceeded");
+    return CC_OK;
+}
+
 int slot_sync(Slot* s, hipStream_t stream) {
     // read-and-clear in one kernel writing to pinned host memory
     k_status_take<<<1, 64, 0, stream>>>(s->st, s->host_status);
     CCM_HIP(hipGetLastError());
     CCM_HIP(hipStreamSynchronize(stream));
     const uint32_t w = __atomic_load_n(s->host_status, __ATOMIC_ACQUIRE);
-    if (w & kStatusInternal) return fail(CC_EDEVICE, "internal scratch bound exceeded");
-    if (w & kStatusRange) return fail(CC_ERANGE, "an endpoint is >= n");
-    if (w & kStatusBadOffsets) return fail(CC_EINVAL, "CSR offsets are not a valid row index");
-    if (w & kStatusLogFull) return fail(CC_ENOMEM, "update log capacity exceeded");
-    return CC_OK;
+    return status_code(w);
+}
+
+// Moves the status word into a per-call record: the bits, then the call's
+// number (system-scope stores to pinned host memory).
+__global__ void k_status_record(DevState* st, uint32_t* bits, uint64_t* seq_out, uint64_t seq) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const uint32_t w = __hip_atomic_exchange(&st->status, 0u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(bits, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(seq_out, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 }
 
 }  // namespace ccm
@@ -172,7 +204,10 @@ int ctx_info(cc_ctx* ctx, int* device, uint64_t* budget, uint32_t* samples) {
 
 extern "C" void cc_destroy(cc_ctx* ctx) {
     if (!ctx) return;
-    slot_destroy(&ctx->slot);
+    slot_destroy(&ctx->slot);    // waits for the device
+    for (auto& e : ctx->st_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->st_ring) (void)hipHostFree(ctx->st_ring);
     delete ctx;
 }
 
@@ -209,7 +244,90 @@ int set_dev(cc_ctx* ctx) {
     return CC_OK;
 }
 
+constexpr uint32_t kKnownFlags = CC_F_ZROOT | CC_F_ZROOT_EXACT | CC_F_ZROOT_HINT | CC_F_NO_SPLIT |
+                                 CC_F_NO_TILE | CC_F_CANON | CC_F_SYMMETRIC;
+
+int check_flags(uint32_t flags) {
+    if (flags & ~kKnownFlags) return fail(CC_EINVAL, "unknown flag bits");
+    return CC_OK;
+}
+
+// After a whole-path call's kernels: record its outcome in the next ring slot
+// and fill *st (nothing when st is NULL: the outcome stays for cc_sync).
+int finish_status(cc_ctx* ctx, hipStream_t stream, cc_status_t* st) {
+    if (!st) return CC_OK;
+    std::lock_guard<std::mutex> lk(ctx->st_mu);
+    if (!ctx->st_ring) {
+        StatusRec* ring = nullptr;
+        if (hipHostMalloc(&ring, sizeof(StatusRec) * CC_STATUS_RING, hipHostMallocCoherent) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CC_ENOMEM, "status ring allocation failed");
+        }
+        std::memset(ring, 0, sizeof(StatusRec) * CC_STATUS_RING);
+        for (auto& e : ctx->st_ev) {
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(CC_EDEVICE, "status event creation failed");
+            }
+        }
+        ctx->st_ring = ring;
+    }
+    const uint64_t seq = ++ctx->st_seq;
+    const uint32_t slot = (uint32_t)(seq % CC_STATUS_RING);
+    StatusRec* r = &ctx->st_ring[slot];
+    k_status_record<<<1, 64, 0, stream>>>(ctx->slot.st, &r->bits, &r->seq, seq);
+    CCM_HIP(hipGetLastError());
+    CCM_HIP(hipEventRecord(ctx->st_ev[slot], stream));
+    st->ctx = ctx;
+    st->seq = seq;
+    st->slot = slot;
+    st->pad = 0;
+    return CC_OK;
+}
+
+uint64_t mono_us() {
+    timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (uint64_t)ts.tv_sec * 1000000ull + (uint64_t)ts.tv_nsec / 1000;
+}
+
 }  // namespace
+
+extern "C" int cc_status_wait(cc_status_t* st, int64_t timeout_us) {
+    if (!st || !st->ctx || !st->seq || st->slot >= CC_STATUS_RING)
+        return fail(CC_EINVAL, "status not filled by a call");
+    cc_ctx* ctx = st->ctx;
+    hipEvent_t ev = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(ctx->st_mu);
+        if (!ctx->st_ring || st->seq > ctx->st_seq) return fail(CC_EINVAL, "unknown status");
+        if (ctx->st_seq - st->seq >= CC_STATUS_RING)
+            return fail(CC_EINVAL, "status record reused by later calls");
+        ev = ctx->st_ev[st->slot];
+    }
+    int rc = set_dev(ctx);
+    if (rc) return rc;
+    if (timeout_us < 0) {
+        CCM_HIP(hipEventSynchronize(ev));
+    } else {
+        const uint64_t t_end = mono_us() + (uint64_t)timeout_us;
+        while (true) {
+            const hipError_t e = hipEventQuery(ev);
+            if (e == hipSuccess) break;
+            if (e != hipErrorNotReady) return hip_fail(e, "hipEventQuery");
+            if (mono_us() >= t_end) return CC_ETIMEDOUT;
+            timespec ts{0, 20000};
+            nanosleep(&ts, nullptr);
+        }
+    }
+    const StatusRec* r = &ctx->st_ring[st->slot];
+    const uint64_t seq = __atomic_load_n(&r->seq, __ATOMIC_ACQUIRE);
+    const uint32_t bits = __atomic_load_n(&r->bits, __ATOMIC_RELAXED);
+    if (seq != st->seq || __atomic_load_n(&r->seq, __ATOMIC_ACQUIRE) != seq)
+        return fail(CC_EINVAL, "status record reused by later calls");
+    return status_code(bits);
+}
 
 // ---- single graph ---------------------------------------------------------------------------
 
@@ -225,47 +343,56 @@ extern "C" int cc_solve(uint64_t n, uint64_t m, const uint32_t* edge_list, uint3
 }
 
 extern "C" int cc_solve_async(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edge_list,
-                              uint32_t* L, uint32_t flags, uint32_t zroot_hint, void* stream) {
+                              uint32_t* L, uint32_t flags, uint32_t zroot_hint, void* stream,
+                              cc_status_t* st) {
     if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
     int rc = check_graph(n, m, edge_list, L);
     if (rc) return rc;
+    if ((rc = check_flags(flags))) return rc;
     if ((flags & CC_F_ZROOT_HINT) && n && zroot_hint >= n)
         return fail(CC_EINVAL, "zroot_hint must be < n");
     if ((rc = set_dev(ctx))) return rc;
-    return run_solve(&ctx->slot, n, m, edge_list, L, flags, zroot_hint, (hipStream_t)stream);
+    if ((rc = run_solve(&ctx->slot, n, m, edge_list, L, flags, zroot_hint, (hipStream_t)stream)))
+        return rc;
+    return finish_status(ctx, (hipStream_t)stream, st);
 }
 
 extern "C" int cc_solve_csr(cc_ctx* ctx, uint64_t n, const uint64_t* offsets, const uint32_t* adj,
-                            uint32_t* L, uint32_t flags, uint32_t zroot_hint, void* stream) {
+                            uint32_t* L, uint32_t flags, uint32_t zroot_hint, void* stream,
+                            cc_status_t* st) {
     if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
     if (n >= (1ull << 32)) return fail(CC_EINVAL, "n must be < 2^32");
-    if (n == 0) return CC_OK;
+    if (check_flags(flags)) return CC_EINVAL;
+    if (n == 0) return finish_status(ctx, (hipStream_t)stream, st);
     if (!offsets || !L) return fail(CC_EINVAL, "NULL offsets or L");
     if ((flags & CC_F_ZROOT_HINT) && zroot_hint >= n) return fail(CC_EINVAL, "zroot_hint must be < n");
     int rc = set_dev(ctx);
     if (rc) return rc;
-    hipStream_t st = (hipStream_t)stream;
+    hipStream_t hs = (hipStream_t)stream;
     // the entry count sizes the launches: read off[n] (a coherent copy)
-    if ((rc = cohere(st))) return rc;
+    if ((rc = cohere(hs))) return rc;
     uint64_t* hm = reinterpret_cast<uint64_t*>(ctx->slot.host_status);
-    CCM_HIP(hipMemcpyAsync(hm, offsets + n, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-    CCM_HIP(hipStreamSynchronize(st));
+    CCM_HIP(hipMemcpyAsync(hm, offsets + n, sizeof(uint64_t), hipMemcpyDeviceToHost, hs));
+    CCM_HIP(hipStreamSynchronize(hs));
     const uint64_t m = *hm;
     *hm = 0;
     if (m && !adj) return fail(CC_EINVAL, "NULL adj with a nonzero entry count");
     if (m > (1ull << 40)) return fail(CC_EINVAL, "offsets[n] is implausibly large");
-    return run_solve_csr(&ctx->slot, n, m, offsets, adj, L, flags, zroot_hint, st);
+    if ((rc = run_solve_csr(&ctx->slot, n, m, offsets, adj, L, flags, zroot_hint, hs))) return rc;
+    return finish_status(ctx, hs, st);
 }
 
 extern "C" int cc_solve_u64(cc_ctx* ctx, uint64_t n, uint64_t m, const uint64_t* edges, uint64_t* L,
-                            uint32_t flags, void* stream) {
+                            uint32_t flags, void* stream, cc_status_t* st) {
     if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
     if (n >> 62) return fail(CC_EINVAL, "n must be < 2^62");
-    if (n == 0) return CC_OK;
-    if (!L || (m && !edges)) return fail(CC_EINVAL, "NULL L, or NULL edges with m > 0");
+    if (check_flags(flags)) return CC_EINVAL;
     int rc = set_dev(ctx);
     if (rc) return rc;
-    return run_solve_w(&ctx->slot, n, m, edges, L, flags, (hipStream_t)stream);
+    if (n == 0) return finish_status(ctx, (hipStream_t)stream, st);
+    if (!L || (m && !edges)) return fail(CC_EINVAL, "NULL L, or NULL edges with m > 0");
+    if ((rc = run_solve_w(&ctx->slot, n, m, edges, L, flags, (hipStream_t)stream))) return rc;
+    return finish_status(ctx, (hipStream_t)stream, st);
 }
 
 extern "C" int cc_sync(cc_ctx* ctx, void* stream) {

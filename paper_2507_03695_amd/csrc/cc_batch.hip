@@ -97,11 +97,14 @@ __device__ __forceinline__ void solve_graph16(uint32_t* P32, uint32_t n, gedge_t
     // is reloaded with entry k of the next round right after entry k is linked,
     // so the next round's loads are in flight while this round is processed.
     constexpr int64_t kRound = (int64_t)kBatchBlock * kBatchEPT;
+    // A graph without entries issues no edge load at all: its entry pointer may
+    // be NULL (an edge-free batch) or point one past the batch's last entry.
     i32x2 x[kBatchEPT];
 #pragma unroll
     for (int k = 0; k < kBatchEPT; ++k) {
         const int64_t e = tid + (int64_t)k * kBatchBlock;
-        x[k] = __builtin_nontemporal_load(E + (e < m ? e : 0));
+        x[k] = i32x2{0, 0};
+        if (m > 0) x[k] = __builtin_nontemporal_load(E + (e < m ? e : 0));
     }
     for (int64_t e0 = tid; e0 < m; e0 += kRound) {
         // every entry's two parent reads first (LDS latency overlaps), then the links

@@ -133,12 +133,13 @@ int slot_sync(Slot* s, hipStream_t stream);
 bool tiled_eligible(uint64_t n, uint64_t m);
 // plain = true: the plain path (key = ID) hooks the first-endpoint buckets in
 // order instead (better locality for the first endpoints' parent reads).
+// sym: the list holds every pair in both orders; only u < v is hooked.
 int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
-                   hipStream_t stream, bool plain = false);
+                   hipStream_t stream, bool plain = false, bool sym = false);
 void tiled_free(TiledScratch* t);
 // The same on CSR input, where the rows already are the first-endpoint buckets.
 int run_hook_tiled_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, const uint32_t* adj,
-                       uint32_t* P, hipStream_t stream);
+                       uint32_t* P, hipStream_t stream, bool sym = false);
 
 // Batched path (cc_batch.hip).
 // Enqueue one persistent launch over G graphs described on the host.

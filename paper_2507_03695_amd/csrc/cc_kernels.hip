@@ -318,12 +318,14 @@ __device__ __forceinline__ void log_append(const uint32_t (&child)[kEPT],
 // Hooking of the kEPT entries (u[k], v[k]) a thread holds (entries beyond the
 // input are passed as (0, 0): a self-loop, skipped); z is the zero root (ZR). Shared by the COO and the
 // CSR launches. LOG (plain path only): the links made are appended to `log`
-// (see log_append); every thread of the block must then call it.
+// (see log_append); every thread of the block must then call it. sym: the
+// list holds every pair in both orders, so only the entries with u < v are
+// hooked (each edge once; Sec. II: processing (u,v) makes (v,u) a no-op).
 template <bool ZR, int SPLIT, bool LOG>
 __device__ __forceinline__ void hook_entries(uint32_t (&u)[kEPT], uint32_t (&v)[kEPT], uint32_t n,
                                              uint32_t z, uint32_t* P, uint32_t* zbits,
                                              DevState* st, uint32_t* log, uint64_t log_cap,
-                                             unsigned long long* log_count) {
+                                             unsigned long long* log_count, bool sym) {
     static_assert(!(ZR && LOG), "the update log belongs to the plain path");
     bool bad = false;
 #pragma unroll
@@ -333,7 +335,7 @@ __device__ __forceinline__ void hook_entries(uint32_t (&u)[kEPT], uint32_t (&v)[
     if (bad) atomicOr(&st->status, kStatusRange);
     bool live[kEPT];
 #pragma unroll
-    for (int k = 0; k < kEPT; ++k) live[k] = u[k] != v[k];
+    for (int k = 0; k < kEPT; ++k) live[k] = sym ? u[k] < v[k] : u[k] != v[k];
     bool inu[kEPT] = {}, inv[kEPT] = {};
     if (ZR) {
         uint32_t bu[kEPT], bv[kEPT];
@@ -394,8 +396,8 @@ __device__ __forceinline__ void hook_entries(uint32_t (&u)[kEPT], uint32_t (&v)[
 template <bool ZR, int SPLIT, bool LOG = false>
 __global__ __launch_bounds__(kBlock) void k_hook(const uint32_t* __restrict__ edges, uint64_t m,
                                                  uint32_t n, uint32_t* P, uint32_t* zbits,
-                                                 DevState* st, uint32_t* log = nullptr,
-                                                 uint64_t log_cap = 0,
+                                                 DevState* st, uint32_t sym,
+                                                 uint32_t* log = nullptr, uint64_t log_cap = 0,
                                                  unsigned long long* log_count = nullptr) {
     const uint32_t z = ZR ? ld_agent(&st->zroot) : 0u;
     const uint64_t tile = (uint64_t)blockIdx.x * (kBlock * kEPT);
@@ -409,7 +411,7 @@ __global__ __launch_bounds__(kBlock) void k_hook(const uint32_t* __restrict__ ed
         u[k] = uv.x;
         v[k] = uv.y;
     }
-    hook_entries<ZR, SPLIT, LOG>(u, v, n, z, P, zbits, st, log, log_cap, log_count);
+    hook_entries<ZR, SPLIT, LOG>(u, v, n, z, P, zbits, st, log, log_cap, log_count, sym != 0);
 }
 
 // The same hook confined to one XCD, for parent arrays small enough to live in
@@ -423,7 +425,7 @@ constexpr uint32_t kXcds = 8;
 template <bool ZR, int SPLIT>
 __global__ __launch_bounds__(kBlock) void k_hook_xcd(const uint32_t* __restrict__ edges, uint64_t m,
                                                      uint32_t n, uint32_t* P, uint32_t* zbits,
-                                                     DevState* st) {
+                                                     DevState* st, uint32_t sym) {
     if (blockIdx.x % kXcds != 0) return;
     const uint64_t workers = gridDim.x / kXcds;
     const uint32_t z = ZR ? ld_agent(&st->zroot) : 0u;
@@ -439,7 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_hook_xcd(const uint32_t* __restrict_
             u[k] = uv.x;
             v[k] = uv.y;
         }
-        hook_entries<ZR, SPLIT, false>(u, v, n, z, P, zbits, st, nullptr, 0, nullptr);
+        hook_entries<ZR, SPLIT, false>(u, v, n, z, P, zbits, st, nullptr, 0, nullptr, sym != 0);
     }
 }
 
@@ -543,7 +545,7 @@ __global__ __launch_bounds__(kBlock) void k_csr_hook(const uint64_t* __restrict_
                                                      const uint32_t* __restrict__ adj, uint32_t n,
                                                      uint64_t m, const uint32_t* __restrict__ tstart,
                                                      uint64_t ntiles, uint32_t* P, uint32_t* zbits,
-                                                     DevState* st) {
+                                                     DevState* st, uint32_t sym) {
     __shared__ uint32_t head[kCsrTile];
     __shared__ uint32_t s_wmax[kBlock / 64];
     const uint32_t z = ZR ? ld_agent(&st->zroot) : 0u;
@@ -629,7 +631,7 @@ __global__ __launch_bounds__(kBlock) void k_csr_hook(const uint64_t* __restrict_
         const uint64_t p = p0 + (uint64_t)k * kBlock + threadIdx.x;
         if (p >= m) u[k] = v[k] = 0;
     }
-    hook_entries<ZR, SPLIT, false>(u, v, n, z, P, zbits, st, nullptr, 0, nullptr);
+    hook_entries<ZR, SPLIT, false>(u, v, n, z, P, zbits, st, nullptr, 0, nullptr, sym != 0);
     __syncthreads();                                    // head of this tile fully used
     }
 }
@@ -904,10 +906,11 @@ int run_hook(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P
     if (blocks > 0x7FFFFFFFull) return fail(CC_EINVAL, "edge count too large for one launch");
     const bool zr = flags & CC_F_ZROOT;
     const bool split = !(flags & CC_F_NO_SPLIT);
+    const uint32_t sym = (flags & CC_F_SYMMETRIC) ? 1u : 0u;
     if (zr && (!s->zr_ready || s->cur_n != n))
         return fail(CC_EINVAL, "a CC_F_ZROOT hook needs cc_init then cc_zroot on the same n");
     if (split && !(flags & CC_F_NO_TILE) && tiled_eligible(n, m))
-        return run_hook_tiled(s, n, m, edges, P, stream, /*plain=*/!zr);
+        return run_hook_tiled(s, n, m, edges, P, stream, /*plain=*/!zr, sym != 0);
     const uint32_t n32 = (uint32_t)n;
     uint32_t* zb = s->zbits;
     const uint32_t g = (uint32_t)blocks;
@@ -917,15 +920,15 @@ int run_hook(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P
         // the hot array over eight L2s (the zero-root hook gains nothing: its
         // bitmap tests drop most entries before they touch P)
         const uint32_t gx = kXcds * (uint32_t)std::min<uint64_t>(blocks, 256);
-        if (split) k_hook_xcd<false, 1><<<gx, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st);
-        else k_hook_xcd<false, 0><<<gx, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st);
+        if (split) k_hook_xcd<false, 1><<<gx, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st, sym);
+        else k_hook_xcd<false, 0><<<gx, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st, sym);
         CCM_HIP(hipGetLastError());
         return CC_OK;
     }
-    if (zr && split) k_hook<true, 1><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st);
-    else if (zr) k_hook<true, 0><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st);
-    else if (split) k_hook<false, 1><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st);
-    else k_hook<false, 0><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st);
+    if (zr && split) k_hook<true, 1><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st, sym);
+    else if (zr) k_hook<true, 0><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st, sym);
+    else if (split) k_hook<false, 1><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st, sym);
+    else k_hook<false, 0><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st, sym);
     CCM_HIP(hipGetLastError());
     return CC_OK;
 }
@@ -941,12 +944,13 @@ int run_hook_log(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_
     if (blocks > 0x7FFFFFFFull) return fail(CC_EINVAL, "edge count too large for one launch");
     const uint32_t g = (uint32_t)blocks;
     auto* cnt = reinterpret_cast<unsigned long long*>(log_count);
+    const uint32_t sym = (flags & CC_F_SYMMETRIC) ? 1u : 0u;
     if (flags & CC_F_NO_SPLIT)
         k_hook<false, 0, true><<<g, kBlock, 0, stream>>>(edges, m, (uint32_t)n, P, nullptr, s->st,
-                                                         log, log_cap, cnt);
+                                                         sym, log, log_cap, cnt);
     else
         k_hook<false, 1, true><<<g, kBlock, 0, stream>>>(edges, m, (uint32_t)n, P, nullptr, s->st,
-                                                         log, log_cap, cnt);
+                                                         sym, log, log_cap, cnt);
     CCM_HIP(hipGetLastError());
     return CC_OK;
 }
@@ -1027,6 +1031,7 @@ int run_solve_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, const ui
     int rc;
     const bool zr = flags & CC_F_ZROOT;
     const bool split = !(flags & CC_F_NO_SPLIT);
+    const uint32_t sym = (flags & CC_F_SYMMETRIC) ? 1u : 0u;
     const uint64_t ntiles = (m + kCsrTile - 1) / kCsrTile;
     if (ntiles > 0x7FFFFFFFull) return fail(CC_EINVAL, "entry count too large for one launch");
     if (s->csr_tiles_cap < ntiles + 1) {
@@ -1069,29 +1074,29 @@ int run_solve_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, const ui
         if (w) {
             k_csr_hook<true, 1><<<(uint32_t)w, kBlock, 0, stream>>>(off, adj, (uint32_t)n, m,
                                                                    s->csr_tiles, ntiles, L,
-                                                                   s->zbits, s->st);
+                                                                   s->zbits, s->st, sym);
             CCM_HIP(hipGetLastError());
         }
-        if ((rc = run_hook_tiled_csr(s, n, m, off, adj, L, stream))) return rc;
+        if ((rc = run_hook_tiled_csr(s, n, m, off, adj, L, stream, sym != 0))) return rc;
     } else if (ntiles && !zr && n <= kOneXcdMaxN && m >= kOneXcdMinM && !(flags & CC_F_NO_TILE)) {
         // plain hook of a small parent array: one XCD (see k_hook_xcd)
         const uint32_t gx = kXcds * (uint32_t)std::min<uint64_t>(ntiles, 256);
         const uint32_t n32 = (uint32_t)n;
         if (split)
             k_csr_hook<false, 1, true><<<gx, kBlock, 0, stream>>>(off, adj, n32, m, s->csr_tiles, ntiles,
-                                                                 L, s->zbits, s->st);
+                                                                 L, s->zbits, s->st, sym);
         else
             k_csr_hook<false, 0, true><<<gx, kBlock, 0, stream>>>(off, adj, n32, m, s->csr_tiles, ntiles,
-                                                                 L, s->zbits, s->st);
+                                                                 L, s->zbits, s->st, sym);
         CCM_HIP(hipGetLastError());
     } else if (ntiles) {
         const uint32_t g = (uint32_t)ntiles;
         const uint32_t n32 = (uint32_t)n;
         uint32_t* zb = s->zbits;
-        if (zr && split) k_csr_hook<true, 1><<<g, kBlock, 0, stream>>>(off, adj, n32, m, s->csr_tiles, ntiles, L, zb, s->st);
-        else if (zr) k_csr_hook<true, 0><<<g, kBlock, 0, stream>>>(off, adj, n32, m, s->csr_tiles, ntiles, L, zb, s->st);
-        else if (split) k_csr_hook<false, 1><<<g, kBlock, 0, stream>>>(off, adj, n32, m, s->csr_tiles, ntiles, L, zb, s->st);
-        else k_csr_hook<false, 0><<<g, kBlock, 0, stream>>>(off, adj, n32, m, s->csr_tiles, ntiles, L, zb, s->st);
+        if (zr && split) k_csr_hook<true, 1><<<g, kBlock, 0, stream>>>(off, adj, n32, m, s->csr_tiles, ntiles, L, zb, s->st, sym);
+        else if (zr) k_csr_hook<true, 0><<<g, kBlock, 0, stream>>>(off, adj, n32, m, s->csr_tiles, ntiles, L, zb, s->st, sym);
+        else if (split) k_csr_hook<false, 1><<<g, kBlock, 0, stream>>>(off, adj, n32, m, s->csr_tiles, ntiles, L, zb, s->st, sym);
+        else k_csr_hook<false, 0><<<g, kBlock, 0, stream>>>(off, adj, n32, m, s->csr_tiles, ntiles, L, zb, s->st, sym);
         CCM_HIP(hipGetLastError());
     }
     if ((rc = cohere(stream))) return rc;

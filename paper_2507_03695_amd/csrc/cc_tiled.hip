@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kPartBlock) void k_t1_part(const uint32_t* __restri
                                                         uint16_t* __restrict__ t1h,
                                                         uint16_t* __restrict__ segT,
                                                         uint32_t* __restrict__ cnt1,
-                                                        DevState* st) {
+                                                        DevState* st, uint32_t sym) {
     __shared__ u32x2 stage[kC1];
     __shared__ uint32_t hist[kMaxSlices + 1];
     __shared__ uint32_t start[kMaxSlices + 1];
@@ -162,7 +162,10 @@ __global__ __launch_bounds__(kPartBlock) void k_t1_part(const uint32_t* __restri
 #pragma unroll
     for (int k = 0; k < kPartEPT; ++k) {
         rank[k] = 0xFFFF;
-        if (e[k].x != e[k].y) rank[k] = (uint16_t)atomicAdd(&hist[e[k].x >> kSliceBits], 1u);
+        // self-loops are dropped; with sym (every pair listed in both orders) so
+        // are the entries with u > v
+        const bool live = sym ? e[k].x < e[k].y : e[k].x != e[k].y;
+        if (live) rank[k] = (uint16_t)atomicAdd(&hist[e[k].x >> kSliceBits], 1u);
     }
     __syncthreads();
     wave_scan_256(hist, start, R);
@@ -563,7 +566,7 @@ __global__ __launch_bounds__(kPartBlock) void k_t2_csr(const uint64_t* __restric
                                                        const uint32_t* __restrict__ cfirst,
                                                        u32x2* __restrict__ tmp2,
                                                        uint16_t* __restrict__ run2T,
-                                                       uint64_t nch2, DevState* st) {
+                                                       uint64_t nch2, DevState* st, uint32_t sym) {
     __shared__ u32x2 stage[kC2];
     // the rows of the positions live in the first half of the sort's staging
     // area: they are read into registers before t2_sort_write first writes it
@@ -670,6 +673,7 @@ __global__ __launch_bounds__(kPartBlock) void k_t2_csr(const uint64_t* __restric
             bad = true;
             vv = uu;                              // skipped as a self-loop
         }
+        if (sym && vv < uu) vv = uu;              // the reverse entry covers it
         e[k].x = uu;
         e[k].y = vv;
     }
@@ -1118,7 +1122,7 @@ void tiled_free(TiledScratch* t) {
 }
 
 int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
-                   hipStream_t stream, bool plain) {
+                   hipStream_t stream, bool plain, bool sym) {
     // Warm-up (zero root): the first 1/1024 of the entries go through the direct
     // hook, so the membership bitmap already holds the core of the zero root's
     // tree when the first tiles load their slices. (Measured on R-MAT-26: from
@@ -1126,7 +1130,8 @@ int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint3
     // random accesses for marks the filter would otherwise set.)
     const uint64_t m0 = plain ? 0 : m >> 10;
     if (m0) {
-        int rc0 = run_hook(s, n, m0, edges, P, CC_F_ZROOT | CC_F_NO_TILE, stream);
+        int rc0 = run_hook(s, n, m0, edges, P,
+                           CC_F_ZROOT | CC_F_NO_TILE | (sym ? CC_F_SYMMETRIC : 0u), stream);
         if (rc0) return rc0;
         edges += 2 * m0;
         m -= m0;
@@ -1174,7 +1179,7 @@ int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint3
     int rc1;
     if ((rc1 = cohere(stream))) return rc1;
     k_t1_part<<<(uint32_t)pl.nch1, kPartBlock, 0, stream>>>(edges, m, (uint32_t)n, R, pl.nch1, t1w,
-                                                           t1h, segT, cnt1, s->st);
+                                                           t1h, segT, cnt1, s->st, sym ? 1u : 0u);
     if ((rc1 = cohere(stream))) return rc1;
     k_t1_tsum<<<(uint32_t)R * ntile, kScanBlock, 0, stream>>>(cnt1, pl.nch1, ntile, tsum);
     if ((rc1 = cohere(stream))) return rc1;
@@ -1214,7 +1219,7 @@ int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint3
 
 // The regrouped zero-root hook on CSR input (steps 4-6 on adj's own buckets).
 int run_hook_tiled_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, const uint32_t* adj,
-                       uint32_t* P, hipStream_t stream) {
+                       uint32_t* P, hipStream_t stream, bool sym) {
     const int R = (int)((n + (1ull << kSliceBits) - 1) >> kSliceBits);
     const uint64_t nch2 = m / kC2 + (uint64_t)R + 1;
     auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
@@ -1248,7 +1253,7 @@ int run_hook_tiled_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, con
     k_c_first<<<(uint32_t)gv, 256, 0, stream>>>(off, n, base2, cbase, cfirst);
     if ((rc1 = cohere(stream))) return rc1;
     k_t2_csr<<<(uint32_t)nch2, kPartBlock, 0, stream>>>(off, adj, n, R, base2, cbase, cfirst, tmp2,
-                                                       run2, nch2, s->st);
+                                                       run2, nch2, s->st, sym ? 1u : 0u);
     if ((rc1 = cohere(stream))) return rc1;
     k_t3_regions<<<nwg, 256, 0, stream>>>(run2, nch2, R, cbase, wgcnt);
     if ((rc1 = cohere(stream))) return rc1;

@@ -49,7 +49,8 @@ __device__ __forceinline__ uint64_t find_w(uint64_t* P, uint64_t x, uint64_t px)
 // loads; all parent reads of a thread are issued before any walk.
 template <int SPLIT>
 __global__ __launch_bounds__(kWBlock) void k_hook_w(const uint64_t* __restrict__ edges, uint64_t m,
-                                                    uint64_t n, uint64_t* P, DevState* st) {
+                                                    uint64_t n, uint64_t* P, DevState* st,
+                                                    uint32_t sym) {
     const uint64_t tile = (uint64_t)blockIdx.x * (kWBlock * kWEPT);
     const u64x2* E = reinterpret_cast<const u64x2*>(edges);
     uint64_t u[kWEPT], v[kWEPT];
@@ -66,6 +67,12 @@ __global__ __launch_bounds__(kWBlock) void k_hook_w(const uint64_t* __restrict__
     for (int k = 0; k < kWEPT; ++k)
         if (u[k] >= n || v[k] >= n) { bad = true; u[k] = v[k] = 0; }
     if (bad) atomicOr(&st->status, kStatusRange);
+    // a list with every pair in both orders: hook each edge once, as u < v
+    if (sym) {
+#pragma unroll
+        for (int k = 0; k < kWEPT; ++k)
+            if (v[k] < u[k]) v[k] = u[k];
+    }
     uint64_t pu[kWEPT], pv[kWEPT];
 #pragma unroll
     for (int k = 0; k < kWEPT; ++k) {
@@ -113,8 +120,10 @@ __global__ __launch_bounds__(kWBlock) void k_compress_w(uint64_t* P, uint64_t n)
 int run_solve_w(Slot* s, uint64_t n, uint64_t m, const uint64_t* edges, uint64_t* L,
                 uint32_t flags, hipStream_t stream) {
     if (n == 0) return CC_OK;
-    if (flags & ~(uint32_t)CC_F_NO_SPLIT)
-        return fail(CC_EINVAL, "64-bit IDs take the plain path only (flags: CC_F_NO_SPLIT)");
+    if (flags & ~(uint32_t)(CC_F_NO_SPLIT | CC_F_SYMMETRIC))
+        return fail(CC_EINVAL,
+                    "64-bit IDs take the plain path only (flags: CC_F_NO_SPLIT, CC_F_SYMMETRIC)");
+    const uint32_t sym = (flags & CC_F_SYMMETRIC) ? 1u : 0u;
     const uint64_t per = (uint64_t)kWBlock * kWEPT;
     const uint64_t tiles = (m + per - 1) / per;
     if (tiles > 0x7FFFFFFFull) return fail(CC_EINVAL, "entry count too large for one launch");
@@ -126,9 +135,9 @@ int run_solve_w(Slot* s, uint64_t n, uint64_t m, const uint64_t* edges, uint64_t
     if ((rc = cohere(stream))) return rc;
     if (tiles) {
         if (flags & CC_F_NO_SPLIT)
-            k_hook_w<0><<<(uint32_t)tiles, kWBlock, 0, stream>>>(edges, m, n, L, s->st);
+            k_hook_w<0><<<(uint32_t)tiles, kWBlock, 0, stream>>>(edges, m, n, L, s->st, sym);
         else
-            k_hook_w<1><<<(uint32_t)tiles, kWBlock, 0, stream>>>(edges, m, n, L, s->st);
+            k_hook_w<1><<<(uint32_t)tiles, kWBlock, 0, stream>>>(edges, m, n, L, s->st, sym);
         CCM_HIP(hipGetLastError());
     }
     if ((rc = cohere(stream))) return rc;

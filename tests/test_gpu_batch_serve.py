@@ -109,6 +109,31 @@ def test_batch_per_graph_status(ctx):
     assert Lh[7:11].tolist() == [0, 1, 2, 2]
 
 
+def test_batch_edge_free(ctx):
+    """Regression: graphs without entries issue no edge load. A batch with no
+    entries at all passes a NULL edge pointer; a batch whose last graphs have no
+    entries gives them a pointer one past the last entry. Both against the oracle."""
+    sizes = [5, 1, 300, 70_000, 17]                    # 70,000 > 2^16: the HBM form
+    b = graphgen.batch_from_graphs([(np.zeros((0, 2), np.uint32), n) for n in sizes])
+    vo, eo, _ = batch_to_dev(b)
+    ed = torch.empty((0, 2), dtype=torch.int32, device="cuda")   # passed as NULL
+    log("edge-free batch: G=%d, NULL edges" % b.G)
+    L, st = ctx.batch(vo, eo, ed)
+    want, wst = oracle.cc_labels_batch(b.vtx_off, b.edge_off, b.edges)
+    assert np.array_equal(st.cpu().numpy(), wst)
+    assert_same_labels(L.cpu().numpy().view(np.uint32), want.view(np.uint32), "edge-free batch")
+
+    graphs = [(graphgen.er(400, 900, 41), 400), (graphgen.er(3000, 5000, 42), 3000),
+              (np.zeros((0, 2), np.uint32), 9), (np.zeros((0, 2), np.uint32), 70_001)]
+    b = graphgen.batch_from_graphs(graphs)
+    vo, eo, ed = batch_to_dev(b)
+    log("batch ending in edge-free graphs: G=%d m=%d" % (b.G, int(b.edge_off[-1])))
+    L, st = ctx.batch(vo, eo, ed)
+    want, wst = oracle.cc_labels_batch(b.vtx_off, b.edge_off, b.edges)
+    assert np.array_equal(st.cpu().numpy(), wst)
+    assert_same_labels(L.cpu().numpy().view(np.uint32), want.view(np.uint32), "trailing empty")
+
+
 def test_batch_4096_full(ctx):
     b = graphgen.batch_4096()
     log(f"batch generated: G={b.G} sum n={b.vtx_off[-1]} sum m={b.edge_off[-1]}")

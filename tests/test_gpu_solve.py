@@ -97,7 +97,9 @@ def test_errors(ctx):
     assert lib.cc_solve(5, 3, None, L.data_ptr()) == cc.CC_EINVAL
     assert lib.cc_solve(5, 0, None, None) == cc.CC_EINVAL
     assert lib.cc_solve_async(ctx.handle, 4, 0, None, L.data_ptr(), cc.F_ZROOT | cc.F_ZROOT_HINT,
-                              9, None) == cc.CC_EINVAL
+                              9, None, None) == cc.CC_EINVAL
+    assert lib.cc_solve_async(ctx.handle, 4, 0, None, L.data_ptr(), 0x100, 0, None,
+                              None) == cc.CC_EINVAL                    # unknown flag bit
     # a zero-root hook needs cc_zroot after the latest cc_init
     ctx.init(4, L)
     with pytest.raises(cc.CCError) as ei:
@@ -107,6 +109,90 @@ def test_errors(ctx):
     ctx.init(4, L)
     with pytest.raises(cc.CCError):
         ctx.push(e[:1], 4, L)
+    assert ctx.sync() == cc.CC_OK
+
+
+def test_symmetric_flag(ctx):
+    """CC_F_SYMMETRIC hooks only the u < v entries of a list that holds every pair
+    in both orders: the labels equal the oracle's on the whole list, through the
+    direct, one-XCD and regrouped hooks (sizes on both sides of their limits) and
+    the CSR and 64-bit paths. On a list that is not symmetric the labels are
+    those of its u < v entries alone (the flag's definition)."""
+    cases = [(graphgen.rmat_sym(12, 20_000, 3), 1 << 12),          # direct hook
+             (graphgen.rmat_sym(17, 1 << 18, 4), 1 << 17),         # one-XCD plain hook
+             (graphgen.rmat_sym(20, 1 << 23, 5), 1 << 20)]         # regrouped hooks
+    for e, n in cases:
+        want = oracle.cc_labels(n, e)
+        ed = to_dev(e)
+        for fl in (0, cc.F_ZROOT, cc.F_NO_SPLIT, cc.F_ZROOT | cc.F_NO_TILE):
+            log(f"symmetric n={n} m={len(e)} flags={fl}")
+            L = ctx.solve(ed, n, flags=fl | cc.F_SYMMETRIC)
+            assert_same_labels(to_host_u32(L), want, f"symmetric n={n} flags={fl}")
+        # CSR rows of the same list (a symmetric CSR graph)
+        order = np.lexsort((e[:, 1], e[:, 0]))
+        adj = np.ascontiguousarray(e[order, 1])
+        off = np.zeros(n + 1, np.int64)
+        np.cumsum(np.bincount(e[:, 0], minlength=n), out=off[1:])
+        o_d = torch.from_numpy(off).cuda()
+        a_d = torch.from_numpy(adj.view(np.int32)).cuda()
+        for fl in (0, cc.F_ZROOT):
+            L = ctx.solve_csr(o_d, a_d, n, flags=fl | cc.F_SYMMETRIC)
+            assert_same_labels(to_host_u32(L), want, f"symmetric CSR n={n} flags={fl}")
+    e, n = cases[0]
+    L = ctx.solve_u64(torch.from_numpy(e.astype(np.int64)).cuda(), n, flags=cc.F_SYMMETRIC)
+    assert np.array_equal(L.cpu().numpy(), oracle.cc_labels(n, e).astype(np.int64))
+    # a list that is not symmetric: only its u < v entries count
+    n = 5000
+    e = graphgen.er(n, 12_000, 17)
+    half = e[e[:, 0] < e[:, 1]]
+    want_half = oracle.cc_labels(n, half)
+    assert not np.array_equal(want_half, oracle.cc_labels(n, e))
+    ed = to_dev(e)
+    for fl in (0, cc.F_ZROOT):
+        L = ctx.solve(ed, n, flags=fl | cc.F_SYMMETRIC)
+        assert_same_labels(to_host_u32(L), want_half, f"asymmetric list flags={fl}")
+
+
+def test_per_call_status(ctx):
+    """Each whole-path call given a cc_status_t gets its own outcome, even with
+    several calls queued on one stream before any wait: an out-of-range solve
+    between two good ones reports CC_ERANGE and only there."""
+    n = 3000
+    good = to_dev(graphgen.er(n, 9000, 5))
+    bad_np = graphgen.er(n, 9000, 6)
+    bad_np[4567] = (n + 11, 3)
+    bad = to_dev(bad_np)
+    Ls = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in range(4)]
+    sts = [cc.Status() for _ in range(4)]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ctx.solve_async(good, n, Ls[0], stream=s, status=sts[0])
+        ctx.solve_async(bad, n, Ls[1], flags=cc.F_ZROOT, stream=s, status=sts[1])
+        ctx.solve_async(good, n, Ls[2], flags=cc.F_ZROOT, stream=s, status=sts[2])
+        ctx.solve_async(bad, n, Ls[3], stream=s)                   # no status: cc_sync gets it
+    got = [ctx.status_wait(st) for st in sts[:3]]
+    assert got == [cc.CC_OK, cc.CC_ERANGE, cc.CC_OK]
+    assert ctx.status_wait(sts[1], 0) == cc.CC_ERANGE             # may be waited for again
+    assert ctx.sync(s) == cc.CC_ERANGE
+    want = oracle.cc_labels(n, graphgen.er(n, 9000, 5))
+    for i in (0, 2):
+        assert_same_labels(to_host_u32(Ls[i]), want, f"status solve {i}")
+    assert sts[1].seq == sts[0].seq + 1 and sts[2].seq == sts[0].seq + 2
+    # CSR: offsets that are not a row index give CC_EINVAL through the status
+    o = torch.tensor([0, 2, 1, 2], dtype=torch.int64, device="cuda")
+    a = torch.tensor([1, 2], dtype=torch.int32, device="cuda")
+    L = torch.empty(3, dtype=torch.int32, device="cuda")
+    st = cc.Status()
+    ctx.solve_csr_async(o, a, 3, L, status=st)
+    assert ctx.status_wait(st) == cc.CC_EINVAL
+    # a record reused CC_STATUS_RING calls later is refused
+    first = cc.Status()
+    ctx.solve_async(good, n, Ls[0], status=first)
+    for _ in range(cc.STATUS_RING):
+        ctx.solve_async(good, n, Ls[0], status=cc.Status())
+    assert ctx.status_wait(first) == cc.CC_EINVAL
+    lib = cc.load()
+    assert lib.cc_status_wait(None, 0) == cc.CC_EINVAL
     assert ctx.sync() == cc.CC_OK
 
 

@@ -411,6 +411,41 @@ def test_push_star():
     np.testing.assert_array_equal(P, want)
 
 
+def test_push_stride_sample():
+    """The Initial Push over a K-entry stride sample (K < m, m not a multiple of K):
+    only the entries at the sampled positions floor(j*m/K) push. Each sampled
+    position holds the zero root with its own partner vertex (as first endpoint at
+    even j, as second at odd j; j = 5 is a self-loop of z); every other position
+    holds z with a vertex of a separate range. A truncated stride (j*(m//K)), a
+    rounded-up one or a swapped endpoint test moves at least one push."""
+    m, K, z = 1003, 97, 3
+    base_s, base_u = 10, 200                           # partners: sampled / unsampled
+    n = base_u + m
+    sampled = {}
+    for j in range(K):
+        i = (j * m) // K
+        assert i not in sampled
+        sampled[i] = j
+    e = np.empty((m, 2), np.uint32)
+    for i in range(m):
+        if i in sampled:
+            j = sampled[i]
+            x = base_s + j
+            e[i] = (z, z) if j == 5 else ((z, x) if j % 2 == 0 else (x, z))
+        else:
+            e[i] = (base_u + i, z) if i % 2 else (z, base_u + i)
+    P = oracle.push(n, e, K, z)
+    want = np.arange(n, dtype=np.uint32)
+    for j in range(K):
+        if j != 5:
+            want[base_s + j] = z
+    np.testing.assert_array_equal(P, want)
+    # every position sampled when K >= m: the unsampled partners are pushed too
+    P_all = oracle.push(n, e, m, z)
+    assert all(P_all[base_u + i] == z for i in range(m) if i not in sampled)
+    assert P_all[base_s + 5] == base_s + 5             # the self-loop pushes nothing
+
+
 # ---- forest checker -------------------------------------------------------------
 
 def test_check_forest():
