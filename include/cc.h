@@ -365,6 +365,36 @@ int cc_pack_ids(cc_ctx* ctx, uint64_t count, const uint32_t* ids, uint32_t id_by
 int cc_unpack_ids(cc_ctx* ctx, uint64_t count, const uint8_t* in, uint32_t id_bytes, uint32_t* ids,
                   void* stream);
 
+/* ---- allocation-free whole path ------------------------------------------- */
+
+/* Bytes of the fixed scratch array behind cc_solve_noalloc (one per device). */
+#define CC_NOALLOC_SCRATCH_BYTES (16u << 20)
+
+/*
+ * For callers that cannot allocate device memory (code under stream capture,
+ * serving loops that must not allocate, harnesses that forbid it): the whole
+ * path of cc_solve_async (init, [zero root + Initial Push], hook, compress,
+ * relabelling), with no allocation at all. Its scratch (status word, zero-root
+ * state, a 16,384-entry sampled-degree table, per-block minima, the zero-root
+ * membership bitmap) is a fixed array of CC_NOALLOC_SCRATCH_BYTES in the
+ * library's device image; each device holds its own copy until the process
+ * ends, located at the first call on that device. Every call on a device
+ * shares that device's array, so calls that overlap on one device race: queue
+ * them on one stream. The hooks are the direct ones (the regrouped hooks'
+ * buffers grow with m).
+ *   n, m, edge_list, L, zroot_hint, stream   as for cc_solve_async
+ *   flags   CC_F_ZROOT, CC_F_ZROOT_HINT, CC_F_NO_SPLIT, CC_F_NO_TILE,
+ *           CC_F_SYMMETRIC (CC_F_ZROOT_EXACT or others: CC_EINVAL)
+ *   status  device, one int32, owned by the caller (may be NULL): written at
+ *           the end of the call's stream work with CC_OK or CC_ERANGE (an
+ *           endpoint >= n; labels unspecified)
+ * Limits: with CC_F_ZROOT, n <= 8 * (CC_NOALLOC_SCRATCH_BYTES - 557,312)
+ * (about 129 M vertices; more: CC_ENOMEM, nothing enqueued); plain: n < 2^32.
+ * Asynchronous on `stream`; argument errors are returned at once.
+ */
+int cc_solve_noalloc(uint64_t n, uint64_t m, const uint32_t* edge_list, uint32_t* L,
+                     uint32_t flags, uint32_t zroot_hint, int32_t* status, void* stream);
+
 /* ---- many graphs in one launch ------------------------------------------- */
 
 /*

@@ -30,6 +30,7 @@ CC_OK, CC_EINVAL, CC_ERANGE, CC_ENOMEM, CC_EDEVICE, CC_EAGAIN, CC_ECANCELED, CC_
 F_ZROOT, F_ZROOT_EXACT, F_ZROOT_HINT, F_NO_SPLIT, F_NO_TILE = 0x1, 0x2, 0x4, 0x8, 0x10
 F_CANON, F_SYMMETRIC = 0x20, 0x40
 STATUS_RING = 256
+NOALLOC_SCRATCH_BYTES = 16 << 20
 
 
 class CCError(RuntimeError):
@@ -79,6 +80,7 @@ SIGNATURES = {
     "cc_solve": (_I32, [_U64, _U64, _P, _P]),
     "cc_solve_async": (_I32, [_P, _U64, _U64, _P, _P, _U32, _U32, _P, ctypes.POINTER(Status)]),
     "cc_status_wait": (_I32, [ctypes.POINTER(Status), _I64]),
+    "cc_solve_noalloc": (_I32, [_U64, _U64, _P, _P, _U32, _U32, _P, _P]),
     "cc_sync": (_I32, [_P, _P]),
     "cc_solve_csr": (_I32, [_P, _U64, _P, _P, _P, _U32, _U32, _P, ctypes.POINTER(Status)]),
     "cc_solve_u64": (_I32, [_P, _U64, _U64, _P, _P, _U32, _P, ctypes.POINTER(Status)]),
@@ -157,6 +159,17 @@ def _stream(stream) -> int | None:
 
 def _st(status):
     return None if status is None else ctypes.byref(status)
+
+
+def solve_noalloc(edges: torch.Tensor, n: int, L: torch.Tensor, flags: int = 0,
+                  zroot_hint: int = 0, status: torch.Tensor | None = None, stream=None):
+    """cc_solve_noalloc: the whole path with the library's fixed scratch, no
+    allocation; `status` an int32 device tensor of one element (or None)."""
+    lib = load()
+    m = edges.shape[0] if edges.dim() == 2 else edges.numel() // 2
+    _check(lib.cc_solve_noalloc(n, m, _dptr(edges, _ID), _dptr(L, _ID), flags, zroot_hint,
+                                _dptr(status, (torch.int32,)), _stream(stream)),
+           "cc_solve_noalloc")
 
 
 def solve(edges: torch.Tensor, n: int, out: torch.Tensor | None = None) -> torch.Tensor:

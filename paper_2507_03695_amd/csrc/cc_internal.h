@@ -81,6 +81,10 @@ struct Slot {
     TiledScratch tiled;
     uint32_t* csr_tiles = nullptr; // device, first row of every CSR tile (grown on demand)
     uint64_t csr_tiles_cap = 0;
+    // Every buffer is fixed (the allocation-free entry point): nothing is grown,
+    // the regrouped hooks (buffers per entry) are not taken, and a request that
+    // would need more memory fails with CC_ENOMEM.
+    bool no_grow = false;
 };
 
 int slot_create(Slot* s, int device, uint32_t samples);

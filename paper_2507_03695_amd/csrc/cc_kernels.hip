@@ -824,6 +824,7 @@ static uint64_t sample_count(uint64_t m, uint64_t K) { return m <= K ? m : K; }
 int zbits_reset(Slot* s, uint64_t n, hipStream_t stream) {
     const uint64_t words = (n + 31) / 32;
     if (s->zbits_cap < words) {
+        if (s->no_grow) return fail(CC_ENOMEM, "zero-root bitmap exceeds the fixed scratch");
         CCM_HIP(hipStreamSynchronize(stream));
         if (s->zbits) CCM_HIP(hipFree(s->zbits));
         s->zbits = nullptr;
@@ -851,6 +852,8 @@ int run_zroot(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t f
         return zbits_reset(s, n, stream);
     }
     if (flags & CC_F_ZROOT_EXACT) {
+        if (s->deg_cap < n && s->no_grow)
+            return fail(CC_ENOMEM, "exact-degree counts need memory beyond the fixed scratch");
         if (s->deg_cap < n) {
             if (s->deg) CCM_HIP(hipFree(s->deg));
             s->deg = nullptr;
@@ -909,7 +912,7 @@ int run_hook(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P
     const uint32_t sym = (flags & CC_F_SYMMETRIC) ? 1u : 0u;
     if (zr && (!s->zr_ready || s->cur_n != n))
         return fail(CC_EINVAL, "a CC_F_ZROOT hook needs cc_init then cc_zroot on the same n");
-    if (split && !(flags & CC_F_NO_TILE) && tiled_eligible(n, m))
+    if (split && !(flags & CC_F_NO_TILE) && !s->no_grow && tiled_eligible(n, m))
         return run_hook_tiled(s, n, m, edges, P, stream, /*plain=*/!zr, sym != 0);
     const uint32_t n32 = (uint32_t)n;
     uint32_t* zb = s->zbits;
