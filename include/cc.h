@@ -443,14 +443,20 @@ typedef struct cc_serve_opts {
                                   0 = 65536                                          */
     uint64_t hbm_budget;       /* bytes of device memory the server may hold; 0 =
                                   the context's budget                              */
+    uint32_t coalesce_us;      /* coalescing window: small ready requests wait until
+                                  the oldest of them has been ready this long (or
+                                  half a staging buffer has gathered) so that later
+                                  arrivals join the same batched launch; 0 = none   */
+    uint32_t reserved;         /* 0 */
 } cc_serve_opts;
 
 typedef struct cc_req_stats {
     int32_t  status;          /* the request's outcome (CC_OK, CC_ERANGE, ...)       */
     uint32_t batched;         /* 1 if it ran inside a batched launch                 */
-    uint64_t t_submit_ns;     /* CLOCK_MONOTONIC timestamps                           */
-    uint64_t t_admit_ns;
-    uint64_t t_done_ns;
+    uint64_t t_submit_ns;     /* CLOCK_MONOTONIC timestamps: submitted,               */
+    uint64_t t_admit_ns;      /* admitted (memory or a batch place granted),          */
+    uint64_t t_start_ns;      /* its device work started (a worker took it),          */
+    uint64_t t_done_ns;       /* labels in host memory                                */
 } cc_req_stats;
 
 /* Start a server thread on ctx's device. */
@@ -460,9 +466,15 @@ int cc_serve_open(cc_ctx* ctx, const cc_serve_opts* opts, cc_server** out);
  * Submit one request (non-blocking). edges_host: 2*m uint32 in host memory,
  * L_host: n uint32 in host memory; both stay owned by the caller and must
  * remain valid until cc_serve_wait returns for this ticket. Admission waits
- * until the request's device footprint (8m + 4n bytes plus scratch) fits the
- * budget. Returns CC_EAGAIN when the queue is full, CC_ENOMEM when the
- * request alone exceeds the budget, CC_EINVAL for bad arguments.
+ * until the request's device footprint fits the budget: 8m + 4n bytes (edges,
+ * labels) plus the scratch its solve needs (the zero-root bitmap, the
+ * regrouped hook's buffers), all taken from the server's arena, so serving
+ * allocates nothing per request. Small requests (n <= small_n) go to batched
+ * launches through per-worker staging instead. flags: CC_F_ZROOT,
+ * CC_F_ZROOT_EXACT, CC_F_NO_SPLIT, CC_F_NO_TILE, CC_F_SYMMETRIC (applied on the
+ * single-graph path; batched requests take the plain path, same labels).
+ * Returns CC_EAGAIN when the queue is full, CC_ENOMEM when the request alone
+ * exceeds the budget, CC_EINVAL for bad arguments.
  */
 int cc_serve_submit(cc_server* srv, uint64_t n, uint64_t m, const uint32_t* edges_host,
                     uint32_t* L_host, uint32_t flags, uint64_t* ticket);

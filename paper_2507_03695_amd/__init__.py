@@ -50,7 +50,8 @@ class _CtxOpts(ctypes.Structure):
 class _ServeOpts(ctypes.Structure):
     _fields_ = [("max_inflight", ctypes.c_uint32), ("queue_capacity", ctypes.c_uint32),
                 ("streams", ctypes.c_uint32), ("small_n", ctypes.c_uint32),
-                ("hbm_budget", ctypes.c_uint64)]
+                ("hbm_budget", ctypes.c_uint64), ("coalesce_us", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class Status(ctypes.Structure):
@@ -63,7 +64,7 @@ class Status(ctypes.Structure):
 class ReqStats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("batched", ctypes.c_uint32),
                 ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
-                ("t_done_ns", ctypes.c_uint64)]
+                ("t_start_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64)]
 
 
 _lib = None
@@ -427,10 +428,10 @@ class Server:
     """cc_serve_*: continuous batching of CC requests held in host memory."""
 
     def __init__(self, ctx: Context, max_inflight=0, queue_capacity=0, streams=0, small_n=0,
-                 hbm_budget=0):
+                 hbm_budget=0, coalesce_us=0):
         self.ctx = ctx
         self.lib = ctx.lib
-        o = _ServeOpts(max_inflight, queue_capacity, streams, small_n, hbm_budget)
+        o = _ServeOpts(max_inflight, queue_capacity, streams, small_n, hbm_budget, coalesce_us, 0)
         h = ctypes.c_void_p()
         _check(self.lib.cc_serve_open(ctx.handle, ctypes.byref(o), ctypes.byref(h)), "cc_serve_open")
         self._h = h

@@ -308,6 +308,13 @@ static int batch_enqueue(int device, BatchScratch* bs, uint32_t G, hipStream_t s
     return cohere(stream);
 }
 
+int batch_reserve(Slot* s, uint32_t G) {
+    BatchScratch& bs = s->batch;
+    if (bs.cap >= G) return CC_OK;
+    batch_scratch_free(&bs);
+    return batch_alloc(&bs, G);
+}
+
 // The host staging is reused per call: the caller waits for the previous launch
 // on this slot (its upload) before the next one.
 int launch_batch(Slot* s, uint32_t G, const GraphDesc* descs, hipStream_t stream) {

@@ -81,10 +81,13 @@ struct Slot {
     TiledScratch tiled;
     uint32_t* csr_tiles = nullptr; // device, first row of every CSR tile (grown on demand)
     uint64_t csr_tiles_cap = 0;
-    // Every buffer is fixed (the allocation-free entry point): nothing is grown,
-    // the regrouped hooks (buffers per entry) are not taken, and a request that
-    // would need more memory fails with CC_ENOMEM.
+    // Nothing is grown: a solve that would need a larger buffer than the slot
+    // holds fails with CC_ENOMEM (a server's lent block, the allocation-free
+    // entry point).
     bool no_grow = false;
+    // The regrouped hooks (buffers per entry) are not taken (the allocation-free
+    // entry point, whose fixed scratch cannot hold them).
+    bool no_tiled = false;
 };
 
 int slot_create(Slot* s, int device, uint32_t samples);
@@ -135,6 +138,21 @@ int slot_sync(Slot* s, hipStream_t stream);
 
 // Tiled zero-root hook (cc_tiled.hip): both membership tests in LDS.
 bool tiled_eligible(uint64_t n, uint64_t m);
+// Bytes of the regrouped hook's buffers for n vertices and m COO entries.
+uint64_t tiled_scratch_bytes(uint64_t n, uint64_t m, bool plain);
+// Device bytes a whole-path solve (run_solve) grows in its slot for these
+// arguments: the bitmap, exact degrees, the regrouped hook's buffers.
+uint64_t solve_scratch_bytes(uint64_t n, uint64_t m, uint32_t flags);
+// Lend a block of device memory (at least solve_scratch_bytes(n, m, flags)) to
+// a slot for one run_solve: its grown buffers point into the block and nothing
+// is allocated; slot_return_scratch gives the slot its own buffers back.
+struct LentScratch {
+    uint32_t* zbits; uint64_t zbits_cap;
+    uint32_t* deg; uint64_t deg_cap;
+    TiledScratch tiled;
+};
+void slot_lend_scratch(Slot* s, char* block, uint64_t n, uint64_t m, uint32_t flags, LentScratch* saved);
+void slot_return_scratch(Slot* s, const LentScratch* saved);
 // plain = true: the plain path (key = ID) hooks the first-endpoint buckets in
 // order instead (better locality for the first endpoints' parent reads).
 // sym: the list holds every pair in both orders; only u < v is hooked.
@@ -148,6 +166,9 @@ int run_hook_tiled_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, con
 // Batched path (cc_batch.hip).
 // Enqueue one persistent launch over G graphs described on the host.
 int launch_batch(Slot* s, uint32_t G, const GraphDesc* descs, hipStream_t stream);
+// Size the slot's batch scratch for G graphs now (so later launches of at most
+// G graphs allocate nothing).
+int batch_reserve(Slot* s, uint32_t G);
 // cc_batch: offsets in device memory; synchronous.
 int run_batch(Slot* s, uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,
               const int32_t* edges, int32_t* L, int32_t* status, hipStream_t stream);

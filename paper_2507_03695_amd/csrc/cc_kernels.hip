@@ -912,7 +912,7 @@ int run_hook(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P
     const uint32_t sym = (flags & CC_F_SYMMETRIC) ? 1u : 0u;
     if (zr && (!s->zr_ready || s->cur_n != n))
         return fail(CC_EINVAL, "a CC_F_ZROOT hook needs cc_init then cc_zroot on the same n");
-    if (split && !(flags & CC_F_NO_TILE) && !s->no_grow && tiled_eligible(n, m))
+    if (split && !(flags & CC_F_NO_TILE) && !s->no_tiled && tiled_eligible(n, m))
         return run_hook_tiled(s, n, m, edges, P, stream, /*plain=*/!zr, sym != 0);
     const uint32_t n32 = (uint32_t)n;
     uint32_t* zb = s->zbits;
@@ -1105,6 +1105,60 @@ int run_solve_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, const ui
     if ((rc = cohere(stream))) return rc;
     if ((rc = run_compress(s, n, L, flags, stream, true))) return rc;
     return cohere(stream);
+}
+
+static uint64_t al256(uint64_t x) { return (x + 255) & ~255ull; }
+
+uint64_t solve_scratch_bytes(uint64_t n, uint64_t m, uint32_t flags) {
+    const bool zr = flags & CC_F_ZROOT;
+    uint64_t b = 0;
+    if (zr) b += al256(4 * ((n + 31) / 32));
+    if (zr && (flags & CC_F_ZROOT_EXACT)) b += al256(4 * n);
+    if (m && !(flags & (CC_F_NO_SPLIT | CC_F_NO_TILE)) && tiled_eligible(n, m))
+        b += al256(tiled_scratch_bytes(n, m, !zr));
+    return b;
+}
+
+void slot_lend_scratch(Slot* s, char* block, uint64_t n, uint64_t m, uint32_t flags,
+                       LentScratch* saved) {
+    saved->zbits = s->zbits;
+    saved->zbits_cap = s->zbits_cap;
+    saved->deg = s->deg;
+    saved->deg_cap = s->deg_cap;
+    saved->tiled = s->tiled;
+    const bool zr = flags & CC_F_ZROOT;
+    char* q = block;
+    s->zbits = nullptr;
+    s->zbits_cap = 0;
+    s->deg = nullptr;
+    s->deg_cap = 0;
+    s->tiled = TiledScratch{};
+    if (zr) {
+        const uint64_t words = (n + 31) / 32;
+        s->zbits = reinterpret_cast<uint32_t*>(q);
+        s->zbits_cap = words;
+        q += al256(4 * words);
+    }
+    if (zr && (flags & CC_F_ZROOT_EXACT)) {
+        s->deg = reinterpret_cast<uint32_t*>(q);
+        s->deg_cap = n;
+        q += al256(4 * n);
+    }
+    if (m && !(flags & (CC_F_NO_SPLIT | CC_F_NO_TILE)) && tiled_eligible(n, m)) {
+        s->tiled.buf = q;
+        s->tiled.cap = tiled_scratch_bytes(n, m, !zr);
+    }
+    s->no_grow = true;
+}
+
+void slot_return_scratch(Slot* s, const LentScratch* saved) {
+    s->zbits = saved->zbits;
+    s->zbits_cap = saved->zbits_cap;
+    s->deg = saved->deg;
+    s->deg_cap = saved->deg_cap;
+    s->tiled = saved->tiled;
+    s->no_grow = false;
+    s->zr_ready = false;
 }
 
 int run_solve(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* L,

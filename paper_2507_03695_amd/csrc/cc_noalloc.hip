@@ -110,6 +110,7 @@ extern "C" int cc_solve_noalloc(uint64_t n, uint64_t m, const uint32_t* edge_lis
     s.zbits = reinterpret_cast<uint32_t*>(base + kOffBits);
     s.zbits_cap = kBitsWords;
     s.no_grow = true;
+    s.no_tiled = true;
     k_na_reset<<<1, 64, 0, hs>>>(s.st);
     CCM_HIP(hipGetLastError());
     if ((rc = run_solve(&s, n, m, edge_list, L, flags, zroot_hint, hs))) return rc;

@@ -3,7 +3,10 @@
 // Requests arrive in host memory (cc_serve_submit) and wait in a FIFO queue.
 // Admission moves a request to the ready list once it fits: a large request
 // needs a block of the server's device arena (8m + 4n bytes, its edges and its
-// labels-as-parent-array), a small one needs only a place in a batch. Worker
+// labels-as-parent-array, plus the scratch its solve grows: the membership
+// bitmap, the regrouped hook's buffers), a small one needs only a place in a
+// batch. The scratch is lent to the worker's slot for that one solve, so no
+// worker allocates or frees device memory while serving. Worker
 // threads, one HIP stream each, take ready work as soon as they are free:
 // a run of small requests is packed into one staging buffer and solved by one
 // persistent batched launch; a large request runs the single-graph path on its
@@ -93,14 +96,15 @@ struct Req {
     const uint32_t* eh = nullptr;
     uint32_t* Lh = nullptr;
     uint32_t flags = 0;
-    uint64_t foot = 0;      // device bytes of the large path
+    uint64_t foot = 0;      // device bytes of the large path: edges, labels, scratch
+    uint64_t scratch = 0;   // of which the solve's own scratch (lent to the slot)
     bool small = false;
     uint64_t off = 0;       // arena offset (large path)
     int status = CC_OK;
     bool done = false;
     uint32_t batched = 0;
     int bypassed = 0;
-    uint64_t t_submit = 0, t_admit = 0, t_done = 0;
+    uint64_t t_submit = 0, t_admit = 0, t_start = 0, t_done = 0;
 };
 
 struct Worker {
@@ -164,12 +168,19 @@ int run_large(cc_server* s, Worker& w, Req* r) {
     char* base = s->arena_base + r->off;
     uint32_t* d_edges = reinterpret_cast<uint32_t*>(base);
     uint32_t* d_L = reinterpret_cast<uint32_t*>(base + align_up(8 * r->m));
+    char* d_scratch = base + align_up(8 * r->m) + align_up(4 * r->n);
     if (r->m)
         CCM_HIP(hipMemcpyAsync(d_edges, r->eh, 8 * r->m, hipMemcpyHostToDevice, w.stream));
+    LentScratch own;
+    slot_lend_scratch(&w.slot, d_scratch, r->n, r->m, r->flags, &own);
     int rc = run_solve(&w.slot, r->n, r->m, d_edges, d_L, r->flags, 0, w.stream);
-    if (rc) { (void)hipStreamSynchronize(w.stream); return rc; }
-    CCM_HIP(hipMemcpyAsync(r->Lh, d_L, 4 * r->n, hipMemcpyDeviceToHost, w.stream));
-    return slot_sync(&w.slot, w.stream);
+    if (!rc) {
+        const hipError_t e = hipMemcpyAsync(r->Lh, d_L, 4 * r->n, hipMemcpyDeviceToHost, w.stream);
+        rc = e == hipSuccess ? slot_sync(&w.slot, w.stream) : hip_fail(e, "label download");
+    }
+    (void)hipStreamSynchronize(w.stream);     // the lent block is idle before it is returned
+    slot_return_scratch(&w.slot, &own);
+    return rc;
 }
 
 // Pack small requests into the worker's staging and solve them in one launch.
@@ -227,7 +238,30 @@ void worker_main(cc_server* s, int wi) {
             continue;
         }
         std::vector<Req*> take;
-        if (s->ready.front()->small) {
+        // a ready large request, if any (the first in order)
+        auto large = std::find_if(s->ready.begin(), s->ready.end(), [](Req* r) { return !r->small; });
+        bool small_due = s->ready.front()->small;
+        if (small_due && s->opts.coalesce_us && !s->closing) {
+            // coalescing window: a batch of small requests waits until its oldest
+            // has been ready for coalesce_us (or half a staging buffer has
+            // gathered), so that requests arriving meanwhile join the same launch
+            uint64_t bytes = 0, oldest = UINT64_MAX;
+            for (Req* r : s->ready)
+                if (r->small) {
+                    bytes += align_up(8 * r->m) + align_up(4 * r->n) + 4;
+                    oldest = std::min(oldest, r->t_admit);
+                }
+            const uint64_t due = oldest + 1000ull * s->opts.coalesce_us;
+            const uint64_t now = now_ns();
+            if (now < due && bytes < s->stage_cap / 2) {
+                if (large == s->ready.end()) {
+                    s->cv_work.wait_for(lk, std::chrono::nanoseconds(due - now));
+                    continue;
+                }
+                small_due = false;       // meanwhile, a large request goes first
+            }
+        }
+        if (small_due) {
             // the ready small requests, in order, up to the staging capacity
             uint64_t bytes = 0;
             for (auto it = s->ready.begin(); it != s->ready.end();) {
@@ -240,9 +274,12 @@ void worker_main(cc_server* s, int wi) {
                 it = s->ready.erase(it);
             }
         } else {
-            take.push_back(s->ready.front());
-            s->ready.pop_front();
+            if (large == s->ready.end()) large = s->ready.begin();
+            take.push_back(*large);
+            s->ready.erase(large);
         }
+        const uint64_t t_start = now_ns();
+        for (Req* r : take) r->t_start = t_start;
         lk.unlock();
         if (take.size() == 1 && !take[0]->small) {
             int rc = run_large(s, w, take[0]);
@@ -316,6 +353,7 @@ extern "C" int cc_serve_open(cc_ctx* ctx, const cc_serve_opts* opts, cc_server**
             return fail(CC_ENOMEM, "server worker allocation failed");
         }
         rc = slot_create(&w.slot, dev, samples);
+        if (!rc) rc = batch_reserve(&w.slot, std::max<uint32_t>(s->opts.max_inflight, 1024));
         if (rc) { server_free(s); return rc; }
     }
     for (uint64_t i = 0; i < W; ++i) s->workers[i].th = std::thread(worker_main, s, (int)i);
@@ -330,10 +368,13 @@ extern "C" int cc_serve_submit(cc_server* s, uint64_t n, uint64_t m, const uint3
     if (m && !edges_host) return fail(CC_EINVAL, "edges_host is NULL with m > 0");
     if (n && !L_host) return fail(CC_EINVAL, "L_host is NULL with n > 0");
     if (n == 0 && m) return fail(CC_ERANGE, "entries given for an empty vertex set");
-    if (flags & CC_F_ZROOT_HINT) return fail(CC_EINVAL, "CC_F_ZROOT_HINT is not accepted here");
+    if (flags & ~(uint32_t)(CC_F_ZROOT | CC_F_ZROOT_EXACT | CC_F_NO_SPLIT | CC_F_NO_TILE |
+                            CC_F_SYMMETRIC))
+        return fail(CC_EINVAL, "flag not accepted by the server (CC_F_ZROOT_HINT, unknown)");
     Req* r = new Req();
     r->n = n; r->m = m; r->eh = edges_host; r->Lh = L_host; r->flags = flags;
-    r->foot = align_up(8 * m) + align_up(4 * n);
+    r->scratch = solve_scratch_bytes(n, m, flags);
+    r->foot = align_up(8 * m) + align_up(4 * n) + r->scratch;
     const uint64_t stage_need = align_up(8 * m) + align_up(4 * n) + 512;
     r->small = n <= s->opts.small_n && n < (1ull << 31) && stage_need <= s->stage_cap;
     if (!r->small && r->foot > s->arena.size) {
@@ -376,6 +417,7 @@ extern "C" int cc_serve_wait(cc_server* s, uint64_t ticket, int64_t timeout_us, 
         stats->batched = r->batched;
         stats->t_submit_ns = r->t_submit;
         stats->t_admit_ns = r->t_admit;
+        stats->t_start_ns = r->t_start ? r->t_start : r->t_admit;
         stats->t_done_ns = r->t_done;
     }
     const int st = r->status;

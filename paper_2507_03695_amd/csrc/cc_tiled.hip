@@ -1101,8 +1101,9 @@ bool tiled_eligible(uint64_t n, uint64_t m) {
     return R >= 2 && R <= (uint64_t)kMaxSlices && m >= (1ull << 24) && m < (1ull << 32);
 }
 
-static int grow(void** p, uint64_t* cap, uint64_t bytes, hipStream_t stream) {
+static int grow(Slot* s, void** p, uint64_t* cap, uint64_t bytes, hipStream_t stream) {
     if (*cap >= bytes) return CC_OK;
+    if (s->no_grow) return fail(CC_ENOMEM, "regrouped-hook scratch exceeds the fixed scratch");
     CCM_HIP(hipStreamSynchronize(stream));
     if (*p) CCM_HIP(hipFree(*p));
     *p = nullptr;
@@ -1114,6 +1115,24 @@ static int grow(void** p, uint64_t* cap, uint64_t bytes, hipStream_t stream) {
     }
     *cap = bytes;
     return CC_OK;
+}
+
+// Bytes of the regrouped hook's buffers for a COO list of m entries (with the
+// zero root's warm-up taken off the front, as run_hook_tiled does); the same
+// arithmetic as the layout below.
+uint64_t tiled_scratch_bytes(uint64_t n, uint64_t m, bool plain) {
+    const uint64_t m0 = plain ? 0 : m >> 10;
+    const TiledPlan pl = tiled_plan(n, m - m0);
+    const uint64_t R = (uint64_t)pl.R;
+    auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
+    const uint64_t cap = pl.nch1 * kC1;
+    const uint64_t ntile = (pl.nch1 + kScanTile - 1) / kScanTile;
+    const uint64_t nbg = (R + kBPerBlock - 1) / kBPerBlock;
+    const uint64_t nwg = R * nbg;
+    return al(4 * cap) + al(2 * cap) + al(8 * cap) + al(2 * pl.nch1 * R) + al(4 * pl.nch1 * R) +
+           al(4 * (pl.nch1 + 1) * R) + al(8 * (R + 1)) + al(4 * (R + 1)) +
+           al(2 * pl.nch2_max * (R + 1)) + al(32 * pl.nch2_max) + al(4 * ntile * R) +
+           al(8 * (nwg + 1)) + al(4 * nwg) + al(4 * (nwg + 1));
 }
 
 void tiled_free(TiledScratch* t) {
@@ -1156,7 +1175,9 @@ int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint3
     const uint64_t b_ipref = al(4 * ((uint64_t)nwg + 1));
     const uint64_t total = b_t1w + b_t1h + b_tmp2 + b_seg1 + b_cnt1 + b_pre1 + b_base2 +
                            b_cbase + b_run2 + b_desc + b_tsum + b_wgoff + b_wgcnt + b_ipref;
-    int rc = grow(reinterpret_cast<void**>(&s->tiled.buf), &s->tiled.cap, total, stream);
+    if (total != tiled_scratch_bytes(n, m0 + m, plain))
+        return fail(CC_EDEVICE, "regrouped-hook scratch size mismatch (a bug)");
+    int rc = grow(s, reinterpret_cast<void**>(&s->tiled.buf), &s->tiled.cap, total, stream);
     if (rc) return rc;
     char* q = s->tiled.buf;
     uint32_t* t1w = reinterpret_cast<uint32_t*>(q); q += b_t1w;
@@ -1232,7 +1253,7 @@ int run_hook_tiled_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, con
     const uint64_t b_ipref = al(4 * ((uint64_t)nwg + 1));
     const uint64_t total = b_sw + b_sh + b_tmp2 + b_base2 + b_cbase + b_cfirst + b_run2 + b_wgoff +
                            b_wgcnt + b_ipref;
-    int rc = grow(reinterpret_cast<void**>(&s->tiled.buf), &s->tiled.cap, total, stream);
+    int rc = grow(s, reinterpret_cast<void**>(&s->tiled.buf), &s->tiled.cap, total, stream);
     if (rc) return rc;
     char* q = s->tiled.buf;
     uint32_t* sw = reinterpret_cast<uint32_t*>(q); q += b_sw;

@@ -1,6 +1,8 @@
 """Helpers shared by the GPU tests: moving seeded inputs to the device and
 checking labels against the oracle and against properties that hold at any size."""
 import functools
+import hashlib
+import os
 import sys
 
 import numpy as np
@@ -42,6 +44,29 @@ def check_properties_on_device(edges_dev: torch.Tensor, L_dev: torch.Tensor, n: 
     ar = torch.arange(n, device=L.device, dtype=torch.int64)
     assert bool((L <= ar).all()), "a label exceeds its vertex"
     assert torch.equal(L[L], L), "a label is not a fixed point"
+
+
+def golden_share30():
+    """tests/golden/share30_oracle.txt (written by make_share30_digest.py from the
+    generators and the oracle only): entry count, digests, components, probes."""
+    out = {"label": {}}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "share30_oracle.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            k, *v = line.split()
+            if k == "label":
+                out["label"][int(v[0])] = int(v[1])
+            else:
+                out[k] = v[0]
+    return out
+
+
+def sha256_of(a) -> str:
+    """SHA-256 of an array's bytes (a device tensor is copied to the host first)."""
+    if isinstance(a, torch.Tensor):
+        a = a.cpu().numpy()
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
 
 
 @functools.lru_cache(maxsize=1)

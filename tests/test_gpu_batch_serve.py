@@ -9,7 +9,8 @@ import torch
 
 import graphgen
 import oracle
-from gpu_helpers import assert_same_labels, log, to_dev, to_host_u32
+from gpu_helpers import (assert_same_labels, golden_share30, log, sha256_of, to_dev,
+                         to_host_u32)
 
 pytestmark = pytest.mark.gpu
 
@@ -151,7 +152,7 @@ def test_batch_4096_full(ctx):
         assert_same_labels(Lh[b.vtx_off[g]:b.vtx_off[g + 1]], alone, f"graph {g} alone")
 
 
-def _requests(count, seed, hi=2.0**17):
+def _requests(count, seed, hi=2.0**24):
     reqs = graphgen.serve_stream(count, seed, rate_per_s=1e9, hi=hi)
     out = []
     for r in reqs:
@@ -160,17 +161,26 @@ def _requests(count, seed, hi=2.0**17):
     return out
 
 
-def test_serve_mix_equals_alone(ctx):
-    reqs = _requests(120, 5)
-    # two large ones that take the single-graph path
-    reqs.append((graphgen.rmat(18, 1 << 21, 1), 1 << 18))
-    reqs.append((graphgen.er(200_000, 400_000, 2), 200_000))
-    srv = cc.Server(ctx, streams=4, small_n=65536)
+def test_serve_full_pareto_range(ctx):
+    """Served labels equal the oracle's and the graph solved alone, across the
+    serving workload's whole size range: 160 requests drawn from it (n Pareto(1.5)
+    on [2^10, 2^24], edgefactor 8..32, ER / R-MAT), plus its top end, which so few
+    draws rarely reach: n = 2^24 (R-MAT, 2^27 entries), 2^22 (ER, 2^27 entries,
+    zero root) and 2^20 (R-MAT, zero root), submitted mid-stream. Small requests
+    go to batched launches, large ones to the single-graph path with scratch
+    from the arena; every third request asks for the zero root."""
+    reqs = [(e, n, cc.F_ZROOT if i % 3 == 0 else 0) for i, (e, n) in enumerate(_requests(160, 5))]
+    top = [(graphgen.rmat(24, 8 << 24, 51), 1 << 24, 0),
+           (graphgen.er(1 << 22, 32 << 22, 52), 1 << 22, cc.F_ZROOT),
+           (graphgen.rmat(20, 16 << 20, 53), 1 << 20, cc.F_ZROOT)]
+    reqs = reqs[:80] + top + reqs[80:]
+    log(f"serving {len(reqs)} requests, largest n={max(n for _, n, _ in reqs)}")
+    srv = cc.Server(ctx, streams=4, small_n=65536, coalesce_us=50)
     outs, tickets = [], []
-    for e, n in reqs:
+    for e, n, fl in reqs:
         L = np.zeros(n, np.uint32)
         outs.append(L)
-        tickets.append(srv.submit(e, n, L))
+        tickets.append(srv.submit(e, n, L, flags=fl))
     stats = []
     for t in tickets:
         rc, st = srv.wait(t)
@@ -178,10 +188,46 @@ def test_serve_mix_equals_alone(ctx):
         stats.append(st)
     srv.close()
     assert any(s.batched for s in stats) and any(not s.batched for s in stats)
-    for (e, n), L in zip(reqs, outs):
-        assert_same_labels(L, oracle.cc_labels(n, e), f"served n={n}")
-        alone = to_host_u32(ctx.solve(to_dev(e), n))
-        assert_same_labels(L, alone, f"served vs alone n={n}")
+    for s in stats:
+        assert s.t_submit_ns <= s.t_admit_ns <= s.t_start_ns <= s.t_done_ns
+    for i, ((e, n, fl), L) in enumerate(zip(reqs, outs)):
+        assert_same_labels(L, oracle.cc_labels(n, e), f"served n={n} flags={fl}")
+        if i % 10 == 0 or n >= 1 << 20:
+            alone = to_host_u32(ctx.solve(to_dev(e), n, flags=fl))
+            assert_same_labels(L, alone, f"served vs alone n={n}")
+    log("served labels equal the oracle's")
+
+
+def test_serve_share_mid_stream(ctx):
+    """The serving workload's share-shaped request (one machine's 1/16 vertex-range
+    share of R-MAT-30 ef16 with the global 2^30-entry parent array) submitted in
+    the middle of a stream of small requests: its labels equal the oracle's (the
+    recorded SHA-256 of all 2^30 labels), and so do the small requests' labels."""
+    g = golden_share30()
+    ed, n = graphgen.rmat30_share_dev()
+    e_share = ed.cpu().numpy().view(np.uint32)
+    del ed
+    torch.cuda.empty_cache()
+    assert sha256_of(e_share) == g["entries_sha256"]
+    small = _requests(100, 77, hi=2.0**16)
+    srv = cc.Server(ctx, streams=4, small_n=65536, hbm_budget=24 << 30)
+    L_share = np.zeros(n, np.uint32)
+    outs, tickets = [], []
+    for i, (e, nn) in enumerate(small):
+        if i == 50:
+            t_share = srv.submit(e_share, n, L_share, flags=cc.F_ZROOT)
+        L = np.zeros(nn, np.uint32)
+        outs.append(L)
+        tickets.append(srv.submit(e, nn, L))
+    rc, st = srv.wait(t_share)
+    assert rc == cc.CC_OK and not st.batched
+    for t in tickets:
+        assert srv.wait(t)[0] == cc.CC_OK
+    srv.close()
+    log(f"share served in {(st.t_done_ns - st.t_submit_ns) / 1e6:.1f} ms")
+    assert sha256_of(L_share) == g["labels_sha256"], "served share labels differ from the oracle's"
+    for (e, nn), L in zip(small, outs):
+        assert_same_labels(L, oracle.cc_labels(nn, e), f"served n={nn}")
 
 
 def test_serve_budget_errors_and_cancel(ctx):

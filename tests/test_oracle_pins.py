@@ -468,3 +468,35 @@ def test_batch_matches_single():
         e, n = b.graph(g)
         np.testing.assert_array_equal(L[b.vtx_off[g]:b.vtx_off[g + 1]].astype(np.uint32),
                                       closure_labels(n, e.tolist()) if n <= 64 else bfs_labels(n, e))
+
+
+# ---- stored oracle results ----------------------------------------------------------
+
+def test_share30_golden_file():
+    """tests/golden/share30_oracle.txt holds the oracle's labels of the R-MAT-30
+    share as digests; its script uses only the generators and the oracle, and the
+    recorded facts are consistent (hex digests, components within n, each probe's
+    label at most the vertex and a fixed point of the labelling where known)."""
+    import re
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    src = open(os.path.join(here, "make_share30_digest.py")).read()
+    imports = set(re.findall(r"^\s*(?:import|from)\s+(\w+)", src, flags=re.M))
+    assert imports <= {"hashlib", "os", "sys", "time", "numpy", "graphgen", "oracle"}, imports
+    g = {"label": {}}
+    for line in open(os.path.join(here, "share30_oracle.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, *v = line.split()
+        if k == "label":
+            g["label"][int(v[0])] = int(v[1])
+        else:
+            g[k] = v[0]
+    n, m = int(g["n"]), int(g["m"])
+    assert n == 1 << 30 and 0.9 * (1 << 30) < m < 1.1 * (1 << 30)
+    assert re.fullmatch(r"[0-9a-f]{64}", g["entries_sha256"])
+    assert re.fullmatch(r"[0-9a-f]{64}", g["labels_sha256"])
+    assert 0 < int(g["components"]) <= n
+    for v, lab in g["label"].items():
+        assert 0 <= lab <= v < n
+        if lab in g["label"]:
+            assert g["label"][lab] == lab
