@@ -47,12 +47,19 @@ constexpr uint32_t kLoMask = (1u << kSliceBits) - 1;
 // passes hold fewer than 8 bytes per entry:
 //  level 1 (bucket a known): w = u_lo | v << 19, h = v >> 13 (4 + 2 bytes)
 // (u_lo: the low 19 bits of u; the top 13 bits of w carry the low 13 bits of v).
-// The survivor regions reuse this format. The level-2 buffer keeps (u, v) as
-// two words: the filter that reads it is bound by latency, not by bytes.
+// The survivor regions reuse this format.
+//  level 2 (both slices known from the run): w = u_lo | v_lo << 19,
+//  h = v_lo >> 13 (4 + 1 bytes), two arrays.
 __device__ __forceinline__ uint32_t pk_w(uint32_t ulo, uint32_t v) { return ulo | (v << kSliceBits); }
 __device__ __forceinline__ uint32_t pk_v1(uint32_t w, uint16_t h) {
     return (w >> kSliceBits) | ((uint32_t)h << (32 - kSliceBits));
 }
+
+// The level-2 buffer: the two arrays of the 5-byte relative form.
+struct L2Buf {
+    uint32_t* w;
+    uint8_t* h;
+};
 
 constexpr int kMaxSlices = 256;
 constexpr int kC1 = 8192;                            // level-1 chunk (entries)
@@ -329,12 +336,12 @@ constexpr int kWin2 = 256;   // level-1 chunks per gather window (owner index fi
 
 // The chunk's cnt entries (entry i in e[i / kPartBlock] of thread i % kPartBlock,
 // hist zeroed beforehand) sorted by the second endpoint's slice through LDS and
-// written contiguously to out, with the start of every slice's run in run2T.
+// written contiguously to out in the level-2 form, with the start of every
+// slice's run in run2T.
 __device__ __forceinline__ void t2_sort_write(const u32x2 (&e)[kPartEPT], uint32_t cnt, int R,
                                               uint32_t* hist, uint32_t* start, u32x2* stage,
-                                              u32x2* __restrict__ out,
-                                              uint16_t* __restrict__ run2T, uint64_t nch2,
-                                              uint32_t g) {
+                                              L2Buf out, uint16_t* __restrict__ run2T,
+                                              uint64_t nch2, uint32_t g) {
     uint16_t rank[kPartEPT];
 #pragma unroll
     for (int k = 0; k < kPartEPT; ++k) {
@@ -349,7 +356,12 @@ __device__ __forceinline__ void t2_sort_write(const u32x2 (&e)[kPartEPT], uint32
     for (int k = 0; k < kPartEPT; ++k)
         if (rank[k] != 0xFFFF) stage[start[e[k].y >> kSliceBits] + rank[k]] = e[k];
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < cnt; i += kPartBlock) out[i] = stage[i];
+    for (uint32_t i = threadIdx.x; i < cnt; i += kPartBlock) {
+        const u32x2 x = stage[i];
+        const uint32_t vlo = x.y & kLoMask;
+        out.w[i] = (x.x & kLoMask) | (vlo << kSliceBits);
+        out.h[i] = (uint8_t)(vlo >> (32 - kSliceBits));
+    }
     for (int d = threadIdx.x; d <= R; d += kPartBlock) run2T[(uint64_t)d * nch2 + g] = (uint16_t)start[d];
 }
 
@@ -419,8 +431,7 @@ __global__ __launch_bounds__(kPartBlock) void k_t2_part(const uint32_t* __restri
                                                         uint64_t nch1, int R,
                                                         const uint32_t* __restrict__ cbase,
                                                         const uint32_t* __restrict__ desc,
-                                                        u32x2* __restrict__ tmp2,
-                                                        uint16_t* __restrict__ run2T,
+                                                        L2Buf tmp2, uint16_t* __restrict__ run2T,
                                                         uint64_t nch2) {
     __shared__ u32x2 stage[kC2];
     __shared__ uint8_t owner[kC2];
@@ -436,7 +447,8 @@ __global__ __launch_bounds__(kPartBlock) void k_t2_part(const uint32_t* __restri
     uint64_t obase;
     const uint32_t cnt = t2_gather(g, t1w, t1h, segT, pre1, nch1, desc, owner, s_pre, s_seg, e, a,
                                    obase);
-    t2_sort_write(e, cnt, R, hist, start, stage, tmp2 + obase, run2T, nch2, g);
+    t2_sort_write(e, cnt, R, hist, start, stage, L2Buf{tmp2.w + obase, tmp2.h + obase}, run2T,
+                  nch2, g);
 }
 
 // Plain path (key = ID) on the level-1 buckets: each workgroup gathers one
@@ -564,7 +576,7 @@ __global__ __launch_bounds__(kPartBlock) void k_t2_csr(const uint64_t* __restric
                                                        const uint64_t* __restrict__ base2,
                                                        const uint32_t* __restrict__ cbase,
                                                        const uint32_t* __restrict__ cfirst,
-                                                       u32x2* __restrict__ tmp2,
+                                                       L2Buf tmp2,
                                                        uint16_t* __restrict__ run2T,
                                                        uint64_t nch2, DevState* st, uint32_t sym) {
     __shared__ u32x2 stage[kC2];
@@ -678,7 +690,8 @@ __global__ __launch_bounds__(kPartBlock) void k_t2_csr(const uint64_t* __restric
         e[k].y = vv;
     }
     if (bad) atomicOr(&st->status, kStatusRange);
-    t2_sort_write(e, cnt, R, hist, start, stage, tmp2 + pos0, run2T, nch2, g);
+    t2_sort_write(e, cnt, R, hist, start, stage, L2Buf{tmp2.w + pos0, tmp2.h + pos0}, run2T, nch2,
+                  g);
 }
 
 // ---- 5. the filter over bucket (a, b) with both slices' bitmap words in LDS ---------------
@@ -695,8 +708,8 @@ __global__ __launch_bounds__(kPartBlock) void k_t2_csr(const uint64_t* __restric
 constexpr int kHook3Block = 1024;
 constexpr int kWaves3 = kHook3Block / 64;
 constexpr int kWin3 = 2000;      // level-2 chunks per window
-constexpr int kRunsInFlight = 16; // entries a lane loads at once (a wave: 16 x 64 consecutive)
-constexpr int kWaveQueue = 128;  // per-wave LDS staging of kept entries
+constexpr int kRunsInFlight = 12; // entries a lane loads at once (a wave: 12 x 64 consecutive)
+constexpr int kPendQueue = 127;  // per-wave LDS staging of entries that need a second look
 
 // Exclusive scan in place of n <= 2 * kHook3Block values (x[n] receives the
 // total); every thread of the workgroup calls it.
@@ -724,39 +737,6 @@ __device__ __forceinline__ void block_scan_2048(uint32_t* x, uint32_t n, uint32_
     if (i1 < n) x[i1] = excl + a0;
     if (tid == 0) x[n] = wsum[kHook3Block / 64];
     __syncthreads();
-}
-
-// Append the first `qn` staged entries of this wave (qn < 128) to the
-// workgroup's survivor region: the place comes from an LDS counter, so no
-// global atomic is involved; one entry per lane per round. Every entry of the
-// workgroup has its first endpoint in slice a, so the level-1 packing applies.
-__device__ __forceinline__ void t3_flush(const u32x2* wq, uint32_t qn, int lane, uint32_t* ow,
-                                         uint16_t* oh, uint32_t cap, uint32_t* s_used,
-                                         DevState* st) {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(s_used, qn);
-    base = __shfl(base, 0, 64);
-    if (base + qn > cap) {
-        // cannot happen (the region holds all of the workgroup's entries); never
-        // write past it
-        if (lane == 0) atomicOr(&st->status, kStatusInternal);
-        qn = 0;
-    }
-    // wq holds (u_lo, v); the region stores the level-1 packed form
-    if ((uint32_t)lane < qn) {
-        const u32x2 x = wq[lane];
-        ow[base + lane] = pk_w(x.x, x.y);
-        oh[base + lane] = (uint16_t)(x.y >> (32 - kSliceBits));
-    }
-    if ((uint32_t)lane + 64 < qn) {
-        const u32x2 x = wq[lane + 64];
-        ow[base + lane + 64] = pk_w(x.x, x.y);
-        oh[base + lane + 64] = (uint16_t)(x.y >> (32 - kSliceBits));
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
 }
 
 constexpr int kBPerBlock = 2;    // second-endpoint slices handled by one workgroup
@@ -816,7 +796,67 @@ __device__ __forceinline__ uint32_t t3_find_run(const uint32_t* s_pre, uint32_t 
     return base + (63u - (uint32_t)__clzll((long long)b2));
 }
 
-__global__ __launch_bounds__(kHook3Block) void k_t3_filter(const u32x2* __restrict__ tmp2,
+// Offset of index j of the window (j in [jb, jb + 64), the indices one wave
+// handles together): t is the run holding index jb, kept wave-uniform and
+// advanced here to the run holding jb + 63. Runs are about as long as a wave,
+// so this is usually one step; lanes past a run's end take the next run's
+// offset. Every branch depends on wave-uniform values only.
+__device__ __forceinline__ uint32_t t3_offset(const uint32_t* s_pre, const uint32_t* s_off,
+                                              uint32_t nw, uint32_t& t, uint32_t jb, uint32_t j) {
+    // the table reads have one address for the whole wave: keep them scalar
+    uint32_t off = __builtin_amdgcn_readfirstlane(s_off[t]);
+    uint32_t nxt = __builtin_amdgcn_readfirstlane(s_pre[t + 1]);
+    while (t + 1 < nw && nxt < jb + 64) {
+        ++t;
+        const uint32_t o = __builtin_amdgcn_readfirstlane(s_off[t]);
+        off = j >= nxt ? o : off;
+        nxt = __builtin_amdgcn_readfirstlane(s_pre[t + 1]);
+    }
+    return off;
+}
+
+// Second look at up to 64 pending entries of this wave (lane l takes pq[l],
+// endpoints relative to the slices' first IDs), with the bits as they are now:
+// both marked, dropped; one marked, the other is marked (LDS, and the global
+// word when this set the bit); neither, kept: written to the workgroup's
+// survivor region (level-1 packing, its place from an LDS counter).
+__device__ __forceinline__ void t3_settle(const u32x2* pq, uint32_t cnt, int lane, uint32_t* sa,
+                                          uint32_t* lb, uint32_t abase, uint32_t bbase,
+                                          uint32_t* zbits, uint32_t* ow, uint16_t* oh,
+                                          uint32_t cap, uint32_t* s_used, DevState* st) {
+    const bool act = (uint32_t)lane < cnt;
+    const u32x2 x = act ? pq[lane] : u32x2{0u, 0u};
+    const uint32_t iu = x.x >> 5, iv = x.y >> 5;
+    const uint32_t bu = 1u << (x.x & 31), bv = 1u << (x.y & 31);
+    const bool mu = (sa[iu] & bu) != 0u, mv = (lb[iv] & bv) != 0u;
+    if (act && mu != mv) {
+        // the entry's whole effect: mark the unmarked endpoint
+        uint32_t* w = mu ? &lb[iv] : &sa[iu];
+        const uint32_t bit = mu ? bv : bu;
+        const uint32_t y = mu ? bbase + x.y : abase + x.x;
+        if (!(atomicOr(w, bit) & bit)) atomicOr(&zbits[y >> 5], 1u << (y & 31));
+    }
+    const bool keep = act && !mu && !mv;
+    const uint64_t ball = __ballot(keep);
+    if (ball) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(s_used, (uint32_t)__popcll(ball));
+        base = __shfl(base, 0, 64);
+        if (keep) {
+            const uint32_t i = base + (uint32_t)__popcll(ball & ((1ull << lane) - 1ull));
+            if (i < cap) {
+                const uint32_t v = bbase + x.y;
+                ow[i] = pk_w(x.x, v);
+                oh[i] = (uint16_t)(v >> (32 - kSliceBits));
+            } else {
+                // cannot happen (the region holds all of the workgroup's entries)
+                atomicOr(&st->status, kStatusInternal);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kHook3Block) void k_t3_filter(L2Buf tmp2,
                                                            const uint16_t* __restrict__ run2T,
                                                            uint64_t nch2, int R,
                                                            const uint64_t* __restrict__ base2,
@@ -831,7 +871,7 @@ __global__ __launch_bounds__(kHook3Block) void k_t3_filter(const u32x2* __restri
     __shared__ uint32_t sb[kSliceWords];
     __shared__ uint32_t s_off[kWin3];
     __shared__ uint32_t s_pre[kWin3 + 1];
-    __shared__ u32x2 queue[kWaves3 * kWaveQueue];
+    __shared__ u32x2 pqueue[kWaves3 * kPendQueue];
     __shared__ uint32_t wsum[kWaves3 + 1];
     __shared__ uint32_t s_used;
     // Launch order: consecutive workgroups take different a (and spread over
@@ -865,11 +905,12 @@ __global__ __launch_bounds__(kHook3Block) void k_t3_filter(const u32x2* __restri
         for (int k = 0; k < PER; ++k) sa[(uint32_t)k * kHook3Block + threadIdx.x] = xa[k];
     }
     const uint32_t abase = (uint32_t)a << kSliceBits;
-    const u32x2* src = tmp2 + base2[a];
+    const uint32_t* srcw = tmp2.w + base2[a];
+    const uint8_t* srch = tmp2.h + base2[a];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    u32x2* wq = queue + wave * kWaveQueue;
+    u32x2* pq = pqueue + wave * kPendQueue;
     constexpr uint32_t kRange = 64 * kRunsInFlight;      // entries per wave per range
-    uint32_t qn = 0;             // wave-uniform staging length, carried across slices b
+    constexpr uint32_t kStep = kWaves3 * kRange;
     for (int bi = 0; bi < kBPerBlock; ++bi) {
         const int b = bg * kBPerBlock + bi;
         if (b >= R) break;
@@ -887,6 +928,7 @@ __global__ __launch_bounds__(kHook3Block) void k_t3_filter(const u32x2* __restri
         }
         uint32_t* lb = (a == b) ? sa : sb;
         const uint32_t bbase = (uint32_t)b << kSliceBits;
+        uint32_t pn = 0;                                  // wave-uniform pending count
         for (uint32_t w0 = 0; w0 < nch; w0 += kWin3) {
             const uint32_t nw = min((uint32_t)kWin3, nch - w0);
             __syncthreads();
@@ -906,79 +948,69 @@ __global__ __launch_bounds__(kHook3Block) void k_t3_filter(const u32x2* __restri
             __syncthreads();
             const uint32_t total = s_pre[nw];
             // The window's entries form one index space [0, total); each wave
-            // takes ranges of kRange consecutive indices (lanes step through the
-            // runs).
+            // takes ranges of kRange consecutive indices. Register k holds index
+            // j0 + 64k + lane; right after it is tested it is reloaded with index
+            // jn + 64k + lane of the next range (index 0 past the end), so the
+            // next range's loads are in flight meanwhile.
             uint32_t j0 = (uint32_t)wave * kRange;
             if (j0 >= total) continue;
-            constexpr uint32_t kStep = kWaves3 * kRange;
-            // Address of index j of the window (t: the run holding an earlier
-            // index of this lane, advanced in place).
-            auto addr = [&](uint32_t j, uint32_t& t) -> uint64_t {
-                while (t + 1 < nw && s_pre[t + 1] <= j) ++t;
-                return (uint64_t)(j + s_off[t]);
-            };
-            // Software pipeline: e[k] holds entry k of the current range; right
-            // after it is tested its register is reloaded with entry k of the
-            // next range, so a range's loads are in flight while the previous
-            // range is tested, and no loaded value is ever copied.
-            u32x2 e[kRunsInFlight];
-            bool h[kRunsInFlight];
-            {
-                uint32_t t = t3_find_run(s_pre, nw, j0, lane);
+            uint32_t ew[kRunsInFlight], eh[kRunsInFlight];
+            uint32_t t = __builtin_amdgcn_readfirstlane(t3_find_run(s_pre, nw, j0, lane));
 #pragma unroll
-                for (int k = 0; k < kRunsInFlight; ++k) {
-                    const uint32_t j = j0 + (uint32_t)k * 64 + lane;
-                    h[k] = j < total;
-                    const uint64_t at = h[k] ? addr(j, t) : 0ull;
-                    e[k] = __builtin_nontemporal_load(src + at);
-                }
+            for (int k = 0; k < kRunsInFlight; ++k) {
+                const uint32_t jb = j0 + (uint32_t)k * 64, j = jb + (uint32_t)lane;
+                const uint32_t off = t3_offset(s_pre, s_off, nw, t, jb, j);
+                const uint32_t at = j < total ? j + off : 0u;
+                ew[k] = __builtin_nontemporal_load(srcw + at);
+                eh[k] = __builtin_nontemporal_load(srch + at);
             }
             while (true) {
                 const uint32_t jn = j0 + kStep;
                 const bool more = jn < total;
-                uint32_t tn = more ? t3_find_run(s_pre, nw, jn, lane) : 0u;
+                uint32_t tn = more ? __builtin_amdgcn_readfirstlane(t3_find_run(s_pre, nw, jn, lane)) : 0u;
 #pragma unroll
                 for (int k = 0; k < kRunsInFlight; ++k) {
-                    // test entry k of the current range
-                    const uint32_t ou = e[k].x - abase, ov = e[k].y - bbase;
-                    const uint32_t iu = h[k] ? (ou >> 5) : 0u, iv = h[k] ? (ov >> 5) : 0u;
-                    const uint32_t bu = 1u << (ou & 31), bv = 1u << (ov & 31);
-                    const bool mu = (sa[iu] & bu) != 0u, mv = (lb[iv] & bv) != 0u;
-                    const bool keep = h[k] && !mu && !mv;
-                    if (h[k] && mu != mv) {
-                        // the entry's whole effect: mark the unmarked endpoint (the
-                        // global word only once per workgroup)
-                        uint32_t* w = mu ? &lb[iv] : &sa[iu];
-                        const uint32_t bit = mu ? bv : bu;
-                        const uint32_t y = mu ? bbase + ov : abase + ou;
-                        if (!(atomicOr(w, bit) & bit)) atomicOr(&zbits[y >> 5], 1u << (y & 31));
-                    }
-                    const uint64_t ball = __ballot(keep);
-                    if (keep) {
-                        const u32x2 x = {ou, bbase + ov};
-                        wq[qn + (uint32_t)__popcll(ball & ((1ull << lane) - 1ull))] = x;
-                    }
-                    qn += (uint32_t)__popcll(ball);
-                    if (qn >= 64) {
-                        t3_flush(wq, qn, lane, ow, oh, cap, &s_used, st);
-                        qn = 0;
-                    }
-                    // reload register k with entry k of the next range (also after
-                    // the last range, from a safe address: an unconditional load
-                    // keeps the count of loads in flight known to the compiler)
+                    const u32x2 x = {ew[k] & kLoMask, (ew[k] >> kSliceBits) | (eh[k] << (32 - kSliceBits))};
                     {
-                        const uint32_t j = jn + (uint32_t)k * 64 + lane;
-                        h[k] = more && j < total;
-                        const uint64_t at = h[k] ? addr(j, tn) : 0ull;
-                        e[k] = __builtin_nontemporal_load(src + at);
+                        const uint32_t jb = jn + (uint32_t)k * 64, j = jb + (uint32_t)lane;
+                        const uint32_t off = more ? t3_offset(s_pre, s_off, nw, tn, jb, j) : 0u;
+                        const uint32_t at = more && j < total ? j + off : 0u;
+                        ew[k] = __builtin_nontemporal_load(srcw + at);
+                        eh[k] = __builtin_nontemporal_load(srch + at);
+                    }
+                    const bool h = j0 + (uint32_t)k * 64 + (uint32_t)lane < total;
+                    const uint32_t both =
+                        (sa[x.x >> 5] >> (x.x & 31)) & (lb[x.y >> 5] >> (x.y & 31)) & 1u;
+                    const bool pend = h && !both;
+                    const uint64_t ball = __ballot(pend);
+                    if (pend) pq[pn + (uint32_t)__popcll(ball & ((1ull << lane) - 1ull))] = x;
+                    pn += (uint32_t)__popcll(ball);
+                    if (pn >= 64) {
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        t3_settle(pq, 64, lane, sa, lb, abase, bbase, zbits, ow, oh, cap, &s_used,
+                                  st);
+                        const u32x2 rest = (uint32_t)lane < pn - 64 ? pq[64 + lane] : u32x2{0u, 0u};
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        if ((uint32_t)lane < pn - 64) pq[lane] = rest;
+                        pn -= 64;
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
                     }
                 }
                 if (!more) break;
                 j0 = jn;
             }
         }
+        // this slice's pending entries are settled before the next slice's
+        // bitmap replaces it
+        if (pn) {
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            t3_settle(pq, pn, lane, sa, lb, abase, bbase, zbits, ow, oh, cap, &s_used, st);
+        }
     }
-    if (qn) t3_flush(wq, qn, lane, ow, oh, cap, &s_used, st);
     __syncthreads();
     if (threadIdx.x == 0) wgcnt[wi] = min(s_used, cap);
 }
@@ -1129,7 +1161,8 @@ uint64_t tiled_scratch_bytes(uint64_t n, uint64_t m, bool plain) {
     const uint64_t ntile = (pl.nch1 + kScanTile - 1) / kScanTile;
     const uint64_t nbg = (R + kBPerBlock - 1) / kBPerBlock;
     const uint64_t nwg = R * nbg;
-    return al(4 * cap) + al(2 * cap) + al(8 * cap) + al(2 * pl.nch1 * R) + al(4 * pl.nch1 * R) +
+    return al(4 * cap) + al(2 * cap) + al(4 * cap) + al(cap) + al(2 * pl.nch1 * R) +
+           al(4 * pl.nch1 * R) +
            al(4 * (pl.nch1 + 1) * R) + al(8 * (R + 1)) + al(4 * (R + 1)) +
            al(2 * pl.nch2_max * (R + 1)) + al(32 * pl.nch2_max) + al(4 * ntile * R) +
            al(8 * (nwg + 1)) + al(4 * nwg) + al(4 * (nwg + 1));
@@ -1159,7 +1192,7 @@ int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint3
     const int R = pl.R;
     auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
     const uint64_t cap = pl.nch1 * kC1;                  // entries of each buffer
-    const uint64_t b_t1w = al(4 * cap), b_t1h = al(2 * cap), b_tmp2 = al(8 * cap);
+    const uint64_t b_t1w = al(4 * cap), b_t1h = al(2 * cap), b_tmp2 = al(4 * cap) + al(cap);
     const uint64_t b_seg1 = al(2 * pl.nch1 * R);
     const uint32_t ntile = (uint32_t)((pl.nch1 + kScanTile - 1) / kScanTile);
     const uint64_t b_tsum = al(4 * (uint64_t)ntile * R);
@@ -1182,7 +1215,8 @@ int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint3
     char* q = s->tiled.buf;
     uint32_t* t1w = reinterpret_cast<uint32_t*>(q); q += b_t1w;
     uint16_t* t1h = reinterpret_cast<uint16_t*>(q); q += b_t1h;
-    u32x2* tmp2 = reinterpret_cast<u32x2*>(q); q += b_tmp2;
+    const L2Buf tmp2{reinterpret_cast<uint32_t*>(q), reinterpret_cast<uint8_t*>(q + al(4 * cap))};
+    q += b_tmp2;
     uint16_t* segT = reinterpret_cast<uint16_t*>(q); q += b_seg1;
     uint32_t* cnt1 = reinterpret_cast<uint32_t*>(q); q += b_cnt1;
     uint32_t* pre1 = reinterpret_cast<uint32_t*>(q); q += b_pre1;
@@ -1244,7 +1278,7 @@ int run_hook_tiled_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, con
     const int R = (int)((n + (1ull << kSliceBits) - 1) >> kSliceBits);
     const uint64_t nch2 = m / kC2 + (uint64_t)R + 1;
     auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
-    const uint64_t b_sw = al(4 * m), b_sh = al(2 * m), b_tmp2 = al(8 * m);
+    const uint64_t b_sw = al(4 * m), b_sh = al(2 * m), b_tmp2 = al(4 * m) + al(m);
     const uint64_t b_base2 = al(8 * (R + 1)), b_cbase = al(4 * (R + 1));
     const uint64_t b_cfirst = al(4 * nch2), b_run2 = al(2 * nch2 * (R + 1));
     const uint32_t nbg = (uint32_t)((R + kBPerBlock - 1) / kBPerBlock);
@@ -1258,7 +1292,8 @@ int run_hook_tiled_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, con
     char* q = s->tiled.buf;
     uint32_t* sw = reinterpret_cast<uint32_t*>(q); q += b_sw;
     uint16_t* sh = reinterpret_cast<uint16_t*>(q); q += b_sh;
-    u32x2* tmp2 = reinterpret_cast<u32x2*>(q); q += b_tmp2;
+    const L2Buf tmp2{reinterpret_cast<uint32_t*>(q), reinterpret_cast<uint8_t*>(q + al(4 * m))};
+    q += b_tmp2;
     uint64_t* base2 = reinterpret_cast<uint64_t*>(q); q += b_base2;
     uint32_t* cbase = reinterpret_cast<uint32_t*>(q); q += b_cbase;
     uint32_t* cfirst = reinterpret_cast<uint32_t*>(q); q += b_cfirst;
