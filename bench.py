@@ -151,26 +151,45 @@ def bench_single(cc, torch, ed, n, m, steps, warmup, flags):
     return total_ms / steps, float(np.mean(hook_ms)), L
 
 
+def _time_batch(ctx, torch, vo, eo, ed, L, st, reps, sched=None):
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        ctx.batch(vo, eo, ed, L, st, sched=sched)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def _tune_report(r):
+    """The tuner's candidates (best-of-reps device time, upload to end of launch)
+    and its pick."""
+    return {"signature": r.signature.decode(),
+            "candidates_ms": {f"wave{c[0]}_multi{c[1]}": round(ms, 4) for c, ms in r.candidates()},
+            "pick": {"wave_max_n": int(r.pick.wave_max_n), "multi_min_n": int(r.pick.multi_min_n)}}
+
+
 def bench_batch(cc, torch, reps=5):
-    """4,096 graphs: one persistent cc_batch launch (and its captured graph replayed)
-    vs one cc_solve_async per graph."""
+    """4,096 graphs: the tuner's candidates, then one persistent cc_batch launch
+    with its pick (and its captured graph replayed) vs the fixed
+    workgroup-per-graph schedule and vs one cc_solve_async per graph."""
     import graphgen
     b = graphgen.batch_4096()
     vo = torch.from_numpy(b.vtx_off).cuda()
     eo = torch.from_numpy(b.edge_off).cuda()
     ed = torch.from_numpy(np.ascontiguousarray(b.edges)).cuda()
-    ctx = cc.Context()
+    ctx = cc.Context(tune_cache="")
     L = torch.empty(int(b.vtx_off[-1]), dtype=torch.int32, device="cuda")
     st = torch.empty(b.G, dtype=torch.int32, device="cuda")
+    tune, _, _ = ctx.batch_tune(vo, eo, ed, L, st, reps=3)
     ctx.batch(vo, eo, ed, L, st)
     torch.cuda.synchronize()
-    ts = []
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        ctx.batch(vo, eo, ed, L, st)
-        torch.cuda.synchronize()
-        ts.append(time.perf_counter() - t0)
-    t_batch = float(np.median(ts))
+    t_batch = _time_batch(ctx, torch, vo, eo, ed, L, st, reps)
+    Lf = torch.empty_like(L)
+    stf = torch.empty_like(st)
+    t_fixed = _time_batch(ctx, torch, vo, eo, ed, Lf, stf, reps, sched=(0, 0))
+    same_fixed = bool(torch.equal(Lf, L)) and bool(torch.equal(stf, st))
+    del Lf, stf
     # the same batch captured once (host work done at capture) and replayed
     Lg = torch.empty_like(L)
     stg = torch.empty_like(st)
@@ -210,8 +229,11 @@ def bench_batch(cc, torch, reps=5):
     # the labels written once (4 B per vertex)
     alg = 8 * m + 4 * sum_n
     return {"graphs": b.G, "sum_n": sum_n, "sum_m": m,
+            "tuner": _tune_report(tune),
             "batched_graphs_per_s": round(b.G / t_batch, 1),
             "batched_ms": round(t_batch * 1e3, 3),
+            "fixed_wg_per_graph_ms": round(t_fixed * 1e3, 3),
+            "fixed_identical": same_fixed,
             "algorithmic_bytes": alg,
             "achieved_GBps": round(alg / t_batch / 1e9, 1),
             "hbm_roofline_frac": round(alg / t_batch / 1e9 / PEAK_HBM_GBS, 4),
@@ -219,6 +241,35 @@ def bench_batch(cc, torch, reps=5):
             "per_graph_launch_graphs_per_s": round(b.G / t_loop, 1),
             "per_graph_launch_ms": round(t_loop * 1e3, 3),
             "speedup": round(t_loop / t_batch, 2), "identical_labels": same}
+
+
+def bench_batch_tail(cc, torch, reps=5):
+    """The 4,096-graph mix with its last 8 graphs replaced by R-MAT scale-20,
+    edgefactor-8 graphs: the tuner's candidates and pick vs the fixed
+    workgroup-per-graph schedule (labels equal; oracle parity of this batch's
+    schedules is a GPU test)."""
+    import graphgen
+    b = graphgen.batch_with_tail(graphgen.config_seed(4))
+    vo = torch.from_numpy(b.vtx_off).cuda()
+    eo = torch.from_numpy(b.edge_off).cuda()
+    ed = torch.from_numpy(np.ascontiguousarray(b.edges)).cuda()
+    ctx = cc.Context(tune_cache="")
+    L = torch.empty(int(b.vtx_off[-1]), dtype=torch.int32, device="cuda")
+    st = torch.empty(b.G, dtype=torch.int32, device="cuda")
+    tune, _, _ = ctx.batch_tune(vo, eo, ed, L, st, reps=3)
+    t_pick = _time_batch(ctx, torch, vo, eo, ed, L, st, reps)
+    Lf = torch.empty_like(L)
+    stf = torch.empty_like(st)
+    t_fixed = _time_batch(ctx, torch, vo, eo, ed, Lf, stf, max(1, reps // 2), sched=(0, 0))
+    same = bool(torch.equal(Lf, L)) and bool(torch.equal(stf, st))
+    ctx.close()
+    m = int(b.edge_off[-1])
+    return {"graphs": b.G, "sum_n": int(b.vtx_off[-1]), "sum_m": m,
+            "tuner": _tune_report(tune),
+            "pick_ms": round(t_pick * 1e3, 3), "fixed_wg_per_graph_ms": round(t_fixed * 1e3, 3),
+            "pick_speedup_over_fixed": round(t_fixed / t_pick, 2),
+            "pick_graphs_per_s": round(b.G / t_pick, 1),
+            "identical_labels": same}
 
 
 def bench_reducer(cc, torch, ed, n, L_ref, g=16, reps=3):
@@ -566,7 +617,7 @@ def main():
                     help="skip every section after the headline and the other variant")
     ap.add_argument("--only", default=None,
                     choices=["reducer", "update_log", "csr", "u64_ids", "share_rmat30", "batch",
-                             "serve"],
+                             "batch_tail", "serve"],
                     help="run just this one further section (for profiling it)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 4 GiB device copy (reference for HBM byte counters)")
@@ -680,6 +731,10 @@ def main():
         t1 = time.time()
         line["batch"] = bench_batch(cc, torch)
         log(f"batch done in {time.time() - t1:.1f} s")
+    if want("batch_tail"):
+        t1 = time.time()
+        line["batch_tail"] = bench_batch_tail(cc, torch)
+        log(f"batch with tail done in {time.time() - t1:.1f} s")
     if want("serve"):
         t1 = time.time()
         line["serve"] = bench_serve(cc, torch)

@@ -277,6 +277,20 @@ def batch_4096() -> Batch:
     return batch(4096, config_seed(4))
 
 
+def batch_with_tail(seed: int, G: int = 4096, tail: int = 8, tail_scale: int = 20,
+                    tail_ef: int = 8) -> Batch:
+    """G - tail graphs drawn as in batch() (n log-uniform in [2^8, 2^16], degree
+    uniform in [2, 32]) followed by `tail` R-MAT graphs of 2^tail_scale vertices
+    and tail_ef * 2^tail_scale entries: the same mix with a few graphs too large
+    for one workgroup."""
+    head = batch(G - tail, seed)
+    graphs = [head.graph(g) for g in range(head.G)]
+    for t in range(tail):
+        graphs.append((rmat(tail_scale, tail_ef << tail_scale, subseed(seed, 0x7A11 + t)),
+                       1 << tail_scale))
+    return batch_from_graphs(graphs)
+
+
 def pareto_n(u: float, alpha: float = 1.5, lo: float = 2.0**10, hi: float = 2.0**24) -> int:
     """Inverse CDF of a Pareto(alpha) truncated to [lo, hi] at quantile u."""
     la, ha = lo ** -alpha, hi ** -alpha

@@ -107,6 +107,15 @@ typedef struct cc_ctx_opts {
     uint32_t zroot_samples;   /* entries sampled for the zero root; 0 = 65536  */
     uint64_t hbm_budget;      /* bytes the server may hold resident; 0 = 3/4 of
                                  free memory at creation                        */
+    const char* tune_cache;   /* file of tuned batch schedules: read at
+                                 creation, appended by cc_batch_tune. NULL =
+                                 the CCMI_TUNE_CACHE environment variable (if
+                                 set), "" = no file (memory only)              */
+    uint32_t batch_autotune;  /* 1: cc_batch tunes (cc_batch_tune, 3 timed runs
+                                 per candidate) a batch whose shape has no
+                                 stored pick before it runs it; 0: such a batch
+                                 takes the default schedule                     */
+    uint32_t reserved;        /* 0 */
 } cc_ctx_opts;
 
 /* Create a context on a device: it owns scratch memory (status word, zero
@@ -406,8 +415,10 @@ int cc_solve_noalloc(uint64_t n, uint64_t m, const uint32_t* edge_list, uint32_t
  *   L                  device, vtx_off[G] int32, written: L[vtx_off[g] + v]
  *                      = smallest local ID of v's component in graph g
  *   status             device, G int32, written: CC_OK or CC_ERANGE per graph
- * The schedule (graph to workgroup mapping, LDS-resident parent arrays for
- * small graphs) is chosen by the context's tuner from the size mix.
+ * The schedule (cc_batch_sched) is the context's choice: the one forced with
+ * cc_batch_sched_force if any, else the pick stored for the batch's shape by
+ * cc_batch_tune (in this context or in the tune_cache file), else (with
+ * batch_autotune) a pick tuned now, else the default schedule.
  * Synchronous: returns after the labels are written.
  * Returns CC_OK when the launch ran (per-graph outcomes are in `status`).
  */
@@ -416,9 +427,10 @@ int cc_batch(cc_ctx* ctx, uint32_t G, const int64_t* vtx_off, const int64_t* edg
 
 /* The same batch captured once and replayed. Creation does everything of
    cc_batch that needs the host (reads and checks the offsets, builds the
-   largest-first work list in its own pinned and device buffers) and captures
-   the rest (the upload of the work list, which also resets the work ticket,
-   and the persistent launch) into a hipGraph; each cc_batch_graph_launch
+   largest-first work list in its own pinned and device buffers, with the
+   schedule cc_batch would take at creation) and captures the rest (the upload
+   of the work list, which also resets the work tickets, the whole-device
+   launches of multi graphs and the persistent launch) into a hipGraph; each cc_batch_graph_launch
    replays it on `stream` asynchronously, with no host work. The graph keeps
    the pointers it was created with: edges, L and status must stay allocated
    (their contents may change between launches: a replay labels whatever the
@@ -431,6 +443,74 @@ int cc_batch_graph_create(cc_ctx* ctx, uint32_t G, const int64_t* vtx_off, const
                           cc_batch_graph** out);
 int cc_batch_graph_launch(cc_batch_graph* graph, void* stream);
 void cc_batch_graph_destroy(cc_batch_graph* graph);
+
+/* ---- batch schedules and their tuner -------------------------------------- */
+/*
+ * Where each graph of a batch runs. The method is the same in every role
+ * (Algorithm 1 with path splitting, then pointer jumping; labels identical):
+ *   multi  multi_min_n > 0 and n >= multi_min_n: the whole device solves the
+ *          graph before the persistent launch. Its vertices and its entries
+ *          are split into chunks dealt to all workgroups (one launch per step
+ *          for all such graphs: init, hook, compress); its parent array is its
+ *          label slice in HBM.
+ *   wave   n <= min(wave_max_n, CC_BATCH_WAVE_MAX_N) and m <= CC_BATCH_WAVE_MAX_M:
+ *          one 64-lane wavefront solves the graph with its parent array in an
+ *          8 KB partition of LDS (16-bit entries); a workgroup runs 16 such
+ *          graphs at once.
+ *   tile   otherwise: one 1,024-thread workgroup solves the graph, its parent
+ *          array in LDS (16-bit entries) when n <= 2^16, else in HBM.
+ * The persistent launch deals the tile graphs first (largest first), then the
+ * wave graphs (largest first); a workgroup out of tile graphs turns to waves.
+ */
+typedef struct cc_batch_sched {
+    uint32_t wave_max_n;      /* 0 = no wave role                               */
+    uint32_t multi_min_n;     /* 0 = no multi role                              */
+} cc_batch_sched;
+#define CC_BATCH_WAVE_MAX_N 4096u
+#define CC_BATCH_WAVE_MAX_M 65536u
+
+/* cc_batch with an explicit schedule (NULL: the context's choice, as cc_batch). */
+int cc_batch_ex(cc_ctx* ctx, uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,
+                const int32_t* edges, int32_t* L, int32_t* status,
+                const cc_batch_sched* sched, void* stream);
+
+/* Force the schedule of the context's later cc_batch calls, captured batches
+   and nothing else (a server keeps its own choice); NULL returns the choice to
+   the stored picks and the default. */
+int cc_batch_sched_force(cc_ctx* ctx, const cc_batch_sched* sched);
+
+#define CC_TUNE_MAX_CAND 16
+#define CC_SCHED_DEFAULT 0u   /* no pick stored for the shape                   */
+#define CC_SCHED_TUNED   1u   /* timed by this call                             */
+#define CC_SCHED_STORED  2u   /* a pick stored earlier (this context or the file) */
+#define CC_SCHED_FORCED  3u   /* cc_batch_sched_force                           */
+typedef struct cc_batch_tune_result {
+    cc_batch_sched pick;                    /* the schedule cc_batch now takes   */
+    uint32_t source;                        /* CC_SCHED_*                        */
+    uint32_t n_cand;                        /* candidates timed (0 if reps == 0) */
+    cc_batch_sched cand[CC_TUNE_MAX_CAND];
+    float cand_ms[CC_TUNE_MAX_CAND];        /* best of reps, milliseconds        */
+    char signature[320];                    /* the shape key, NUL-terminated     */
+} cc_batch_tune_result;
+
+/*
+ * Tune the schedule for this batch's shape. The shape key is the device (its
+ * architecture name and compute-unit count) and the batch's size histogram:
+ * for each power-of-two range of n, the bit length of the graph count and of
+ * the mean entries per vertex (times 2) in that range. With reps > 0 every
+ * candidate (wave_max_n in {0, 256, 1024, 4096} x multi_min_n in {0, 2^14,
+ * 2^16 + 1, 2^18}, those that place the graphs differently for this batch)
+ * runs once untimed and reps times timed (HIP events on `stream`, from the
+ * upload of the work list to the end of the launch); the fastest becomes the
+ * stored pick for the shape, in the context and appended to the tune_cache
+ * file if there is one. Every run writes L and status as cc_batch would.
+ * With reps == 0 nothing runs: `out` reports the schedule cc_batch would take
+ * and its source. Synchronous. Errors: as cc_batch; CC_EDEVICE if the cache
+ * file cannot be appended (the pick is still stored in the context).
+ */
+int cc_batch_tune(cc_ctx* ctx, uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,
+                  const int32_t* edges, int32_t* L, int32_t* status, uint32_t reps,
+                  cc_batch_tune_result* out, void* stream);
 
 /* ---- continuous-batching server ------------------------------------------- */
 typedef struct cc_server cc_server;

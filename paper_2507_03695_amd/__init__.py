@@ -44,7 +44,38 @@ class CCError(RuntimeError):
 
 class _CtxOpts(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("zroot_samples", ctypes.c_uint32),
-                ("hbm_budget", ctypes.c_uint64)]
+                ("hbm_budget", ctypes.c_uint64), ("tune_cache", ctypes.c_char_p),
+                ("batch_autotune", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+BATCH_WAVE_MAX_N = 4096
+BATCH_WAVE_MAX_M = 65536
+TUNE_MAX_CAND = 16
+SCHED_DEFAULT, SCHED_TUNED, SCHED_STORED, SCHED_FORCED = 0, 1, 2, 3
+
+
+class BatchSched(ctypes.Structure):
+    """cc_batch_sched: graphs with n >= multi_min_n (if > 0) run on the whole
+    device, graphs with n <= wave_max_n (and m <= BATCH_WAVE_MAX_M) on one
+    wavefront, the rest on one workgroup each."""
+    _fields_ = [("wave_max_n", ctypes.c_uint32), ("multi_min_n", ctypes.c_uint32)]
+
+    def as_tuple(self):
+        return (int(self.wave_max_n), int(self.multi_min_n))
+
+    def __repr__(self):
+        return f"BatchSched(wave_max_n={self.wave_max_n}, multi_min_n={self.multi_min_n})"
+
+
+class TuneResult(ctypes.Structure):
+    """cc_batch_tune_result."""
+    _fields_ = [("pick", BatchSched), ("source", ctypes.c_uint32), ("n_cand", ctypes.c_uint32),
+                ("cand", BatchSched * TUNE_MAX_CAND), ("cand_ms", ctypes.c_float * TUNE_MAX_CAND),
+                ("signature", ctypes.c_char * 320)]
+
+    def candidates(self):
+        """[((wave_max_n, multi_min_n), ms), ...] of the timed candidates."""
+        return [(self.cand[i].as_tuple(), float(self.cand_ms[i])) for i in range(self.n_cand)]
 
 
 class _ServeOpts(ctypes.Structure):
@@ -100,6 +131,9 @@ SIGNATURES = {
     "cc_pack_ids": (_I32, [_P, _U64, _P, _U32, _P, _P]),
     "cc_unpack_ids": (_I32, [_P, _U64, _P, _U32, _P, _P]),
     "cc_batch": (_I32, [_P, _U32, _P, _P, _P, _P, _P, _P]),
+    "cc_batch_ex": (_I32, [_P, _U32, _P, _P, _P, _P, _P, ctypes.POINTER(BatchSched), _P]),
+    "cc_batch_sched_force": (_I32, [_P, ctypes.POINTER(BatchSched)]),
+    "cc_batch_tune": (_I32, [_P, _U32, _P, _P, _P, _P, _P, _U32, ctypes.POINTER(TuneResult), _P]),
     "cc_batch_graph_create": (_I32, [_P, _U32, _P, _P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
     "cc_batch_graph_launch": (_I32, [_P, _P]),
     "cc_batch_graph_destroy": (None, [_P]),
@@ -191,9 +225,11 @@ def solve(edges: torch.Tensor, n: int, out: torch.Tensor | None = None) -> torch
 class Context:
     """A cc_ctx: scratch for one solve at a time per stream (see cc.h)."""
 
-    def __init__(self, device: int | None = None, zroot_samples: int = 0, hbm_budget: int = 0):
+    def __init__(self, device: int | None = None, zroot_samples: int = 0, hbm_budget: int = 0,
+                 tune_cache: str | None = None, batch_autotune: bool = False):
         lib = load()
-        o = _CtxOpts(-1 if device is None else device, zroot_samples, hbm_budget)
+        o = _CtxOpts(-1 if device is None else device, zroot_samples, hbm_budget,
+                     None if tune_cache is None else tune_cache.encode(), int(batch_autotune), 0)
         h = ctypes.c_void_p()
         _check(lib.cc_create(ctypes.byref(h), ctypes.byref(o)), "cc_create")
         self._h = h
@@ -380,17 +416,45 @@ class Context:
                                               ctypes.byref(h)), "cc_batch_graph_create")
         return BatchGraph(self, h, (vtx_off, edge_off, edges, L, status))
 
-    def batch(self, vtx_off, edge_off, edges, L=None, status=None, stream=None):
+    def _batch_out(self, vtx_off, edges, L, status):
         G = vtx_off.numel() - 1
         if L is None:
             L = torch.empty(int(vtx_off[-1].item()), dtype=torch.int32, device=edges.device)
         if status is None:
             status = torch.empty(G, dtype=torch.int32, device=edges.device)
-        _check(self.lib.cc_batch(self._h, G, _dptr(vtx_off, (torch.int64,)),
-                                 _dptr(edge_off, (torch.int64,)), _dptr(edges, (torch.int32,)),
-                                 _dptr(L, (torch.int32,)), _dptr(status, (torch.int32,)),
-                                 _stream(stream)), "cc_batch")
+        return G, L, status
+
+    def batch(self, vtx_off, edge_off, edges, L=None, status=None, stream=None, sched=None):
+        """cc_batch (sched None: the context's choice) or cc_batch_ex with
+        sched = (wave_max_n, multi_min_n) or a BatchSched."""
+        G, L, status = self._batch_out(vtx_off, edges, L, status)
+        args = (self._h, G, _dptr(vtx_off, (torch.int64,)), _dptr(edge_off, (torch.int64,)),
+                _dptr(edges, (torch.int32,)), _dptr(L, (torch.int32,)),
+                _dptr(status, (torch.int32,)))
+        if sched is None:
+            _check(self.lib.cc_batch(*args, _stream(stream)), "cc_batch")
+        else:
+            sc = sched if isinstance(sched, BatchSched) else BatchSched(*sched)
+            _check(self.lib.cc_batch_ex(*args, ctypes.byref(sc), _stream(stream)), "cc_batch_ex")
         return L, status
+
+    def batch_sched_force(self, sched=None):
+        """cc_batch_sched_force: (wave_max_n, multi_min_n), a BatchSched, or None."""
+        if sched is None:
+            _check(self.lib.cc_batch_sched_force(self._h, None), "cc_batch_sched_force")
+            return
+        sc = sched if isinstance(sched, BatchSched) else BatchSched(*sched)
+        _check(self.lib.cc_batch_sched_force(self._h, ctypes.byref(sc)), "cc_batch_sched_force")
+
+    def batch_tune(self, vtx_off, edge_off, edges, L=None, status=None, reps=3, stream=None):
+        """cc_batch_tune -> (TuneResult, L, status)."""
+        G, L, status = self._batch_out(vtx_off, edges, L, status)
+        r = TuneResult()
+        _check(self.lib.cc_batch_tune(self._h, G, _dptr(vtx_off, (torch.int64,)),
+                                      _dptr(edge_off, (torch.int64,)), _dptr(edges, (torch.int32,)),
+                                      _dptr(L, (torch.int32,)), _dptr(status, (torch.int32,)),
+                                      reps, ctypes.byref(r), _stream(stream)), "cc_batch_tune")
+        return r, L, status
 
 
 class BatchGraph:

@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libccmi.so")
 STRESS_LIB = os.path.join(PKG, "libccmi_stress.so")
 SOURCES = ["cc_api.hip", "cc_kernels.hip", "cc_tiled.hip", "cc_batch.hip", "cc_serve.hip",
-           "cc_exchange.hip", "cc_wide.hip", "cc_noalloc.hip"]
+           "cc_exchange.hip", "cc_wide.hip", "cc_noalloc.hip", "cc_tune.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

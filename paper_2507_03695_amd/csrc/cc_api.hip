@@ -28,6 +28,8 @@ struct cc_ctx {
     StatusRec* st_ring = nullptr;
     hipEvent_t st_ev[CC_STATUS_RING] = {};
     uint64_t st_seq = 0;
+    // batch schedules: forced one, stored picks, the cache file
+    ccm::Tuner tuner;
 };
 
 namespace ccm {
@@ -182,6 +184,12 @@ extern "C" int cc_create(cc_ctx** out, const cc_ctx_opts* opts) {
     c->samples = samples;
     int rc = slot_create(&c->slot, dev, samples);
     if (rc) { delete c; return rc; }
+    if (opts && opts->reserved) {
+        slot_destroy(&c->slot);
+        delete c;
+        return fail(CC_EINVAL, "cc_ctx_opts.reserved must be 0");
+    }
+    tuner_open(&c->tuner, opts ? opts->tune_cache : nullptr, opts && opts->batch_autotune);
     if (opts && opts->hbm_budget) c->hbm_budget = opts->hbm_budget;
     else {
         size_t fr = 0, tot = 0;
@@ -200,6 +208,7 @@ int ctx_info(cc_ctx* ctx, int* device, uint64_t* budget, uint32_t* samples) {
     *samples = ctx->samples;
     return CC_OK;
 }
+Tuner* ctx_tuner(cc_ctx* ctx) { return ctx ? &ctx->tuner : nullptr; }
 }  // namespace ccm
 
 extern "C" void cc_destroy(cc_ctx* ctx) {
@@ -563,20 +572,39 @@ extern "C" int cc_get_zroot(cc_ctx* ctx, void* stream, uint32_t* zroot_out) {
 
 // ---- batch -------------------------------------------------------------------------------------
 
+// Arguments of cc_batch and its variants checked, descriptors built.
+static int batch_args(cc_ctx* ctx, uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,
+                      const int32_t* edges, int32_t* L, int32_t* status, void* stream,
+                      std::vector<GraphDesc>* descs) {
+    if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    if (!vtx_off || !edge_off || !status) return fail(CC_EINVAL, "NULL offsets or status");
+    int rc = set_dev(ctx);
+    if (rc) return rc;
+    return batch_descs(G, vtx_off, edge_off, edges, L, status, (hipStream_t)stream, descs);
+}
+
+static int check_sched(const cc_batch_sched* s) {
+    if (s && s->wave_max_n > CC_BATCH_WAVE_MAX_N)
+        return fail(CC_EINVAL, "wave_max_n above CC_BATCH_WAVE_MAX_N");
+    return CC_OK;
+}
+
 extern "C" int cc_batch_graph_create(cc_ctx* ctx, uint32_t G, const int64_t* vtx_off,
                                      const int64_t* edge_off, const int32_t* edges, int32_t* L,
                                      int32_t* status, void* stream, cc_batch_graph** out) {
     if (!out) return fail(CC_EINVAL, "out is NULL");
     *out = nullptr;
-    if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
     if (G == 0) return fail(CC_EINVAL, "G must be > 0");
-    if (!vtx_off || !edge_off || !status) return fail(CC_EINVAL, "NULL offsets or status");
-    int rc = set_dev(ctx);
+    std::vector<GraphDesc> descs;
+    int rc = batch_args(ctx, G, vtx_off, edge_off, edges, L, status, stream, &descs);
     if (rc) return rc;
+    BatchSched sc;
+    uint32_t source = 0;
+    if ((rc = tuner_choose(&ctx->tuner, &ctx->slot, G, descs.data(), (hipStream_t)stream, &sc,
+                           &source)))
+        return rc;
     void* h = nullptr;
-    rc = batch_graph_create(&ctx->slot, G, vtx_off, edge_off, edges, L, status, (hipStream_t)stream,
-                            &h);
-    if (rc) return rc;
+    if ((rc = batch_graph_create(&ctx->slot, G, descs.data(), sc, &h))) return rc;
     *out = reinterpret_cast<cc_batch_graph*>(h);
     return CC_OK;
 }
@@ -590,12 +618,54 @@ extern "C" void cc_batch_graph_destroy(cc_batch_graph* g) {
     if (g) batch_graph_destroy(g);
 }
 
-extern "C" int cc_batch(cc_ctx* ctx, uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,
-                        const int32_t* edges, int32_t* L, int32_t* status, void* stream) {
+extern "C" int cc_batch_ex(cc_ctx* ctx, uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,
+                           const int32_t* edges, int32_t* L, int32_t* status,
+                           const cc_batch_sched* sched, void* stream) {
     if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
     if (G == 0) return CC_OK;
-    if (!vtx_off || !edge_off || !status) return fail(CC_EINVAL, "NULL offsets or status");
-    int rc = set_dev(ctx);
+    int rc = check_sched(sched);
     if (rc) return rc;
-    return run_batch(&ctx->slot, G, vtx_off, edge_off, edges, L, status, (hipStream_t)stream);
+    std::vector<GraphDesc> descs;
+    if ((rc = batch_args(ctx, G, vtx_off, edge_off, edges, L, status, stream, &descs))) return rc;
+    hipStream_t hs = (hipStream_t)stream;
+    BatchSched sc;
+    if (sched) {
+        sc = *sched;
+    } else {
+        uint32_t source = 0;
+        if ((rc = tuner_choose(&ctx->tuner, &ctx->slot, G, descs.data(), hs, &sc, &source)))
+            return rc;
+    }
+    if ((rc = launch_batch(&ctx->slot, G, descs.data(), sc, hs))) return rc;
+    CCM_HIP(hipStreamSynchronize(hs));
+    return CC_OK;
+}
+
+extern "C" int cc_batch(cc_ctx* ctx, uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,
+                        const int32_t* edges, int32_t* L, int32_t* status, void* stream) {
+    return cc_batch_ex(ctx, G, vtx_off, edge_off, edges, L, status, nullptr, stream);
+}
+
+extern "C" int cc_batch_sched_force(cc_ctx* ctx, const cc_batch_sched* sched) {
+    if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    int rc = check_sched(sched);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(ctx->tuner.mu);
+    ctx->tuner.forced = sched != nullptr;
+    if (sched) ctx->tuner.force = *sched;
+    return CC_OK;
+}
+
+extern "C" int cc_batch_tune(cc_ctx* ctx, uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,
+                             const int32_t* edges, int32_t* L, int32_t* status, uint32_t reps,
+                             cc_batch_tune_result* out, void* stream) {
+    if (!out) return fail(CC_EINVAL, "out is NULL");
+    std::memset(out, 0, sizeof(*out));
+    if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    if (G == 0) return fail(CC_EINVAL, "G must be > 0");
+    if (reps > 1000) return fail(CC_EINVAL, "reps above 1000");
+    std::vector<GraphDesc> descs;
+    int rc = batch_args(ctx, G, vtx_off, edge_off, edges, L, status, stream, &descs);
+    if (rc) return rc;
+    return tuner_tune(&ctx->tuner, &ctx->slot, G, descs.data(), reps, (hipStream_t)stream, out);
 }

@@ -1,14 +1,24 @@
-// cc_batch.hip — many graphs in one persistent launch.
+// cc_batch.hip — many graphs in one batch: three roles, one enqueue.
 //
-// Each workgroup takes whole graphs from a largest-first work list (one atomic
-// ticket per graph) and runs Algorithm 1 for that graph on its own: init, one
-// pass of hooking over the graph's entries, pointer jumping, separated by
-// workgroup barriers, so the launch needs no grid-wide synchronisation. A graph
-// of at most 2^16 vertices keeps its parent array in the workgroup's LDS as
-// 16-bit entries (128 KB at n = 2^16; a link is a compare-and-swap on the
-// 32-bit word holding the entry); labels go to HBM once, coalesced. A larger
-// graph keeps its parent array in its label slice in HBM. Every thread keeps
-// kBatchEPT edge loads in flight.
+// Every graph runs Algorithm 1 on its own (init, one pass of hooking over its
+// entries with path splitting, pointer jumping); what differs is how much of
+// the device one graph gets (the schedule, cc_batch_sched):
+//  - tile: one workgroup takes whole graphs from a largest-first work list (one
+//    atomic ticket per graph), its steps separated by workgroup barriers, so
+//    the launch needs no grid-wide synchronisation. A graph of at most 2^16
+//    vertices keeps its parent array in the workgroup's LDS as 16-bit entries
+//    (128 KB at n = 2^16; a link is a compare-and-swap on the 32-bit word
+//    holding the entry); labels go to HBM once, coalesced. A larger graph keeps
+//    its parent array in its label slice in HBM.
+//  - wave: one wavefront takes a small graph from a second work list and solves
+//    it in an 8 KB partition of the workgroup's LDS, its steps separated by
+//    wavefront-level ordering only; 16 graphs per workgroup run at once. The
+//    persistent kernel runs the tile list first, then the wave list.
+//  - multi: a large graph is solved by the whole device before the persistent
+//    kernel: three launches (init, hook, compress) cover all such graphs of the
+//    batch, each block taking a chunk of one graph's vertices or entries from a
+//    host-built chunk table; the parent array is the label slice in HBM.
+// Every thread keeps kBatchEPT edge loads in flight.
 #include <algorithm>
 #include <cstring>
 #include <numeric>
@@ -27,7 +37,10 @@ typedef const CCM_GLOBAL i32x2 gedge_t;
 typedef CCM_GLOBAL uint32_t glabel_t;
 
 constexpr int kBatchBlock = 1024;
+constexpr int kWaves = kBatchBlock / 64;
 constexpr size_t kTicketBytes = 256;
+constexpr int kTileTicket = 0;     // word of the tile list's ticket
+constexpr int kWaveTicket = 16;    // the wave list's, on its own 64-byte line
 
 constexpr int kBatchEPT = 8;
 
@@ -35,7 +48,18 @@ constexpr int kBatchEPT = 8;
 __device__ __forceinline__ void gstore(glabel_t* p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ uint32_t gload_agent(glabel_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
+// The lanes of one wavefront execute together and its LDS operations complete
+// in issue order; this keeps the compiler from moving LDS accesses across the
+// point, so what one lane wrote before it is what another lane reads after it.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // ---- 16-bit parent array in LDS (n <= 2^16) ------------------------------------------
 
@@ -86,34 +110,41 @@ __device__ __forceinline__ void blink16(uint16_t* P, uint32_t* P32, uint32_t u, 
     }
 }
 
-__device__ __forceinline__ void solve_graph16(uint32_t* P32, uint32_t n, gedge_t* E, int64_t m,
-                                              glabel_t* out, int* bad_flag) {
-    const int tid = threadIdx.x;
+// One graph with its parent array in LDS, by a group of T threads (T = 64: one
+// wavefront; T = kBatchBlock: the workgroup); idx is the thread's index in the
+// group. Returns whether this thread saw an endpoint out of range.
+template <int T>
+__device__ __forceinline__ bool solve_graph16(uint32_t* P32, uint32_t n, gedge_t* E, int64_t m,
+                                              glabel_t* out, int idx) {
+    auto sync = [] {
+        if (T == 64) wave_sync();
+        else __syncthreads();
+    };
     uint16_t* P = reinterpret_cast<uint16_t*>(P32);
-    for (uint32_t i = tid; 2 * i < n; i += kBatchBlock) P32[i] = (2 * i) | ((2 * i + 1) << 16);
-    __syncthreads();
+    for (uint32_t i = idx; 2 * i < n; i += T) P32[i] = (2 * i) | ((2 * i + 1) << 16);
+    sync();
     bool bad = false;
     // Software pipeline over rounds of kBatchEPT entries per thread: register k
     // is reloaded with entry k of the next round right after entry k is linked,
     // so the next round's loads are in flight while this round is processed.
-    constexpr int64_t kRound = (int64_t)kBatchBlock * kBatchEPT;
+    constexpr int64_t kRound = (int64_t)T * kBatchEPT;
     // A graph without entries issues no edge load at all: its entry pointer may
     // be NULL (an edge-free batch) or point one past the batch's last entry.
     i32x2 x[kBatchEPT];
 #pragma unroll
     for (int k = 0; k < kBatchEPT; ++k) {
-        const int64_t e = tid + (int64_t)k * kBatchBlock;
+        const int64_t e = idx + (int64_t)k * T;
         x[k] = i32x2{0, 0};
         if (m > 0) x[k] = __builtin_nontemporal_load(E + (e < m ? e : 0));
     }
-    for (int64_t e0 = tid; e0 < m; e0 += kRound) {
+    for (int64_t e0 = idx; e0 < m; e0 += kRound) {
         // every entry's two parent reads first (LDS latency overlaps), then the links
         uint32_t pu[kBatchEPT], pv[kBatchEPT];
         bool live[kBatchEPT];
 #pragma unroll
         for (int k = 0; k < kBatchEPT; ++k) {
             const uint32_t u = (uint32_t)x[k].x, v = (uint32_t)x[k].y;
-            const bool in = e0 + (int64_t)k * kBatchBlock < m;
+            const bool in = e0 + (int64_t)k * T < m;
             const bool ok = u < n && v < n;
             bad |= in && !ok;
             live[k] = in && ok && u != v;
@@ -123,18 +154,18 @@ __device__ __forceinline__ void solve_graph16(uint32_t* P32, uint32_t n, gedge_t
 #pragma unroll
         for (int k = 0; k < kBatchEPT; ++k) {
             if (live[k]) blink16(P, P32, (uint32_t)x[k].x, pu[k], (uint32_t)x[k].y, pv[k]);
-            const int64_t e = e0 + kRound + (int64_t)k * kBatchBlock;
+            const int64_t e = e0 + kRound + (int64_t)k * T;
             x[k] = __builtin_nontemporal_load(E + (e < m ? e : 0));
         }
     }
-    if (bad) *bad_flag = 1;
-    __syncthreads();
-    for (uint32_t v = tid; v < n; v += kBatchBlock) {
+    sync();
+    for (uint32_t v = idx; v < n; v += T) {
         uint32_t r = P[v];
         uint32_t q = P[r];
         while (q != r) { r = q; q = P[r]; }
         gstore(&out[v], r);
     }
+    return bad;
 }
 
 // ---- 32-bit parent array in the label slice (HBM) --------------------------------------
@@ -152,10 +183,10 @@ __device__ __forceinline__ uint32_t bfind(glabel_t* P, uint32_t x, uint32_t px) 
     return x;
 }
 
-// Algorithm 1 hooking of one entry: the root of greater ID is linked under the
-// smaller; a failed CAS resumes from the value it returns.
-__device__ __forceinline__ void blink(glabel_t* P, uint32_t u, uint32_t v) {
-    uint32_t pu = P[u], pv = P[v];
+// Algorithm 1 hooking of one entry (u, v) whose parents pu, pv were read
+// earlier: the root of greater ID is linked under the smaller; a failed CAS
+// resumes from the value it returns.
+__device__ __forceinline__ void blink(glabel_t* P, uint32_t u, uint32_t pu, uint32_t v, uint32_t pv) {
     if (pu == pv || pu == v || pv == u) return;
     while (true) {
         const uint32_t ru = bfind(P, u, pu);
@@ -173,29 +204,54 @@ __device__ __forceinline__ void blink(glabel_t* P, uint32_t u, uint32_t v) {
     }
 }
 
+// Hooking of entries [first, end) of a graph with its parent array P in HBM, by
+// T threads (idx: this thread's index) stepping T entries at a time. Each
+// thread keeps kBatchEPT entries and their 2 * kBatchEPT parent reads in flight:
+// the entries of the next round are loaded while this round links, and a
+// round's parent reads are all issued before its first link. Returns whether
+// this thread saw an endpoint out of range.
+template <int T>
+__device__ __forceinline__ bool hook_hbm(glabel_t* P, uint32_t n, gedge_t* E, int64_t first,
+                                         int64_t end, int idx) {
+    bool bad = false;
+    if (first >= end) return bad;
+    constexpr int64_t kRound = (int64_t)T * kBatchEPT;
+    i32x2 x[kBatchEPT];
+#pragma unroll
+    for (int k = 0; k < kBatchEPT; ++k) {
+        const int64_t e = first + idx + (int64_t)k * T;
+        x[k] = __builtin_nontemporal_load(E + (e < end ? e : first));
+    }
+    for (int64_t e0 = first + idx; e0 < end; e0 += kRound) {
+        uint32_t pu[kBatchEPT], pv[kBatchEPT];
+        bool live[kBatchEPT];
+#pragma unroll
+        for (int k = 0; k < kBatchEPT; ++k) {
+            const uint32_t u = (uint32_t)x[k].x, v = (uint32_t)x[k].y;
+            const bool in = e0 + (int64_t)k * T < end;
+            const bool ok = u < n && v < n;
+            bad |= in && !ok;
+            live[k] = in && ok && u != v;
+            pu[k] = live[k] ? P[u] : 0u;
+            pv[k] = live[k] ? P[v] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < kBatchEPT; ++k) {
+            if (live[k]) blink(P, (uint32_t)x[k].x, pu[k], (uint32_t)x[k].y, pv[k]);
+            const int64_t e = e0 + kRound + (int64_t)k * T;
+            x[k] = __builtin_nontemporal_load(E + (e < end ? e : first));
+        }
+    }
+    return bad;
+}
+
 __device__ __forceinline__ void solve_graph_hbm(glabel_t* P, uint32_t n, gedge_t* E, int64_t m,
                                                 int* bad_flag) {
     const int tid = threadIdx.x;
     for (uint32_t v = tid; v < n; v += kBatchBlock) gstore(&P[v], v);
     __threadfence_block();
     __syncthreads();
-    bool bad = false;
-    for (int64_t e0 = tid; e0 < m; e0 += (int64_t)kBatchBlock * kBatchEPT) {
-        i32x2 x[kBatchEPT];
-#pragma unroll
-        for (int k = 0; k < kBatchEPT; ++k) {
-            const int64_t e = e0 + (int64_t)k * kBatchBlock;
-            x[k] = __builtin_nontemporal_load(E + (e < m ? e : 0));
-        }
-#pragma unroll
-        for (int k = 0; k < kBatchEPT; ++k) {
-            if (e0 + (int64_t)k * kBatchBlock >= m) continue;
-            const uint32_t u = (uint32_t)x[k].x, v = (uint32_t)x[k].y;
-            if (u >= n || v >= n) { bad = true; continue; }
-            if (u != v) blink(P, u, v);
-        }
-    }
-    if (bad) *bad_flag = 1;
+    if (hook_hbm<kBatchBlock>(P, n, E, 0, m, tid)) *bad_flag = 1;
     __threadfence_block();
     __syncthreads();
     for (uint32_t v = tid; v < n; v += kBatchBlock) {
@@ -206,29 +262,146 @@ __device__ __forceinline__ void solve_graph_hbm(glabel_t* P, uint32_t n, gedge_t
     }
 }
 
-__global__ __launch_bounds__(kBatchBlock) void k_batch(uint32_t G, const GraphDesc* __restrict__ descs,
+// The persistent kernel: tile graphs order[0, Gt) first, then wave graphs
+// order[Gt, Gt + Gw). lds16_cap: largest n whose 16-bit parent array fits the
+// dynamic LDS; wave_words: 32-bit words of LDS per wavefront in the wave role.
+__global__ __launch_bounds__(kBatchBlock) void k_batch(const GraphDesc* __restrict__ descs,
                                                        const uint32_t* __restrict__ order,
-                                                       uint32_t* ticket, uint32_t lds16_cap) {
+                                                       uint32_t Gt, uint32_t Gw, uint32_t* tickets,
+                                                       uint32_t lds16_cap, uint32_t wave_words) {
     extern __shared__ uint32_t sP[];
     __shared__ uint32_t s_next;
     __shared__ int s_bad;
-    while (true) {
+    while (Gt) {
         if (threadIdx.x == 0) {
-            s_next = atomicAdd(ticket, 1u);
+            s_next = atomicAdd(&tickets[kTileTicket], 1u);
             s_bad = 0;
         }
         __syncthreads();
         const uint32_t t = s_next;
-        if (t >= G) break;
+        if (t >= Gt) break;
         const GraphDesc d = descs[order[t]];
         gedge_t* E = (gedge_t*)d.edges;
-        if (d.n <= lds16_cap) solve_graph16(sP, d.n, E, d.m, (glabel_t*)d.L, &s_bad);
-        else solve_graph_hbm((glabel_t*)d.L, d.n, E, d.m, &s_bad);
+        if (d.n <= lds16_cap) {
+            if (solve_graph16<kBatchBlock>(sP, d.n, E, d.m, (glabel_t*)d.L, threadIdx.x)) s_bad = 1;
+        } else {
+            solve_graph_hbm((glabel_t*)d.L, d.n, E, d.m, &s_bad);
+        }
         __syncthreads();
         if (threadIdx.x == 0) *(CCM_GLOBAL int32_t*)d.status = s_bad ? CC_ERANGE : CC_OK;
         __syncthreads();
     }
+    // Wave role: from here on no workgroup barrier (waves leave independently).
+    // The tile role's last barrier has passed, so the LDS is free.
+    const int lane = threadIdx.x & 63;
+    uint32_t* wP = sP + (threadIdx.x >> 6) * wave_words;
+    while (Gw) {
+        uint32_t t = 0;
+        if (lane == 0) t = atomicAdd(&tickets[kWaveTicket], 1u);
+        t = __shfl(t, 0);
+        if (t >= Gw) break;
+        const GraphDesc d = descs[order[Gt + t]];
+        const bool bad = solve_graph16<64>(wP, d.n, (gedge_t*)d.edges, d.m, (glabel_t*)d.L, lane);
+        const bool any_bad = __ballot(bad) != 0;
+        if (lane == 0) *(CCM_GLOBAL int32_t*)d.status = any_bad ? CC_ERANGE : CC_OK;
+        wave_sync();   // the next graph's init must not overtake this one's reads
+    }
 }
+
+// ---- multi role: whole-device launches over chunk tables -------------------------------
+
+constexpr int kMultiBlock = 256;
+constexpr int kMultiVPT = 8;
+constexpr uint64_t kMultiVChunk = (uint64_t)kMultiBlock * kMultiVPT;   // vertices per chunk
+constexpr uint64_t kMultiEChunk = (uint64_t)kMultiBlock * kBatchEPT * 4;   // entries per chunk
+
+// The multi graph owning chunk b: pre holds K+1 chunk-count prefixes
+// (pre[0] = 0, pre[K] = total > b); returns k with pre[k] <= b < pre[k+1].
+__device__ __forceinline__ uint32_t chunk_owner(const uint32_t* pre, uint32_t K, uint32_t b) {
+    uint32_t lo = 0, hi = K;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// P_v = v over every multi graph; the first chunk of a graph also sets its
+// status to CC_OK (every multi graph has at least one vertex chunk).
+__global__ __launch_bounds__(kMultiBlock) void k_bm_init(const GraphDesc* __restrict__ descs,
+                                                         const uint32_t* __restrict__ mlist,
+                                                         const uint32_t* __restrict__ vpre, uint32_t K) {
+    const uint32_t total = vpre[K];
+    for (uint32_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const uint32_t k = chunk_owner(vpre, K, b);
+        const GraphDesc d = descs[mlist[k]];
+        glabel_t* P = (glabel_t*)d.L;
+        const uint64_t v0 = (uint64_t)(b - vpre[k]) * kMultiVChunk;
+#pragma unroll
+        for (int i = 0; i < kMultiVPT; ++i) {
+            const uint64_t v = v0 + (uint64_t)i * kMultiBlock + threadIdx.x;
+            if (v < d.n) gstore(&P[v], (uint32_t)v);
+        }
+        if (v0 == 0 && threadIdx.x == 0) gstore((glabel_t*)d.status, (uint32_t)CC_OK);
+    }
+}
+
+// Hooking of every multi graph's entries, a chunk of kMultiEChunk entries per
+// block step (Algorithm 1, as the HBM tile role, across the device).
+__global__ __launch_bounds__(kMultiBlock) void k_bm_hook(const GraphDesc* __restrict__ descs,
+                                                         const uint32_t* __restrict__ mlist,
+                                                         const uint32_t* __restrict__ epre, uint32_t K) {
+    const uint32_t total = epre[K];
+    for (uint32_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const uint32_t k = chunk_owner(epre, K, b);
+        const GraphDesc d = descs[mlist[k]];
+        glabel_t* P = (glabel_t*)d.L;
+        gedge_t* E = (gedge_t*)d.edges;
+        const int64_t e0 = (int64_t)(b - epre[k]) * (int64_t)kMultiEChunk;
+        const int64_t e1 = std::min<int64_t>(e0 + (int64_t)kMultiEChunk, d.m);
+        const bool bad = hook_hbm<kMultiBlock>(P, d.n, E, e0, e1, threadIdx.x);
+        if (bad) gstore((glabel_t*)d.status, (uint32_t)CC_ERANGE);
+    }
+}
+
+// P_v <- root(v) over every multi graph. Other XCDs linked these entries, so the
+// vertex's own entry and the root the walk stops at are read coherently (a
+// stale copy in this XCD's L2 is an ancestor, but a stale "root" would end the
+// walk early); a coherent value that differs continues the walk.
+__global__ __launch_bounds__(kMultiBlock) void k_bm_compress(const GraphDesc* __restrict__ descs,
+                                                             const uint32_t* __restrict__ mlist,
+                                                             const uint32_t* __restrict__ vpre, uint32_t K) {
+    const uint32_t total = vpre[K];
+    for (uint32_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const uint32_t k = chunk_owner(vpre, K, b);
+        const GraphDesc d = descs[mlist[k]];
+        glabel_t* P = (glabel_t*)d.L;
+        const uint64_t v0 = (uint64_t)(b - vpre[k]) * kMultiVChunk;
+        uint32_t pv[kMultiVPT];
+#pragma unroll
+        for (int i = 0; i < kMultiVPT; ++i) {
+            const uint64_t v = v0 + (uint64_t)i * kMultiBlock + threadIdx.x;
+            pv[i] = v < d.n ? gload_agent(&P[v]) : (uint32_t)v;
+        }
+#pragma unroll
+        for (int i = 0; i < kMultiVPT; ++i) {
+            const uint64_t v = v0 + (uint64_t)i * kMultiBlock + threadIdx.x;
+            if (v >= d.n || pv[i] == (uint32_t)v) continue;
+            uint32_t r = pv[i];
+            while (true) {
+                uint32_t q = P[r];
+                while (q != r) { r = q; q = P[r]; }
+                q = gload_agent(&P[r]);
+                if (q == r) break;
+                r = q;
+            }
+            if (r != pv[i]) gstore(&P[v], r);
+        }
+    }
+}
+
+// ---- host side ---------------------------------------------------------------------------
 
 void batch_scratch_free(BatchScratch* b) {
     if (b->dev) (void)hipFree(b->dev);
@@ -236,27 +409,52 @@ void batch_scratch_free(BatchScratch* b) {
     *b = BatchScratch{};
 }
 
-static size_t batch_bytes(uint64_t G) {
-    return kTicketBytes + ((4 * G + 63) & ~63ull) + sizeof(GraphDesc) * G;
+// Layout of the work list block (device and pinned host staging alike):
+// [tickets: 256 B][order: 4G][mlist: 4G][vpre: 4(G+1)][epre: 4(G+1)][descs: 40G],
+// every part on a 64-byte boundary. order = tile graphs, then wave graphs;
+// mlist = multi graphs; vpre / epre = their vertex / entry chunk-count prefixes.
+struct BatchLayout {
+    uint64_t order, mlist, vpre, epre, descs, bytes;
+};
+static BatchLayout batch_layout(uint64_t G) {
+    auto al = [](uint64_t x) { return (x + 63) & ~63ull; };
+    BatchLayout l;
+    l.order = kTicketBytes;
+    l.mlist = l.order + al(4 * G);
+    l.vpre = l.mlist + al(4 * G);
+    l.epre = l.vpre + al(4 * (G + 1));
+    l.descs = l.epre + al(4 * (G + 1));
+    l.bytes = l.descs + sizeof(GraphDesc) * G;
+    return l;
 }
 
-// Dynamic LDS for the 16-bit parent array: 2^16 entries (128 KB), or what the
-// device allows beside the static words; graphs above that size use HBM.
-static int lds_capacity(int device, size_t* bytes, uint32_t* entries16) {
+// Dynamic LDS of the persistent kernel: 2^16 16-bit entries (128 KB), or what
+// the device allows beside the static words; tile graphs above that size use
+// HBM. The wave role splits the same bytes into kWaves partitions.
+struct LdsPlan {
+    size_t bytes;
+    uint32_t tile_cap;     // largest n of a tile graph in LDS
+    uint32_t wave_words;   // 32-bit words per wavefront
+    uint32_t wave_cap;     // largest n of a wave graph
+};
+static int lds_plan(int device, LdsPlan* out) {
     int max_lds = 0;
     CCM_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
     size_t b = (size_t)max_lds > 1024 ? (size_t)max_lds - 1024 : 0;   // static words beside
     b = std::min<size_t>(b, (size_t)1 << 17);
     b &= ~(size_t)255;
-    *bytes = b;
-    *entries16 = (uint32_t)std::min<size_t>(b / sizeof(uint16_t), (size_t)1 << 16);
+    out->bytes = b;
+    out->tile_cap = (uint32_t)std::min<size_t>(b / sizeof(uint16_t), (size_t)1 << 16);
+    out->wave_words = (uint32_t)std::min<size_t>(b / 4 / kWaves, CC_BATCH_WAVE_MAX_N / 2);
+    out->wave_cap = 2 * out->wave_words;
     return CC_OK;
 }
 
 static int batch_alloc(BatchScratch* bs, uint64_t G) {
     uint64_t cap = std::max<uint64_t>(G, 1024);
-    if (hipMalloc(&bs->dev, batch_bytes(cap)) != hipSuccess ||
-        hipHostMalloc(&bs->host, batch_bytes(cap), hipHostMallocDefault) != hipSuccess) {
+    const uint64_t bytes = batch_layout(cap).bytes;
+    if (hipMalloc(&bs->dev, bytes) != hipSuccess ||
+        hipHostMalloc(&bs->host, bytes, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         batch_scratch_free(bs);
         return fail(CC_ENOMEM, "batch scratch allocation failed");
@@ -265,46 +463,120 @@ static int batch_alloc(BatchScratch* bs, uint64_t G) {
     return CC_OK;
 }
 
-// Host staging of one launch: the zeroed ticket, the largest-first order (by
-// entries + vertices) and the descriptors, in the device layout.
-static void batch_prepare(BatchScratch* bs, uint32_t G, const GraphDesc* descs) {
-    std::vector<uint32_t> order(G);
-    std::iota(order.begin(), order.end(), 0u);
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+int batch_wave_cap(int device, uint32_t* cap) {
+    LdsPlan lds;
+    int rc = lds_plan(device, &lds);
+    if (rc) return rc;
+    *cap = lds.wave_cap;
+    return CC_OK;
+}
+
+int batch_role(const GraphDesc& d, const BatchSched& sc, uint32_t wave_cap) {
+    const uint32_t wave_n = std::min(sc.wave_max_n, wave_cap);
+    if (sc.multi_min_n && d.n >= sc.multi_min_n) return kRoleMulti;
+    if (wave_n && d.n <= wave_n && d.m <= (int64_t)CC_BATCH_WAVE_MAX_M) return kRoleWave;
+    return kRoleTile;
+}
+
+BatchSched batch_default_sched() {
+    BatchSched s;
+    s.wave_max_n = 0;
+    s.multi_min_n = (1u << 16) + 1;   // beyond the LDS-resident tile graphs
+    return s;
+}
+
+// What one launch runs: graph counts per role and the multi chunk totals.
+struct BatchPlan {
+    uint32_t G = 0, Gt = 0, Gw = 0, Gm = 0;
+    uint32_t vchunks = 0, echunks = 0;
+};
+
+// Host staging of one launch: the zeroed tickets, the role lists (tile and wave
+// largest-first by entries + vertices), the chunk tables and the descriptors.
+static int batch_prepare(BatchScratch* bs, uint32_t G, const GraphDesc* descs,
+                         const BatchSched& sc, const LdsPlan& lds, BatchPlan* plan) {
+    std::vector<uint32_t> tile, wave, multi;
+    tile.reserve(G);
+    for (uint32_t g = 0; g < G; ++g) {
+        const int role = batch_role(descs[g], sc, lds.wave_cap);
+        (role == kRoleMulti ? multi : role == kRoleWave ? wave : tile).push_back(g);
+    }
+    auto larger = [&](uint32_t a, uint32_t b) {
         return descs[a].m + (int64_t)descs[a].n > descs[b].m + (int64_t)descs[b].n;
-    });
+    };
+    std::stable_sort(tile.begin(), tile.end(), larger);
+    std::stable_sort(wave.begin(), wave.end(), larger);
+    const BatchLayout l = batch_layout(G);
     char* h = bs->host;
     std::memset(h, 0, kTicketBytes);
-    uint32_t* h_order = reinterpret_cast<uint32_t*>(h + kTicketBytes);
-    GraphDesc* h_desc = reinterpret_cast<GraphDesc*>(h + kTicketBytes + ((4 * (uint64_t)G + 63) & ~63ull));
-    std::copy(order.begin(), order.end(), h_order);
-    std::copy(descs, descs + G, h_desc);
+    uint32_t* order = reinterpret_cast<uint32_t*>(h + l.order);
+    std::copy(tile.begin(), tile.end(), order);
+    std::copy(wave.begin(), wave.end(), order + tile.size());
+    uint32_t* mlist = reinterpret_cast<uint32_t*>(h + l.mlist);
+    uint32_t* vpre = reinterpret_cast<uint32_t*>(h + l.vpre);
+    uint32_t* epre = reinterpret_cast<uint32_t*>(h + l.epre);
+    uint64_t vt = 0, et = 0;
+    vpre[0] = epre[0] = 0;
+    for (size_t k = 0; k < multi.size(); ++k) {
+        const GraphDesc& d = descs[multi[k]];
+        mlist[k] = multi[k];
+        vt += std::max<uint64_t>(1, (d.n + kMultiVChunk - 1) / kMultiVChunk);
+        et += ((uint64_t)d.m + kMultiEChunk - 1) / kMultiEChunk;
+        if (vt > 0xFFFFFFFFull || et > 0xFFFFFFFFull)
+            return fail(CC_EINVAL, "multi graphs too large for one batch");
+        vpre[k + 1] = (uint32_t)vt;
+        epre[k + 1] = (uint32_t)et;
+    }
+    std::copy(descs, descs + G, reinterpret_cast<GraphDesc*>(h + l.descs));
+    plan->G = G;
+    plan->Gt = (uint32_t)tile.size();
+    plan->Gw = (uint32_t)wave.size();
+    plan->Gm = (uint32_t)multi.size();
+    plan->vchunks = (uint32_t)vt;
+    plan->echunks = (uint32_t)et;
+    return CC_OK;
 }
 
 // The device part of one launch: upload of the staging (which also zeroes the
-// ticket, so a captured copy of this sequence replays correctly), the
-// persistent kernel, and the coherence points around it. Only stream work: it
-// can be captured into a graph.
-static int batch_enqueue(int device, BatchScratch* bs, uint32_t G, hipStream_t stream) {
-    const size_t bytes = batch_bytes(G);
-    CCM_HIP(hipMemcpyAsync(bs->dev, bs->host, bytes, hipMemcpyHostToDevice, stream));
-    size_t lds_bytes = 0;
-    uint32_t lds_cap = 0;
-    int rc = lds_capacity(device, &lds_bytes, &lds_cap);
-    if (rc) return rc;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-    (void)hipGetLastError();
-    const int cus = device_cu_count(device);
-    const uint32_t grid = (uint32_t)std::min<int64_t>((int64_t)cus, (int64_t)G);
+// tickets, so a captured copy of this sequence replays correctly), the
+// whole-device launches of the multi graphs, the persistent kernel, and the
+// coherence points around them. Only stream work: it can be captured.
+static int batch_enqueue(int device, BatchScratch* bs, const BatchPlan& p, const LdsPlan& lds,
+                         hipStream_t stream) {
+    const BatchLayout l = batch_layout(p.G);
+    CCM_HIP(hipMemcpyAsync(bs->dev, bs->host, l.bytes, hipMemcpyHostToDevice, stream));
     char* d = bs->dev;
-    const uint64_t desc_off = kTicketBytes + ((4 * (uint64_t)G + 63) & ~63ull);
-    rc = cohere(stream);
+    const GraphDesc* descs = reinterpret_cast<const GraphDesc*>(d + l.descs);
+    const int cus = device_cu_count(device);
+    int rc = cohere(stream);
     if (rc) return rc;
-    k_batch<<<grid, kBatchBlock, lds_bytes, stream>>>(
-        G, reinterpret_cast<const GraphDesc*>(d + desc_off),
-        reinterpret_cast<const uint32_t*>(d + kTicketBytes), reinterpret_cast<uint32_t*>(d), lds_cap);
-    CCM_HIP(hipGetLastError());
+    if (p.Gm) {
+        const uint32_t* mlist = reinterpret_cast<const uint32_t*>(d + l.mlist);
+        const uint32_t* vpre = reinterpret_cast<const uint32_t*>(d + l.vpre);
+        const uint32_t* epre = reinterpret_cast<const uint32_t*>(d + l.epre);
+        const uint32_t cap = (uint32_t)cus * 8;
+        k_bm_init<<<std::min(p.vchunks, cap), kMultiBlock, 0, stream>>>(descs, mlist, vpre, p.Gm);
+        CCM_HIP(hipGetLastError());
+        if ((rc = cohere(stream))) return rc;
+        if (p.echunks) {
+            k_bm_hook<<<std::min(p.echunks, cap), kMultiBlock, 0, stream>>>(descs, mlist, epre, p.Gm);
+            CCM_HIP(hipGetLastError());
+            if ((rc = cohere(stream))) return rc;
+        }
+        k_bm_compress<<<std::min(p.vchunks, cap), kMultiBlock, 0, stream>>>(descs, mlist, vpre, p.Gm);
+        CCM_HIP(hipGetLastError());
+    }
+    if (p.Gt + p.Gw) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds.bytes);
+        (void)hipGetLastError();
+        const uint64_t want = (uint64_t)p.Gt + (p.Gw + kWaves - 1) / kWaves;
+        const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)cus, want);
+        k_batch<<<grid, kBatchBlock, lds.bytes, stream>>>(
+            descs, reinterpret_cast<const uint32_t*>(d + l.order), p.Gt, p.Gw,
+            reinterpret_cast<uint32_t*>(d), lds.tile_cap, lds.wave_words);
+        CCM_HIP(hipGetLastError());
+    }
     return cohere(stream);
 }
 
@@ -317,7 +589,8 @@ int batch_reserve(Slot* s, uint32_t G) {
 
 // The host staging is reused per call: the caller waits for the previous launch
 // on this slot (its upload) before the next one.
-int launch_batch(Slot* s, uint32_t G, const GraphDesc* descs, hipStream_t stream) {
+int launch_batch(Slot* s, uint32_t G, const GraphDesc* descs, const BatchSched& sc,
+                 hipStream_t stream) {
     if (G == 0) return CC_OK;
     BatchScratch& bs = s->batch;
     if (bs.cap < G) {
@@ -327,14 +600,17 @@ int launch_batch(Slot* s, uint32_t G, const GraphDesc* descs, hipStream_t stream
         int rc = batch_alloc(&bs, G);
         if (rc) return rc;
     }
-    batch_prepare(&bs, G, descs);
-    return batch_enqueue(s->device, &bs, G, stream);
+    LdsPlan lds;
+    int rc = lds_plan(s->device, &lds);
+    if (rc) return rc;
+    BatchPlan plan;
+    if ((rc = batch_prepare(&bs, G, descs, sc, lds, &plan))) return rc;
+    return batch_enqueue(s->device, &bs, plan, lds, stream);
 }
 
 // Offsets read back and checked, descriptors built (cc_batch's arguments).
-static int batch_descs(uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,
-                       const int32_t* edges, int32_t* L, int32_t* status, hipStream_t stream,
-                       std::vector<GraphDesc>* out) {
+int batch_descs(uint32_t G, const int64_t* vtx_off, const int64_t* edge_off, const int32_t* edges,
+                int32_t* L, int32_t* status, hipStream_t stream, std::vector<GraphDesc>* out) {
     std::vector<int64_t> vo(G + 1), eo(G + 1);
     CCM_HIP(hipMemcpyAsync(vo.data(), vtx_off, (G + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, stream));
     CCM_HIP(hipMemcpyAsync(eo.data(), edge_off, (G + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, stream));
@@ -369,12 +645,11 @@ struct BatchGraph {
     hipGraphExec_t exec = nullptr;
 };
 
-int batch_graph_create(Slot* s, uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,
-                       const int32_t* edges, int32_t* L, int32_t* status, hipStream_t stream,
+int batch_graph_create(Slot* s, uint32_t G, const GraphDesc* descs, const BatchSched& sc,
                        void** out) {
     *out = nullptr;
-    std::vector<GraphDesc> descs;
-    int rc = batch_descs(G, vtx_off, edge_off, edges, L, status, stream, &descs);
+    LdsPlan lds;
+    int rc = lds_plan(s->device, &lds);
     if (rc) return rc;
     BatchGraph* bg = new BatchGraph;
     bg->device = s->device;
@@ -382,7 +657,12 @@ int batch_graph_create(Slot* s, uint32_t G, const int64_t* vtx_off, const int64_
         delete bg;
         return rc;
     }
-    batch_prepare(&bg->bs, G, descs.data());
+    BatchPlan plan;
+    if ((rc = batch_prepare(&bg->bs, G, descs, sc, lds, &plan))) {
+        batch_scratch_free(&bg->bs);
+        delete bg;
+        return rc;
+    }
     // capture on a private stream of default priority (the null stream cannot be
     // captured); nothing else runs on it
     hipStream_t cs = nullptr;
@@ -394,7 +674,7 @@ int batch_graph_create(Slot* s, uint32_t G, const int64_t* vtx_off, const int64_
     }
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        rc = batch_enqueue(bg->device, &bg->bs, G, cs);
+        rc = batch_enqueue(bg->device, &bg->bs, plan, lds, cs);
         hipGraph_t gr = nullptr;
         const hipError_t e2 = hipStreamEndCapture(cs, &gr);
         bg->graph = gr;
@@ -429,16 +709,6 @@ void batch_graph_destroy(void* h) {
     if (bg->graph) (void)hipGraphDestroy(bg->graph);
     batch_scratch_free(&bg->bs);
     delete bg;
-}
-
-int run_batch(Slot* s, uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,
-              const int32_t* edges, int32_t* L, int32_t* status, hipStream_t stream) {
-    std::vector<GraphDesc> descs;
-    int rc = batch_descs(G, vtx_off, edge_off, edges, L, status, stream, &descs);
-    if (rc) return rc;
-    if ((rc = launch_batch(s, G, descs.data(), stream))) return rc;
-    CCM_HIP(hipStreamSynchronize(stream));
-    return CC_OK;
 }
 
 }  // namespace ccm

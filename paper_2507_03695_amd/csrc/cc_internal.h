@@ -6,7 +6,10 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <map>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "cc.h"
 
@@ -43,13 +46,18 @@ struct GraphDesc {
 };
 static_assert(sizeof(GraphDesc) == 40, "GraphDesc layout");
 
-// Scratch of the batched path: descriptors, largest-first order and the work
-// ticket, uploaded in one copy per launch.
+// Scratch of the batched path: the work tickets, the work lists, the chunk
+// tables of the whole-device graphs and the descriptors, uploaded in one copy
+// per launch (layout in cc_batch.hip).
 struct BatchScratch {
-    char* dev = nullptr;       // device: [ticket: 256 B][order: 4G][descs: 40G]
+    char* dev = nullptr;       // device
     char* host = nullptr;      // pinned host staging of the same layout
     uint64_t cap = 0;          // graphs
 };
+
+// A batch schedule (cc_batch_sched): which graphs run on the whole device, which
+// on one wavefront, the rest on one workgroup each.
+typedef cc_batch_sched BatchSched;
 
 // Scratch of the tiled zero-root hook (one block, grown on demand).
 struct TiledScratch {
@@ -164,19 +172,27 @@ int run_hook_tiled_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, con
                        uint32_t* P, hipStream_t stream, bool sym = false);
 
 // Batched path (cc_batch.hip).
-// Enqueue one persistent launch over G graphs described on the host.
-int launch_batch(Slot* s, uint32_t G, const GraphDesc* descs, hipStream_t stream);
+// The schedule taken when nothing else is known about a batch.
+BatchSched batch_default_sched();
+// Largest n of a wave-role graph on this device (its LDS per wavefront).
+int batch_wave_cap(int device, uint32_t* cap);
+// Role of one graph under a schedule: kRoleTile, kRoleWave or kRoleMulti.
+constexpr int kRoleTile = 0, kRoleWave = 1, kRoleMulti = 2;
+int batch_role(const GraphDesc& d, const BatchSched& sc, uint32_t wave_cap);
+// Enqueue one batch (the whole-device launches of its multi graphs, then the
+// persistent launch) over G graphs described on the host.
+int launch_batch(Slot* s, uint32_t G, const GraphDesc* descs, const BatchSched& sc,
+                 hipStream_t stream);
 // Size the slot's batch scratch for G graphs now (so later launches of at most
 // G graphs allocate nothing).
 int batch_reserve(Slot* s, uint32_t G);
-// cc_batch: offsets in device memory; synchronous.
-int run_batch(Slot* s, uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,
-              const int32_t* edges, int32_t* L, int32_t* status, hipStream_t stream);
+// Offsets read back and checked, descriptors built (cc_batch's arguments).
+int batch_descs(uint32_t G, const int64_t* vtx_off, const int64_t* edge_off, const int32_t* edges,
+                int32_t* L, int32_t* status, hipStream_t stream, std::vector<GraphDesc>* out);
 void batch_scratch_free(BatchScratch* b);
-// A captured cc_batch (opaque handle): creation reads and checks the offsets
-// like cc_batch and captures the upload and the launch into a graph.
-int batch_graph_create(Slot* s, uint32_t G, const int64_t* vtx_off, const int64_t* edge_off,
-                       const int32_t* edges, int32_t* L, int32_t* status, hipStream_t stream,
+// A captured cc_batch (opaque handle): creation takes descriptors built by
+// batch_descs and captures the upload and the launches into a graph.
+int batch_graph_create(Slot* s, uint32_t G, const GraphDesc* descs, const BatchSched& sc,
                        void** out);
 int batch_graph_launch(void* g, hipStream_t stream);
 void batch_graph_destroy(void* g);
@@ -232,5 +248,27 @@ __device__ __forceinline__ void stress_delay(uint32_t salt) {
 
 // Device, memory budget and zero-root sample count of a context.
 int ctx_info(cc_ctx* ctx, int* device, uint64_t* budget, uint32_t* samples);
+
+// Batch schedule tuner (cc_tune.hip): picks stored per device and shape, in
+// memory and optionally in a file.
+struct Tuner {
+    std::mutex mu;
+    std::string path;                          // the cache file ("" = none)
+    std::map<std::string, BatchSched> picks;   // key: device | signature
+    bool forced = false;
+    BatchSched force{};
+    bool autotune = false;
+};
+// Read the cache file (if any) into the tuner.
+void tuner_open(Tuner* t, const char* path_opt, bool autotune);
+// The schedule cc_batch takes for these graphs, and its source (CC_SCHED_*).
+// With autotune and no stored pick, tunes first (runs the batch).
+int tuner_choose(Tuner* t, Slot* s, uint32_t G, const GraphDesc* descs, hipStream_t stream,
+                 BatchSched* out, uint32_t* source);
+int tuner_tune(Tuner* t, Slot* s, uint32_t G, const GraphDesc* descs, uint32_t reps,
+               hipStream_t stream, cc_batch_tune_result* out);
+// Stored pick or default for these graphs (no forcing, no tuning): the server's.
+BatchSched tuner_lookup(Tuner* t, int device, uint32_t G, const GraphDesc* descs);
+Tuner* ctx_tuner(cc_ctx* ctx);
 
 }  // namespace ccm

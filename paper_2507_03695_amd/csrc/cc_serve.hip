@@ -120,6 +120,7 @@ struct Worker {
 struct cc_server {
     int device = 0;
     cc_serve_opts opts{};
+    ccm::Tuner* tuner = nullptr;   // the context's stored batch schedules
     uint64_t stage_cap = 0;      // bytes per worker staging buffer
     char* arena_base = nullptr;
     Arena arena;
@@ -209,7 +210,8 @@ void run_small(cc_server* s, Worker& w, std::vector<Req*>& rs) {
     hipError_t e = hipSuccess;
     if (edge_bytes) e = hipMemcpyAsync(w.dstage, w.hstage, edge_bytes, hipMemcpyHostToDevice, w.stream);
     if (e != hipSuccess) rc = hip_fail(e, "batch upload");
-    if (!rc) rc = launch_batch(&w.slot, G, descs.data(), w.stream);
+    if (!rc) rc = launch_batch(&w.slot, G, descs.data(),
+                               tuner_lookup(s->tuner, s->device, G, descs.data()), w.stream);
     if (!rc) {
         e = hipMemcpyAsync(w.hstage + edge_bytes, w.dstage + edge_bytes, total - edge_bytes,
                            hipMemcpyDeviceToHost, w.stream);
@@ -322,6 +324,7 @@ extern "C" int cc_serve_open(cc_ctx* ctx, const cc_serve_opts* opts, cc_server**
     if (rc) return rc;
     cc_server* s = new cc_server();
     s->device = dev;
+    s->tuner = ctx_tuner(ctx);
     if (opts) s->opts = *opts;
     if (!s->opts.max_inflight) s->opts.max_inflight = 64;
     if (!s->opts.queue_capacity) s->opts.queue_capacity = 4096;

@@ -152,6 +152,143 @@ def test_batch_4096_full(ctx):
         assert_same_labels(Lh[b.vtx_off[g]:b.vtx_off[g + 1]], alone, f"graph {g} alone")
 
 
+def _mixed_batch(seed, large=True):
+    """Every role's case in one batch: tiny graphs on both sides of the wave
+    limits (n 4,096, m 65,536), medium ones, graphs above 2^16 vertices on both
+    sides of the whole-device thresholds, a tiny graph denser than the wave role
+    takes, edge-free graphs (n = 0 included) and one out-of-range entry per size
+    class. Returns the Batch and the indices of the bad graphs."""
+    graphs = []
+    tiny = graphgen.batch(500, seed, lg_n_lo=0, lg_n_hi=12.6, deg_lo=0, deg_hi=24)
+    graphs += [tiny.graph(g) for g in range(tiny.G)]
+    mid = graphgen.batch(30, seed + 1, lg_n_lo=12, lg_n_hi=16, deg_lo=1, deg_hi=16)
+    graphs += [mid.graph(g) for g in range(mid.G)]
+    graphs += [(graphgen.er(4096, 65536, seed + 2), 4096),      # at both wave limits
+               (graphgen.er(4096, 65537, seed + 3), 4096),      # one entry too many
+               (graphgen.er(64, 70_000, seed + 4), 64),         # dense tiny: tile role
+               (np.zeros((0, 2), np.uint32), 0), (np.zeros((0, 2), np.uint32), 5),
+               (np.zeros((0, 2), np.uint32), 70_000)]
+    if large:
+        graphs += [(graphgen.rmat(17, 1 << 19, seed + 5) % 90_000, 90_000),
+                   (graphgen.er(1 << 18, 1 << 20, seed + 6), 1 << 18),
+                   (graphgen.rmat(19, 1 << 21, seed + 7), 1 << 19),
+                   (graphgen.er(16_384, 40_000, seed + 8), 16_384)]
+    with_entries = [g for g, (e, _) in enumerate(graphs) if len(e)]
+    tiny_bad = next(g for g in with_entries if g < tiny.G)
+    mid_bad = next(g for g in with_entries if g >= tiny.G)
+    bad = [tiny_bad, mid_bad] + ([len(graphs) - 4] if large else [])
+    for g in bad:
+        e, n = graphs[g]
+        e = np.array(e, np.int64)
+        e[len(e) // 2, 1] = n + 1                                 # out of range
+        graphs[g] = (e, n)
+    return graphgen.batch_from_graphs(graphs), bad
+
+
+SCHEDULES = [(0, 0), (4096, 0), (256, 0), (0, 1), (4096, 1), (4096, 65537), (1024, 16384),
+             (0, 1 << 18)]
+
+
+def _check_batch(b, L, st, what):
+    want, wst = oracle.cc_labels_batch(b.vtx_off, b.edge_off, b.edges)
+    assert np.array_equal(st.cpu().numpy(), wst), f"{what}: status"
+    ok = np.repeat(wst == 0, np.diff(b.vtx_off))
+    assert_same_labels(L.cpu().numpy().view(np.uint32)[ok], want.view(np.uint32)[ok], what)
+    return wst
+
+
+def test_batch_every_schedule(ctx):
+    """Each schedule forced (cc_batch_ex), on a batch holding every role's
+    cases: statuses and labels equal the oracle's."""
+    b, bad = _mixed_batch(61)
+    vo, eo, ed = batch_to_dev(b)
+    log(f"mixed batch: G={b.G} sum n={int(b.vtx_off[-1])} sum m={int(b.edge_off[-1])} bad={bad}")
+    for sc in SCHEDULES:
+        log(f"schedule {sc}")
+        L, st = ctx.batch(vo, eo, ed, sched=sc)
+        wst = _check_batch(b, L, st, f"schedule {sc}")
+        assert all(wst[g] == cc.CC_ERANGE for g in bad)
+
+
+def test_batch_schedule_captured(ctx):
+    """A captured batch takes the context's forced schedule (every role at once
+    here) and its replays equal the oracle, with eager batches between them."""
+    b, _ = _mixed_batch(62)
+    vo, eo, ed = batch_to_dev(b)
+    L = torch.empty(int(b.vtx_off[-1]), dtype=torch.int32, device="cuda")
+    st = torch.empty(b.G, dtype=torch.int32, device="cuda")
+    ctx.batch_sched_force((1024, 16384))
+    try:
+        with ctx.batch_graph(vo, eo, ed, L, st) as gr:
+            for rep in range(3):
+                L.fill_(-1)
+                st.fill_(7)
+                ctx.batch(vo, eo, ed, sched=(0, 0))            # eager work in between
+                torch.cuda.synchronize()
+                gr.launch()
+                torch.cuda.synchronize()
+                _check_batch(b, L, st, f"captured replay {rep}")
+    finally:
+        ctx.batch_sched_force(None)
+
+
+def test_batch_tuner_and_cache(tmp_path):
+    """cc_batch_tune times the candidates, stores the fastest for the batch's
+    shape in the context and the cache file; a new context reads it back;
+    forcing overrides it; batch_autotune tunes on first sight. Every run's labels
+    equal the oracle's."""
+    path = str(tmp_path / "tune.txt")
+    b, _ = _mixed_batch(63)
+    vo, eo, ed = batch_to_dev(b)
+    c1 = cc.Context(tune_cache=path)
+    try:
+        r0, _, _ = c1.batch_tune(vo, eo, ed, reps=0)
+        assert r0.source == cc.SCHED_DEFAULT and r0.n_cand == 0
+        r, L, st = c1.batch_tune(vo, eo, ed, reps=2)
+        _check_batch(b, L, st, "tuning runs")
+        cands = r.candidates()
+        log("candidates: " + ", ".join(f"{c}: {ms:.3f} ms" for c, ms in cands))
+        assert r.source == cc.SCHED_TUNED and r.n_cand >= 4
+        best = min(cands, key=lambda t: t[1])
+        assert r.pick.as_tuple() == best[0]
+        assert len({c for c, _ in cands}) == len(cands)
+        r1, _, _ = c1.batch_tune(vo, eo, ed, reps=0)
+        assert r1.source == cc.SCHED_STORED and r1.pick.as_tuple() == best[0]
+        lines = open(path).read().splitlines()
+        assert len(lines) == 1 and lines[0].startswith("ccmi-batch-tune-v1 ")
+        f = lines[0].split()
+        assert (int(f[3]), int(f[4])) == best[0]
+        assert r.signature.decode() == f[1] + "|" + f[2]
+    finally:
+        c1.close()
+    c2 = cc.Context(tune_cache=path)
+    try:
+        r2, _, _ = c2.batch_tune(vo, eo, ed, reps=0)
+        assert r2.source == cc.SCHED_STORED and r2.pick.as_tuple() == best[0]
+        L, st = c2.batch(vo, eo, ed)
+        _check_batch(b, L, st, "stored pick")
+        c2.batch_sched_force((4096, 0))
+        r3, _, _ = c2.batch_tune(vo, eo, ed, reps=0)
+        assert r3.source == cc.SCHED_FORCED and r3.pick.as_tuple() == (4096, 0)
+        L, st = c2.batch(vo, eo, ed)
+        _check_batch(b, L, st, "forced")
+        c2.batch_sched_force(None)
+        r4, _, _ = c2.batch_tune(vo, eo, ed, reps=0)
+        assert r4.source == cc.SCHED_STORED
+    finally:
+        c2.close()
+    c3 = cc.Context(tune_cache="", batch_autotune=True)
+    try:
+        L, st = c3.batch(vo, eo, ed)
+        _check_batch(b, L, st, "autotuned")
+        r5, _, _ = c3.batch_tune(vo, eo, ed, reps=0)
+        assert r5.source == cc.SCHED_STORED
+    finally:
+        c3.close()
+    with pytest.raises(cc.CCError):
+        cc.Context(tune_cache="").batch(vo, eo, ed, sched=(8192, 0))   # above the wave cap
+
+
 def _requests(count, seed, hi=2.0**24):
     reqs = graphgen.serve_stream(count, seed, rate_per_s=1e9, hi=hi)
     out = []
