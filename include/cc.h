@@ -81,10 +81,7 @@ int cc_version(void);
    L2. Labels are identical either way. Pass it for lists in which a vertex
    recurs in many entries at once, such as a Reducer's messages from several
    shares: grouped, their links contend for the same roots (R-MAT-26's 165 M
-   SiskinCC messages: 4.6 ms in the given order, 13 ms grouped). It also keeps
-   the plain hook spread over all XCDs for small parent arrays (n <= 2^18 with
-   m >= 2^18), which otherwise run on one XCD so that their hot entries live
-   in one L2. */
+   SiskinCC messages: 4.6 ms in the given order, 13 ms grouped). */
 #define CC_F_NO_TILE      0x10u
 /* cc_compress with CC_F_ZROOT: give the zero root's component its smallest ID
    in the same pass (what cc_canon writes), so that no cc_canon is needed.

@@ -170,13 +170,16 @@ __device__ __forceinline__ bool solve_graph16(uint32_t* P32, uint32_t n, gedge_t
 
 // ---- 32-bit parent array in the label slice (HBM) --------------------------------------
 
-// Root of x with path splitting (each visited vertex takes its grandparent).
-__device__ __forceinline__ uint32_t bfind(glabel_t* P, uint32_t x, uint32_t px) {
+// Root of x; with split, path splitting (each visited vertex takes its
+// grandparent) with device-coherent stores (the rule of cc_kernels.hip's
+// find_root), used where the graph's parent array outgrows one XCD's L2
+// (split_walks).
+__device__ __forceinline__ uint32_t bfind(glabel_t* P, uint32_t x, uint32_t px, bool split) {
     while (px != x) {
         const uint32_t gp = P[px];
         if (gp == px) return px;
         stress_delay(x);
-        gstore(&P[x], gp);
+        if (split) gstore(&P[x], gp);
         x = px;
         px = gp;
     }
@@ -186,16 +189,23 @@ __device__ __forceinline__ uint32_t bfind(glabel_t* P, uint32_t x, uint32_t px) 
 // Algorithm 1 hooking of one entry (u, v) whose parents pu, pv were read
 // earlier: the root of greater ID is linked under the smaller; a failed CAS
 // resumes from the value it returns.
-__device__ __forceinline__ void blink(glabel_t* P, uint32_t u, uint32_t pu, uint32_t v, uint32_t pv) {
+__device__ __forceinline__ void blink(glabel_t* P, uint32_t u, uint32_t pu, uint32_t v, uint32_t pv,
+                                      bool split) {
     if (pu == pv || pu == v || pv == u) return;
     while (true) {
-        const uint32_t ru = bfind(P, u, pu);
-        const uint32_t rv = bfind(P, v, pv);
+        const uint32_t ru = bfind(P, u, pu, split);
+        const uint32_t rv = bfind(P, v, pv, split);
         if (ru == rv) return;
         const uint32_t hi = ru < rv ? rv : ru;
         const uint32_t lo = ru < rv ? ru : rv;
-        uint32_t old = hi;
         stress_delay(hi);
+        // a coherent read before the CAS, as in cc_kernels.hip's link
+        uint32_t old = gload_agent(&P[hi]);
+        if (old != hi) {
+            u = hi; pu = old;
+            v = lo; pv = lo;
+            continue;
+        }
         if (__hip_atomic_compare_exchange_strong(&P[hi], &old, lo, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             return;
@@ -215,6 +225,7 @@ __device__ __forceinline__ bool hook_hbm(glabel_t* P, uint32_t n, gedge_t* E, in
                                          int64_t end, int idx) {
     bool bad = false;
     if (first >= end) return bad;
+    const bool split = split_walks(0, n);
     constexpr int64_t kRound = (int64_t)T * kBatchEPT;
     i32x2 x[kBatchEPT];
 #pragma unroll
@@ -237,7 +248,7 @@ __device__ __forceinline__ bool hook_hbm(glabel_t* P, uint32_t n, gedge_t* E, in
         }
 #pragma unroll
         for (int k = 0; k < kBatchEPT; ++k) {
-            if (live[k]) blink(P, (uint32_t)x[k].x, pu[k], (uint32_t)x[k].y, pv[k]);
+            if (live[k]) blink(P, (uint32_t)x[k].x, pu[k], (uint32_t)x[k].y, pv[k], split);
             const int64_t e = e0 + kRound + (int64_t)k * T;
             x[k] = __builtin_nontemporal_load(E + (e < end ? e : first));
         }
@@ -254,11 +265,22 @@ __device__ __forceinline__ void solve_graph_hbm(glabel_t* P, uint32_t n, gedge_t
     if (hook_hbm<kBatchBlock>(P, n, E, 0, m, tid)) *bad_flag = 1;
     __threadfence_block();
     __syncthreads();
+    // Links are CASes performed at the memory side, which leave this XCD's L2
+    // copy of a linked root as it was: the vertex's own entry and the root a
+    // walk stops at are read coherently, and a coherent value that differs
+    // continues the walk (as k_bm_compress).
     for (uint32_t v = tid; v < n; v += kBatchBlock) {
-        uint32_t r = P[v];
-        uint32_t q = P[r];
-        while (q != r) { r = q; q = P[r]; }
-        gstore(&P[v], r);
+        const uint32_t p = gload_agent(&P[v]);
+        if (p == v) continue;
+        uint32_t r = p;
+        while (true) {
+            uint32_t q = P[r];
+            while (q != r) { r = q; q = P[r]; }
+            q = gload_agent(&P[r]);
+            if (q == r) break;
+            r = q;
+        }
+        if (r != p) gstore(&P[v], r);
     }
 }
 

@@ -33,6 +33,17 @@ constexpr uint32_t kStatusInternal = 2u;   // a scratch bound check failed (a bu
 constexpr uint32_t kStatusLogFull = 4u;    // an update log ran out of capacity
 constexpr uint32_t kStatusBadOffsets = 8u; // CSR offsets not a valid row index
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+
+// Path splitting in the direct hooks' walks pays only where the parent array
+// outgrows one XCD's L2 (4 MB): below that every walk step is an L2 hit and the
+// splitting stores, which go to memory, cost more than the steps they save
+// (ER n = 2^16, 2^20 entries: 0.82 ms with splitting, 0.14 ms without; R-MAT
+// n = 2^22 direct hook: 4.9 ms with, 7.2 ms without). CC_F_NO_SPLIT turns it
+// off everywhere.
+constexpr uint64_t kSplitMinBytes = 4ull << 20;
+__host__ __device__ inline bool split_walks(uint32_t flags, uint64_t n, uint64_t entry_bytes = 4) {
+    return !(flags & CC_F_NO_SPLIT) && n * entry_bytes > kSplitMinBytes;
+}
 constexpr uint32_t kGridCap = 256 * 32;   // blocks of a grid-stride launch over n
 
 // One graph of a batched launch: where its entries and labels live.

@@ -203,11 +203,12 @@ __global__ __launch_bounds__(kBlock) void k_zbits_clear(uint32_t* zbits, uint64_
 
 // Root of x, given px = a value read from P[x]. SPLIT = 1: path splitting (each
 // visited vertex takes its grandparent); SPLIT = 0: plain walk.
-// The splitting writes are device-coherent stores: a plain store leaves the line
-// in the writing XCD's L2, and such a copy has been observed to outlive later
-// kernels' writes from other XCDs (a reader on that XCD then sees the old
-// parent). Each one is issued after the next step's load, so that its latency
-// overlaps the walk instead of adding to it.
+// The splitting writes are device-coherent stores. A plain store would leave a
+// dirty line in the writing XCD's L2 whose other words are that XCD's copies;
+// links are CASes performed at the memory side, which that copy does not see,
+// so the line's write-back can undo a link made meanwhile in the same line (a
+// whole-device batch lost links this way). Each store is issued after the next
+// step's load, so that its latency overlaps the walk instead of adding to it.
 template <int SPLIT>
 __device__ __forceinline__ uint32_t find_root(uint32_t* P, uint32_t x, uint32_t px) {
     if (px == x) return x;
@@ -225,6 +226,16 @@ __device__ __forceinline__ uint32_t find_root(uint32_t* P, uint32_t x, uint32_t 
     return px;
 }
 
+// The check before each link's CAS. Global atomics are performed at the memory
+// side, past the XCD's L2, and leave the L2's copy of the word as it was; a
+// walk that reads P through the L2 can therefore end at a root that has since
+// been linked. A CAS on such an entry fails, but only after its round trip, and
+// every CAS on one word waits for the ones before it: a giant component's
+// former root collects thousands (ER n = 2^16, 2^20 entries: 16,000 CAS on one
+// word, a 1.6 ms hook). The entry is read coherently first (a load, which does
+// not wait behind the CASes) and a changed entry continues the walk from its
+// new value; the CAS is issued only on an entry that still reads as a root.
+// ER n = 2^16, 2^20 entries: 1.7 M CAS -> 0.11 M, 1.6-3.4 ms -> 0.16 ms.
 // Algorithm 1 / 3 hooking of one entry whose endpoints u, v have parents pu, pv.
 // Returns the root under which both endpoints ended up (the surviving root of
 // the link, or the common root found). When it is the zero root z, both
@@ -243,6 +254,13 @@ __device__ __forceinline__ uint32_t link(uint32_t* P, uint32_t u, uint32_t pu, u
         const uint32_t hi = u_low ? rv : ru;
         const uint32_t lo = u_low ? ru : rv;
         stress_delay(hi);
+        // hi's entry read coherently first (the check described above)
+        const uint32_t cur = ld_agent(&P[hi]);
+        if (cur != hi) {
+            u = hi; pu = cur;
+            v = lo; pv = lo;
+            continue;
+        }
         const uint32_t old = atomicCAS(&P[hi], hi, lo);
         if (old == hi) {
             if (linked) *linked = hi;
@@ -414,37 +432,6 @@ __global__ __launch_bounds__(kBlock) void k_hook(const uint32_t* __restrict__ ed
     hook_entries<ZR, SPLIT, LOG>(u, v, n, z, P, zbits, st, log, log_cap, log_count, sym != 0);
 }
 
-// The same hook confined to one XCD, for parent arrays small enough to live in
-// one XCD's L2. Workgroups are dealt to the eight XCDs in turn (workgroup i runs
-// on XCD i mod 8); here only every eighth workgroup works, so all working
-// workgroups share one L2 and see each other's parent updates there, instead of
-// following copies of the whole (small, hot) array that other XCDs' L2s keep.
-// The working workgroups walk the tiles in a grid-stride loop.
-constexpr uint32_t kXcds = 8;
-
-template <bool ZR, int SPLIT>
-__global__ __launch_bounds__(kBlock) void k_hook_xcd(const uint32_t* __restrict__ edges, uint64_t m,
-                                                     uint32_t n, uint32_t* P, uint32_t* zbits,
-                                                     DevState* st, uint32_t sym) {
-    if (blockIdx.x % kXcds != 0) return;
-    const uint64_t workers = gridDim.x / kXcds;
-    const uint32_t z = ZR ? ld_agent(&st->zroot) : 0u;
-    const u32x2* E = reinterpret_cast<const u32x2*>(edges);
-    constexpr uint64_t per = (uint64_t)kBlock * kEPT;
-    for (uint64_t t = blockIdx.x / kXcds; t * per < m; t += workers) {
-        uint32_t u[kEPT], v[kEPT];
-#pragma unroll
-        for (int k = 0; k < kEPT; ++k) {
-            const uint64_t e = t * per + (uint64_t)k * kBlock + threadIdx.x;
-            u32x2 uv = {0u, 0u};
-            if (e < m) uv = __builtin_nontemporal_load(E + e);
-            u[k] = uv.x;
-            v[k] = uv.y;
-        }
-        hook_entries<ZR, SPLIT, false>(u, v, n, z, P, zbits, st, nullptr, 0, nullptr, sym != 0);
-    }
-}
-
 // ---- CSR input -------------------------------------------------------------------
 // Row u of a CSR graph holds the entries (u, adj[j]) for j in [off[u], off[u+1]);
 // these are the same unordered pairs as a COO list, sorted by first endpoint,
@@ -536,11 +523,9 @@ __global__ __launch_bounds__(kBlock) void k_csr_push(const uint64_t* __restrict_
     if (bad) atomicOr(&st->status, kStatusRange);
 }
 
-// ONE_XCD: the launch has 8 workgroups per working one and only those of XCD 0
-// work, walking the tiles in a grid-stride loop (small parent arrays, as
-// k_hook_xcd); otherwise workgroup t takes tile t only (a launch may cover a
-// prefix of the tiles, as the warm-up does).
-template <bool ZR, int SPLIT, bool ONE_XCD = false>
+// Workgroup t takes tile t (a launch may cover a prefix of the tiles, as the
+// warm-up does).
+template <bool ZR, int SPLIT>
 __global__ __launch_bounds__(kBlock) void k_csr_hook(const uint64_t* __restrict__ off,
                                                      const uint32_t* __restrict__ adj, uint32_t n,
                                                      uint64_t m, const uint32_t* __restrict__ tstart,
@@ -549,13 +534,9 @@ __global__ __launch_bounds__(kBlock) void k_csr_hook(const uint64_t* __restrict_
     __shared__ uint32_t head[kCsrTile];
     __shared__ uint32_t s_wmax[kBlock / 64];
     const uint32_t z = ZR ? ld_agent(&st->zroot) : 0u;
-    uint64_t t0 = blockIdx.x, tstep = ntiles;           // one tile per workgroup
-    if (ONE_XCD) {
-        if (blockIdx.x % kXcds != 0) return;
-        t0 = blockIdx.x / kXcds;
-        tstep = gridDim.x / kXcds;
-    }
-    for (uint64_t t = t0; t < ntiles; t += tstep) {
+    if (blockIdx.x >= ntiles) return;
+    {
+    const uint64_t t = blockIdx.x;
     const uint64_t p0 = t * kCsrTile;
     uint32_t ua = tstart[t];
     uint32_t ub = (t + 1 < ntiles) ? tstart[t + 1] : n - 1;
@@ -799,8 +780,6 @@ int cohere(hipStream_t stream) {
 
 // ---- host-side launchers ---------------------------------------------------------------
 
-constexpr uint64_t kOneXcdMaxN = 1u << 18;   // parent arrays of at most 1 MB
-constexpr uint64_t kOneXcdMinM = 1u << 18;   // and at least this many entries
 
 static uint32_t grid_for(uint64_t work, uint64_t per_block, uint32_t cap) {
     uint64_t g = (work + per_block - 1) / per_block;
@@ -908,26 +887,15 @@ int run_hook(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P
     const uint64_t blocks = (m + per - 1) / per;
     if (blocks > 0x7FFFFFFFull) return fail(CC_EINVAL, "edge count too large for one launch");
     const bool zr = flags & CC_F_ZROOT;
-    const bool split = !(flags & CC_F_NO_SPLIT);
     const uint32_t sym = (flags & CC_F_SYMMETRIC) ? 1u : 0u;
     if (zr && (!s->zr_ready || s->cur_n != n))
         return fail(CC_EINVAL, "a CC_F_ZROOT hook needs cc_init then cc_zroot on the same n");
-    if (split && !(flags & CC_F_NO_TILE) && !s->no_tiled && tiled_eligible(n, m))
+    if (!(flags & (CC_F_NO_SPLIT | CC_F_NO_TILE)) && !s->no_tiled && tiled_eligible(n, m))
         return run_hook_tiled(s, n, m, edges, P, stream, /*plain=*/!zr, sym != 0);
+    const bool split = split_walks(flags, n);
     const uint32_t n32 = (uint32_t)n;
     uint32_t* zb = s->zbits;
     const uint32_t g = (uint32_t)blocks;
-    if (!zr && n <= kOneXcdMaxN && m >= kOneXcdMinM && !(flags & CC_F_NO_TILE)) {
-        // plain path, parent array of at most 1 MB, enough entries to keep one XCD
-        // busy (32 CUs, 8 workgroups each): measured 2-3x faster than spreading
-        // the hot array over eight L2s (the zero-root hook gains nothing: its
-        // bitmap tests drop most entries before they touch P)
-        const uint32_t gx = kXcds * (uint32_t)std::min<uint64_t>(blocks, 256);
-        if (split) k_hook_xcd<false, 1><<<gx, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st, sym);
-        else k_hook_xcd<false, 0><<<gx, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st, sym);
-        CCM_HIP(hipGetLastError());
-        return CC_OK;
-    }
     if (zr && split) k_hook<true, 1><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st, sym);
     else if (zr) k_hook<true, 0><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st, sym);
     else if (split) k_hook<false, 1><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st, sym);
@@ -948,7 +916,7 @@ int run_hook_log(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_
     const uint32_t g = (uint32_t)blocks;
     auto* cnt = reinterpret_cast<unsigned long long*>(log_count);
     const uint32_t sym = (flags & CC_F_SYMMETRIC) ? 1u : 0u;
-    if (flags & CC_F_NO_SPLIT)
+    if (!split_walks(flags, n))
         k_hook<false, 0, true><<<g, kBlock, 0, stream>>>(edges, m, (uint32_t)n, P, nullptr, s->st,
                                                          sym, log, log_cap, cnt);
     else
@@ -1009,7 +977,7 @@ __global__ __launch_bounds__(kBlock) void k_hook_ids(const uint32_t* __restrict_
 int run_hook_ids(Slot* s, uint64_t n, uint64_t count, const uint32_t* ids, uint32_t target,
                  uint32_t* P, uint32_t flags, hipStream_t stream) {
     const bool zr = flags & CC_F_ZROOT;
-    const bool split = !(flags & CC_F_NO_SPLIT);
+    const bool split = split_walks(flags, n);
     if (zr && (!s->zr_ready || s->cur_n != n))
         return fail(CC_EINVAL, "a CC_F_ZROOT id hook needs cc_init then cc_zroot on the same n");
     const uint32_t g = grid_for(count, kBlock, kGridCap);
@@ -1033,7 +1001,7 @@ int run_solve_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, const ui
     if (n == 0) return CC_OK;
     int rc;
     const bool zr = flags & CC_F_ZROOT;
-    const bool split = !(flags & CC_F_NO_SPLIT);
+    const bool split = split_walks(flags, n);
     const uint32_t sym = (flags & CC_F_SYMMETRIC) ? 1u : 0u;
     const uint64_t ntiles = (m + kCsrTile - 1) / kCsrTile;
     if (ntiles > 0x7FFFFFFFull) return fail(CC_EINVAL, "entry count too large for one launch");
@@ -1069,7 +1037,7 @@ int run_solve_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, const ui
         CCM_HIP(hipGetLastError());
     }
     if ((rc = cohere(stream))) return rc;
-    if (zr && split && !(flags & CC_F_NO_TILE) && tiled_eligible(n, m)) {
+    if (zr && !(flags & (CC_F_NO_SPLIT | CC_F_NO_TILE)) && tiled_eligible(n, m)) {
         // as on COO input: a warm-up over the first 1/1024 of the tiles seeds the
         // bitmap, then the regrouped hook covers every position (the warm-up's
         // entries again too, which finds them joined)
@@ -1081,17 +1049,6 @@ int run_solve_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, const ui
             CCM_HIP(hipGetLastError());
         }
         if ((rc = run_hook_tiled_csr(s, n, m, off, adj, L, stream, sym != 0))) return rc;
-    } else if (ntiles && !zr && n <= kOneXcdMaxN && m >= kOneXcdMinM && !(flags & CC_F_NO_TILE)) {
-        // plain hook of a small parent array: one XCD (see k_hook_xcd)
-        const uint32_t gx = kXcds * (uint32_t)std::min<uint64_t>(ntiles, 256);
-        const uint32_t n32 = (uint32_t)n;
-        if (split)
-            k_csr_hook<false, 1, true><<<gx, kBlock, 0, stream>>>(off, adj, n32, m, s->csr_tiles, ntiles,
-                                                                 L, s->zbits, s->st, sym);
-        else
-            k_csr_hook<false, 0, true><<<gx, kBlock, 0, stream>>>(off, adj, n32, m, s->csr_tiles, ntiles,
-                                                                 L, s->zbits, s->st, sym);
-        CCM_HIP(hipGetLastError());
     } else if (ntiles) {
         const uint32_t g = (uint32_t)ntiles;
         const uint32_t n32 = (uint32_t)n;

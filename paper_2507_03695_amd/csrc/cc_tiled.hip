@@ -73,8 +73,9 @@ __device__ __forceinline__ bool t_key_less(uint32_t a, uint32_t b, uint32_t z) {
     return (a == z) | ((b != z) & (a < b));
 }
 
-// Root of x with path splitting; device-coherent splitting stores, each issued
-// after the next step's load (as in the plain hook).
+// Root of x with path splitting: device-coherent splitting stores, each issued
+// after the next step's load (the rule and its reasons are those of
+// cc_kernels.hip's find_root).
 __device__ __forceinline__ uint32_t t_find(uint32_t* P, uint32_t x, uint32_t px) {
     if (px == x) return x;
     uint32_t gp = P[px];
@@ -99,6 +100,14 @@ __device__ __forceinline__ uint32_t t_link(uint32_t* P, uint32_t u, uint32_t pu,
         const uint32_t hi = u_low ? rv : ru;
         const uint32_t lo = u_low ? ru : rv;
         stress_delay(hi);
+        // a coherent read before the CAS, as in cc_kernels.hip's link: a root
+        // seen through a stale L2 copy is not CASed
+        const uint32_t cur = ld_agent(&P[hi]);
+        if (cur != hi) {
+            u = hi; pu = cur;
+            v = lo; pv = lo;
+            continue;
+        }
         const uint32_t old = atomicCAS(&P[hi], hi, lo);
         if (old == hi) return lo;
         u = hi; pu = old;

@@ -28,6 +28,8 @@ __global__ __launch_bounds__(kWBlock) void k_init_w(uint64_t* __restrict__ P, ui
         st_agent_w(&P[v], v);
 }
 
+// Root of x; SPLIT: path splitting with device-coherent stores (the rule of
+// cc_kernels.hip's find_root).
 template <int SPLIT>
 __device__ __forceinline__ uint64_t find_w(uint64_t* P, uint64_t x, uint64_t px) {
     if (px == x) return x;
@@ -91,6 +93,13 @@ __global__ __launch_bounds__(kWBlock) void k_hook_w(const uint64_t* __restrict__
             const uint64_t hi = ra < rb ? rb : ra;
             const uint64_t lo = ra < rb ? ra : rb;
             stress_delay((uint32_t)hi);
+            // a coherent read before the CAS, as in cc_kernels.hip's link
+            const uint64_t cur = __hip_atomic_load(&P[hi], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (cur != hi) {
+                a = hi; pa = cur;
+                b = lo; pb = lo;
+                continue;
+            }
             const uint64_t old = atomicCAS((unsigned long long*)&P[hi], (unsigned long long)hi,
                                            (unsigned long long)lo);
             if (old == hi) break;
@@ -134,7 +143,7 @@ int run_solve_w(Slot* s, uint64_t n, uint64_t m, const uint64_t* edges, uint64_t
     CCM_HIP(hipGetLastError());
     if ((rc = cohere(stream))) return rc;
     if (tiles) {
-        if (flags & CC_F_NO_SPLIT)
+        if (!split_walks(flags, n, sizeof(uint64_t)))
             k_hook_w<0><<<(uint32_t)tiles, kWBlock, 0, stream>>>(edges, m, n, L, s->st, sym);
         else
             k_hook_w<1><<<(uint32_t)tiles, kWBlock, 0, stream>>>(edges, m, n, L, s->st, sym);

@@ -1,9 +1,10 @@
 """Parity under injected delays, run in a child process whose CCMI_LIBRARY is the
 race-testing build (libccmi_stress.so: every link CAS and path-splitting store
 is preceded by a varying pause of its wave). Every solve, each on the entries
-in a new seeded order, must give the oracle's labels; the direct, regrouped and
-one-XCD hooks, the 64-bit path and the batched launch (parent arrays in LDS and
-in HBM) are all exercised. Exit status 0 when every
+in a new seeded order, must give the oracle's labels; the direct hooks (with
+path splitting above 4 MB of parent array, without it below), the regrouped
+hooks, the 64-bit path and the batched launch (parent arrays in LDS and in HBM)
+are all exercised. Exit status 0 when every
 solve agrees. Started by tests/test_gpu_stress_delays.py; with --full it also
 solves the bench's R-MAT-26 + extras workload (about a minute more)."""
 import os
@@ -27,7 +28,8 @@ def main(full: bool = False) -> int:
         cases.append(("rmat26_extras", g.n, g.edges, 1))
     cases += [
         ("er_2^14", 1 << 14, graphgen.er(1 << 14, 1 << 16, 301), 4),
-        ("rmat_2^16", 1 << 16, graphgen.rmat(16, 1 << 20, 302), 3),   # one-XCD plain hook
+        ("rmat_2^16", 1 << 16, graphgen.rmat(16, 1 << 20, 302), 3),   # small array: no splitting
+        ("rmat_2^21", 1 << 21, graphgen.rmat(21, 1 << 22, 304), 2),   # direct hooks split
         ("rmat_2^20_2^24", 1 << 20, graphgen.rmat(20, 1 << 24, 303), 2),  # regrouped hooks
     ]
     flagsets = {"plain": 0, "plain_nosplit": cc.F_NO_SPLIT, "plain_direct": cc.F_NO_TILE,

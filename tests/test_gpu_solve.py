@@ -115,11 +115,11 @@ def test_errors(ctx):
 def test_symmetric_flag(ctx):
     """CC_F_SYMMETRIC hooks only the u < v entries of a list that holds every pair
     in both orders: the labels equal the oracle's on the whole list, through the
-    direct, one-XCD and regrouped hooks (sizes on both sides of their limits) and
+    direct and regrouped hooks (sizes on both sides of their limits) and
     the CSR and 64-bit paths. On a list that is not symmetric the labels are
     those of its u < v entries alone (the flag's definition)."""
     cases = [(graphgen.rmat_sym(12, 20_000, 3), 1 << 12),          # direct hook
-             (graphgen.rmat_sym(17, 1 << 18, 4), 1 << 17),         # one-XCD plain hook
+             (graphgen.rmat_sym(17, 1 << 18, 4), 1 << 17),         # small array, dense
              (graphgen.rmat_sym(20, 1 << 23, 5), 1 << 20)]         # regrouped hooks
     for e, n in cases:
         want = oracle.cc_labels(n, e)
@@ -507,10 +507,11 @@ def test_labels_read_back_by_the_next_kernel():
 
 
 @pytest.mark.parametrize("case", ["er_16", "er_18", "rmat_17"])
-def test_small_array_one_xcd_hook(case):
-    """The plain hook on small parent arrays (n <= 2^18, m >= 2^18) runs on one XCD;
-    with and without splitting, ragged entry counts, it equals the oracle and the
-    spread launch (CC_F_NO_TILE)."""
+def test_small_array_hook(case):
+    """Small parent arrays with many entries per vertex (the case where walks end
+    at roots read through stale L2 copies and the check before each CAS matters),
+    ragged entry counts: with and without splitting, plain and zero-root, every
+    solve equals the oracle."""
     if case == "er_16":
         n, e = 1 << 16, graphgen.er(1 << 16, (1 << 18) + 123, 121)
     elif case == "er_18":
@@ -520,6 +521,6 @@ def test_small_array_one_xcd_hook(case):
     want = oracle.cc_labels(n, e)
     ed = to_dev(e)
     with cc.Context() as c:
-        for fl in (0, cc.F_NO_SPLIT, cc.F_NO_TILE):
+        for fl in (0, cc.F_NO_SPLIT, cc.F_NO_TILE, cc.F_ZROOT, cc.F_ZROOT | cc.F_NO_SPLIT):
             L = c.solve(ed, n, flags=fl)
             assert_same_labels(to_host_u32(L), want, f"{case} flags {fl:#x}")
