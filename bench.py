@@ -151,6 +151,47 @@ def bench_single(cc, torch, ed, n, m, steps, warmup, flags):
     return total_ms / steps, float(np.mean(hook_ms)), L
 
 
+def bench_small(cc, torch, name, steps=40, warmup=5):
+    """A configuration below the headline's size, plain path as the workload names
+    it: the whole path (one cc_solve_async per step, steps back to back on one
+    stream, HIP events around them) and the hook launch alone (events around
+    cc_hook in a step-wise solve), each against the HBM roofline of its
+    algorithmic bytes (whole path: 8 B per entry read, 12 B per vertex for init,
+    compress and the label write; hook: 8 B per entry)."""
+    edges, n, cfg = make_workload(name)
+    m = len(edges)
+    ed = torch.from_numpy(edges.view(np.int32)).cuda()
+    flags = cc.F_SYMMETRIC if name == "rmat22" else 0
+    ctx = cc.Context()
+    stream = torch.cuda.current_stream()
+    L = torch.empty(n, dtype=torch.int32, device="cuda")
+    for _ in range(warmup):
+        ctx.solve_async(ed, n, L, flags=flags, stream=stream)
+    assert ctx.sync(stream) == cc.CC_OK
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(steps):
+        ctx.solve_async(ed, n, L, flags=flags, stream=stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    assert ctx.sync(stream) == cc.CC_OK
+    ctx.close()
+    _, hook_ms, L2 = bench_single(cc, torch, ed, n, m, max(5, steps // 4), 2, flags)
+    same = bool(torch.equal(L, L2))
+    whole = (8 * m + 12 * n) / (ms * 1e-3) / 1e9
+    hook = 8 * m / (hook_ms * 1e-3) / 1e9
+    return {"workload": cfg["workload"], "n": n, "m": m,
+            "flags": "CC_F_SYMMETRIC" if flags else "plain",
+            "ms_per_solve": round(ms, 4), "GTEPS": round(m / (ms * 1e-3) / 1e9, 3),
+            "whole_path_GBps": round(whole, 1),
+            "whole_path_roofline_frac": round(whole / PEAK_HBM_GBS, 4),
+            "hook_ms": round(hook_ms, 4), "hook_GBps": round(hook, 1),
+            "hook_roofline_frac": round(hook / PEAK_HBM_GBS, 4),
+            "identical_labels_step_vs_whole": same}
+
+
 def _time_batch(ctx, torch, vo, eo, ed, L, st, reps, sched=None):
     ts = []
     for _ in range(reps):
@@ -616,8 +657,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip every section after the headline and the other variant")
     ap.add_argument("--only", default=None,
-                    choices=["reducer", "update_log", "csr", "u64_ids", "share_rmat30", "batch",
-                             "batch_tail", "serve"],
+                    choices=["small_configs", "reducer", "update_log", "csr", "u64_ids",
+                             "share_rmat30", "batch", "batch_tail", "serve"],
                     help="run just this one further section (for profiling it)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 4 GiB device copy (reference for HBM byte counters)")
@@ -723,6 +764,10 @@ def main():
         line["u64_ids"] = u64
     del ed, L
     torch.cuda.empty_cache()
+    if want("small_configs"):
+        t1 = time.time()
+        line["small_configs"] = {w: bench_small(cc, torch, w) for w in ("er65k", "rmat22")}
+        log(f"small configurations done in {time.time() - t1:.1f} s")
     if want("share_rmat30"):
         t1 = time.time()
         line["share_rmat30"] = bench_share30(cc, torch)

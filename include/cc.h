@@ -70,11 +70,15 @@ int cc_version(void);
 #define CC_F_ZROOT_EXACT  0x2u
 /* With CC_F_ZROOT: the zero root is `zroot_hint` (must be < n).            */
 #define CC_F_ZROOT_HINT   0x4u
-/* Plain root walks without path splitting (Algorithm 1's finds as printed). */
+/* Plain root walks without path splitting (Algorithm 1's finds as printed)
+   everywhere. Without the flag the regrouped hooks and the batch's workgroup
+   role split paths, and the direct hooks split them where the parent array
+   exceeds 4 MB (one XCD's L2; below that the walks are L2 hits and the
+   splitting stores cost more than they save).                              */
 #define CC_F_NO_SPLIT     0x8u
 /* Keep the direct hook, which takes the entries in their given order, where
-   the regrouped hooks would apply (2 <= ceil(n / 2^19) <= 256 and
-   2^24 <= m < 2^32, path splitting on). With CC_F_ZROOT the regrouped hook
+   the regrouped hooks would apply (4 <= ceil(n / 2^19) <= 256, or 8 <= with
+   CC_F_ZROOT, and 2^24 <= m < 2^32, without CC_F_NO_SPLIT). With CC_F_ZROOT the regrouped hook
    sorts the entries by the vertex ranges of both endpoints so that both
    membership tests read LDS; without it, the plain hook takes the entries
    grouped by their first endpoint's range, so that those parent reads stay in

@@ -172,8 +172,8 @@ __device__ __forceinline__ bool solve_graph16(uint32_t* P32, uint32_t n, gedge_t
 
 // Root of x; with split, path splitting (each visited vertex takes its
 // grandparent) with device-coherent stores (the rule of cc_kernels.hip's
-// find_root), used where the graph's parent array outgrows one XCD's L2
-// (split_walks).
+// find_root): the whole-device role splits where the graph's parent array
+// outgrows one XCD's L2 (split_walks), the tile role always.
 __device__ __forceinline__ uint32_t bfind(glabel_t* P, uint32_t x, uint32_t px, bool split) {
     while (px != x) {
         const uint32_t gp = P[px];
@@ -222,10 +222,9 @@ __device__ __forceinline__ void blink(glabel_t* P, uint32_t u, uint32_t pu, uint
 // this thread saw an endpoint out of range.
 template <int T>
 __device__ __forceinline__ bool hook_hbm(glabel_t* P, uint32_t n, gedge_t* E, int64_t first,
-                                         int64_t end, int idx) {
+                                         int64_t end, int idx, bool split) {
     bool bad = false;
     if (first >= end) return bad;
-    const bool split = split_walks(0, n);
     constexpr int64_t kRound = (int64_t)T * kBatchEPT;
     i32x2 x[kBatchEPT];
 #pragma unroll
@@ -262,7 +261,9 @@ __device__ __forceinline__ void solve_graph_hbm(glabel_t* P, uint32_t n, gedge_t
     for (uint32_t v = tid; v < n; v += kBatchBlock) gstore(&P[v], v);
     __threadfence_block();
     __syncthreads();
-    if (hook_hbm<kBatchBlock>(P, n, E, 0, m, tid)) *bad_flag = 1;
+    // one workgroup's walks: without splitting its trees grow deep (R-MAT
+    // n = 2^20, 2^23 entries: 117 ms against 28 ms), so it always splits
+    if (hook_hbm<kBatchBlock>(P, n, E, 0, m, tid, true)) *bad_flag = 1;
     __threadfence_block();
     __syncthreads();
     // Links are CASes performed at the memory side, which leave this XCD's L2
@@ -382,7 +383,7 @@ __global__ __launch_bounds__(kMultiBlock) void k_bm_hook(const GraphDesc* __rest
         gedge_t* E = (gedge_t*)d.edges;
         const int64_t e0 = (int64_t)(b - epre[k]) * (int64_t)kMultiEChunk;
         const int64_t e1 = std::min<int64_t>(e0 + (int64_t)kMultiEChunk, d.m);
-        const bool bad = hook_hbm<kMultiBlock>(P, d.n, E, e0, e1, threadIdx.x);
+        const bool bad = hook_hbm<kMultiBlock>(P, d.n, E, e0, e1, threadIdx.x, split_walks(0, d.n));
         if (bad) gstore((glabel_t*)d.status, (uint32_t)CC_ERANGE);
     }
 }

@@ -156,7 +156,7 @@ int zbits_reset(Slot* s, uint64_t n, hipStream_t stream);
 int slot_sync(Slot* s, hipStream_t stream);
 
 // Tiled zero-root hook (cc_tiled.hip): both membership tests in LDS.
-bool tiled_eligible(uint64_t n, uint64_t m);
+bool tiled_eligible(uint64_t n, uint64_t m, bool zr);
 // Bytes of the regrouped hook's buffers for n vertices and m COO entries.
 uint64_t tiled_scratch_bytes(uint64_t n, uint64_t m, bool plain);
 // Device bytes a whole-path solve (run_solve) grows in its slot for these

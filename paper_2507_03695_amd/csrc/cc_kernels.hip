@@ -276,8 +276,14 @@ __device__ __forceinline__ bool zbit(const uint32_t* zbits, uint32_t x) {
     return (zbits[x >> 5] >> (x & 31)) & 1u;
 }
 
+// Sets x's bit. The word is read coherently first and the atomic (performed at
+// the memory side, where the atomics on one word wait for each other) is issued
+// only if the bit is still clear: most of a giant component's members are
+// reached by many entries, and their word would otherwise take an atomic for
+// each (bits only go from 0 to 1, so a set bit read anywhere stays set).
 __device__ __forceinline__ void zbit_set(uint32_t* zbits, uint32_t x) {
-    atomicOr(&zbits[x >> 5], 1u << (x & 31));
+    const uint32_t b = 1u << (x & 31);
+    if (!(ld_agent(&zbits[x >> 5]) & b)) atomicOr(&zbits[x >> 5], b);
 }
 
 constexpr int kEPT = 4;  // entries per thread per tile
@@ -677,7 +683,7 @@ __global__ __launch_bounds__(kBlock) void k_compress(uint32_t* P, uint64_t n, De
             if (ZR && r == z) {
                 local_min = min(local_min, (uint32_t)v);
             } else if (marked) {
-                atomicOr(&zbits[r >> 5], 1u << (r & 31));
+                zbit_set(zbits, r);
                 local_min = min(local_min, r);
             }
         }
@@ -890,7 +896,7 @@ int run_hook(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P
     const uint32_t sym = (flags & CC_F_SYMMETRIC) ? 1u : 0u;
     if (zr && (!s->zr_ready || s->cur_n != n))
         return fail(CC_EINVAL, "a CC_F_ZROOT hook needs cc_init then cc_zroot on the same n");
-    if (!(flags & (CC_F_NO_SPLIT | CC_F_NO_TILE)) && !s->no_tiled && tiled_eligible(n, m))
+    if (!(flags & (CC_F_NO_SPLIT | CC_F_NO_TILE)) && !s->no_tiled && tiled_eligible(n, m, zr))
         return run_hook_tiled(s, n, m, edges, P, stream, /*plain=*/!zr, sym != 0);
     const bool split = split_walks(flags, n);
     const uint32_t n32 = (uint32_t)n;
@@ -1037,7 +1043,7 @@ int run_solve_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, const ui
         CCM_HIP(hipGetLastError());
     }
     if ((rc = cohere(stream))) return rc;
-    if (zr && !(flags & (CC_F_NO_SPLIT | CC_F_NO_TILE)) && tiled_eligible(n, m)) {
+    if (zr && !(flags & (CC_F_NO_SPLIT | CC_F_NO_TILE)) && tiled_eligible(n, m, true)) {
         // as on COO input: a warm-up over the first 1/1024 of the tiles seeds the
         // bitmap, then the regrouped hook covers every position (the warm-up's
         // entries again too, which finds them joined)
@@ -1071,7 +1077,7 @@ uint64_t solve_scratch_bytes(uint64_t n, uint64_t m, uint32_t flags) {
     uint64_t b = 0;
     if (zr) b += al256(4 * ((n + 31) / 32));
     if (zr && (flags & CC_F_ZROOT_EXACT)) b += al256(4 * n);
-    if (m && !(flags & (CC_F_NO_SPLIT | CC_F_NO_TILE)) && tiled_eligible(n, m))
+    if (m && !(flags & (CC_F_NO_SPLIT | CC_F_NO_TILE)) && tiled_eligible(n, m, zr))
         b += al256(tiled_scratch_bytes(n, m, !zr));
     return b;
 }
@@ -1101,7 +1107,7 @@ void slot_lend_scratch(Slot* s, char* block, uint64_t n, uint64_t m, uint32_t fl
         s->deg_cap = n;
         q += al256(4 * n);
     }
-    if (m && !(flags & (CC_F_NO_SPLIT | CC_F_NO_TILE)) && tiled_eligible(n, m)) {
+    if (m && !(flags & (CC_F_NO_SPLIT | CC_F_NO_TILE)) && tiled_eligible(n, m, zr)) {
         s->tiled.buf = q;
         s->tiled.cap = tiled_scratch_bytes(n, m, !zr);
     }

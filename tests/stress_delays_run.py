@@ -30,7 +30,7 @@ def main(full: bool = False) -> int:
         ("er_2^14", 1 << 14, graphgen.er(1 << 14, 1 << 16, 301), 4),
         ("rmat_2^16", 1 << 16, graphgen.rmat(16, 1 << 20, 302), 3),   # small array: no splitting
         ("rmat_2^21", 1 << 21, graphgen.rmat(21, 1 << 22, 304), 2),   # direct hooks split
-        ("rmat_2^20_2^24", 1 << 20, graphgen.rmat(20, 1 << 24, 303), 2),  # regrouped hooks
+        ("rmat_2^22_2^24", 1 << 22, graphgen.rmat(22, 1 << 24, 303), 2),  # regrouped hooks
     ]
     flagsets = {"plain": 0, "plain_nosplit": cc.F_NO_SPLIT, "plain_direct": cc.F_NO_TILE,
                 "zroot": cc.F_ZROOT, "zroot_direct": cc.F_ZROOT | cc.F_NO_TILE}

@@ -125,10 +125,10 @@ def test_csr_matches_coo_on_a_large_graph():
 
 
 def test_csr_regrouped_zero_root_path():
-    """R-MAT-21 + extras (about 2^25 entries, five vertex slices): the regrouped
+    """R-MAT-22 + extras (about 2^25 entries, nine vertex slices): the regrouped
     zero-root hook on CSR rows, the direct one (CC_F_NO_TILE) and the oracle
     agree; the rows include the empty block and the appended paths."""
-    g = graphgen.rmat_extras(21, 16, 108, n_paths=2000)
+    g = graphgen.rmat_extras(22, 8, 108, n_paths=2000)
     n, e = g.n, g.edges
     want = oracle.cc_labels(n, e)
     log(f"n={n} m={len(e)}: oracle done")

@@ -233,15 +233,15 @@ def test_zero_root_choice_does_not_change_labels(ctx, size):
     """Variant Z: any vertex may be the zero root (the max-degree choice only
     saves work, Sec. IV), so forcing it through the hint leaves the labels
     equal to the oracle's: z = 0, n - 1, the true max-degree vertex, a random
-    vertex and an isolated one. "regrouped": 2^24 entries over two vertex
-    slices, the size at which the zero-root hook regroups its entries; with
+    vertex and an isolated one. "regrouped": 2^24 entries over eight vertex
+    slices, the size from which the zero-root hook regroups its entries; with
     CC_F_NO_SPLIT it takes the direct hook instead."""
     if size == "direct":
         n = 50_000
         e = graphgen.rmat(16, 400_000, 61) % n
     else:
-        n = 1 << 20
-        e = graphgen.rmat(20, 1 << 24, 62)
+        n = 1 << 22
+        e = graphgen.rmat(22, 1 << 24, 62)
     want = oracle.cc_labels(n, e)
     deg = np.bincount(e.ravel(), minlength=n)
     iso = np.flatnonzero(deg == 0)
@@ -416,7 +416,8 @@ def test_rmat26_extras_full():
 
 # ---- the tiled zero-root hook (entries regrouped by both endpoints' vertex ranges) -------
 
-@pytest.mark.parametrize("case", ["er_R6", "rmat_unpermuted", "two_slices", "loops_dups", "R256"])
+@pytest.mark.parametrize("case", ["er_R6", "rmat_unpermuted", "four_slices", "eight_slices",
+                                  "loops_dups", "R256"])
 def test_tiled_hook_parity(case):
     rng = np.random.default_rng(hash(case) % 2**32)
     if case == "er_R6":
@@ -425,11 +426,14 @@ def test_tiled_hook_parity(case):
     elif case == "rmat_unpermuted":          # skewed: low slices hold most entries
         n = 1 << 22
         e = graphgen.rmat(22, (1 << 24) + 777, 62, permute=False)
-    elif case == "two_slices":
-        n = (1 << 19) + 1
+    elif case == "four_slices":                # the fewest the plain path regroups
+        n = 3 * (1 << 19) + 1
         e = graphgen.er(n, 1 << 24, 63)
+    elif case == "eight_slices":               # the fewest the zero-root path regroups
+        n = 7 * (1 << 19) + 1
+        e = graphgen.rmat(22, 1 << 24, 67) % n
     elif case == "loops_dups":
-        n = 2_000_000
+        n = 4_000_000
         e = graphgen.er(n, 1 << 24, 64)
         e[::7, 1] = e[::7, 0]                  # self-loops
         e[1::11] = e[0:-1:11][: len(e[1::11])]  # repeats
@@ -446,7 +450,7 @@ def test_tiled_hook_parity(case):
 
 
 def test_tiled_hook_out_of_range():
-    n = 1 << 21
+    n = 1 << 22
     e = graphgen.er(n, 1 << 24, 66)
     e[12345] = (n + 5, 3)
     with cc.Context() as c:
