@@ -390,9 +390,15 @@ def bench_reducer(cc, torch, ed, n, L_ref, g=16, reps=3):
             "reducer_ms": round(med(2), 3), "identical_labels": same}
 
 
-def bench_serve(cc, torch, count=2000, seed=0x2507036950000005):
-    """Poisson stream of requests (Pareto n in [2^10, 2^24]) through cc_serve at an
-    offered load above a FIFO plain-path server's capacity; p50/p99 latency."""
+def bench_serve(cc, torch, count=3000, seed=0x2507036950000005):
+    """Poisson streams of requests (truncated Pareto n in [2^10, 2^24], edgefactor
+    8-32, R-MAT/ER) through cc_serve and through a FIFO plain-path server (one
+    stream, no batching, one request in flight) at the same offered rates:
+    rho = 0.5, 0.9 and 1.2 of the FIFO server's capacity, and 1.25 of the
+    server's own. Capacities are whole streams submitted at once. At rho = 0.9
+    the R-MAT-30 share (one machine's 1/16 vertex range with the global 2^30
+    parent array) is submitted in the middle of the stream. p50/p99 latency from
+    submission to labels in host memory."""
     import graphgen
     reqs = graphgen.serve_stream(count, seed, rate_per_s=1.0)
     data = []
@@ -400,41 +406,74 @@ def bench_serve(cc, torch, count=2000, seed=0x2507036950000005):
         e = np.ascontiguousarray(r.edges().view(np.uint32).reshape(-1, 2))
         data.append((e, r.n))
 
-    def run(srv_kwargs, rate):
+    def run(srv_kwargs, rate, share=None):
         ctx = cc.Context()
         srv = cc.Server(ctx, **srv_kwargs)
         outs = [np.empty(n, np.uint32) for _, n in data]
         tickets = []
+        t_share = None
         t0 = time.perf_counter()
         for i, ((e, n), r) in enumerate(zip(data, reqs)):
             due = t0 + r.arrival_s / rate
             while time.perf_counter() < due:
                 pass
+            if share is not None and i == count // 2:
+                t_share = srv.submit(share[0], share[1], share[2], flags=cc.F_ZROOT)
             tickets.append(srv.submit(e, n, outs[i]))
-        lat = []
+        lat, first, last = [], None, 0
         for t in tickets:
             rc, s = srv.wait(t)
             assert rc == cc.CC_OK, rc
             lat.append((s.t_done_ns - s.t_submit_ns) / 1e6)
-        wall = time.perf_counter() - t0
+            first = s.t_submit_ns if first is None else min(first, s.t_submit_ns)
+            last = max(last, s.t_done_ns)
+        share_ms = None
+        if t_share is not None:
+            rc, s = srv.wait(t_share)
+            assert rc == cc.CC_OK, rc
+            share_ms = (s.t_done_ns - s.t_submit_ns) / 1e6
         srv.close()
         ctx.close()
-        return outs, np.array(lat), wall
+        lat = np.array(lat)
+        # the stream's own requests over their own span (first submission to last
+        # labels in host memory), the share excluded
+        return outs, {"served_graphs_per_s": round(count / ((last - first) * 1e-9), 1),
+                      "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                      "p99_ms": round(float(np.percentile(lat, 99)), 3)}, share_ms
 
-    # capacity of a FIFO plain-path server: one stream, no batching, back to back
-    outs_fifo, lat_fifo, wall_fifo = run({"streams": 1, "small_n": 1, "max_inflight": 1}, 1e9)
-    cap = count / wall_fifo
-    rate = 1.2 * cap
-    outs, lat, wall = run({"streams": 4}, rate)
-    same = all(np.array_equal(a, b) for a, b in zip(outs, outs_fifo))
-    return {"requests": count, "offered_rate_per_s": round(rate, 1),
-            "fifo_capacity_graphs_per_s": round(cap, 1),
-            "served_graphs_per_s": round(count / wall, 1),
-            "p50_ms": round(float(np.percentile(lat, 50)), 3),
-            "p99_ms": round(float(np.percentile(lat, 99)), 3),
-            "fifo_p50_ms_saturated": round(float(np.percentile(lat_fifo, 50)), 3),
-            "fifo_p99_ms_saturated": round(float(np.percentile(lat_fifo, 99)), 3),
-            "identical_to_fifo": same}
+    fifo = {"streams": 1, "small_n": 1, "max_inflight": 1}
+    served = {"streams": 4}
+    outs_fifo, st_fifo, _ = run(fifo, 1e12)
+    cap_fifo = st_fifo["served_graphs_per_s"]
+    outs_cap, st_cap, _ = run(served, 1e12)
+    cap_srv = st_cap["served_graphs_per_s"]
+    same = all(np.array_equal(a, b) for a, b in zip(outs_cap, outs_fifo))
+    # the share, generated on the device and held in host memory like any request
+    ed, n_share = graphgen.rmat30_share_dev()
+    e_share = ed.cpu().numpy().view(np.uint32)
+    del ed
+    torch.cuda.empty_cache()
+    L_share = np.empty(n_share, np.uint32)
+    loads = []
+    for rho, base in ((0.5, cap_fifo), (0.9, cap_fifo), (1.2, cap_fifo), (1.25, cap_srv)):
+        rate = rho * base
+        with_share = rho == 0.9 and base == cap_fifo
+        outs, st, share_ms = run(served, rate, (e_share, n_share, L_share) if with_share else None)
+        same = same and all(np.array_equal(a, b) for a, b in zip(outs, outs_fifo))
+        _, st_f, _ = run(fifo, rate)
+        entry = {"offered_per_s": round(rate, 1),
+                 "rho_of": "fifo_capacity" if base == cap_fifo else "server_capacity",
+                 "rho": rho, "server": st, "fifo": st_f}
+        if share_ms is not None:
+            entry["share_rmat30_in_stream_ms"] = round(share_ms, 1)
+        loads.append(entry)
+    return {"requests": count, "fifo_capacity_graphs_per_s": cap_fifo,
+            "server_capacity_graphs_per_s": cap_srv,
+            "server_p50_ms_at_capacity": st_cap["p50_ms"], "server_p99_ms_at_capacity": st_cap["p99_ms"],
+            "fifo_p50_ms_at_capacity": st_fifo["p50_ms"], "fifo_p99_ms_at_capacity": st_fifo["p99_ms"],
+            "loads": loads, "identical_to_fifo": same,
+            "share_rmat30": {"n": n_share, "m": int(len(e_share)), "flags": "CC_F_ZROOT",
+                             "submitted_at_request": count // 2}}
 
 
 def bench_update_log(cc, torch, ed, n, L_ref, g=16, reps=3):
