@@ -515,7 +515,35 @@ def bench_update_log(cc, torch, ed, n, L_ref, g=16, reps=3):
     ctx.compress(n, P, stream=stream)
     assert ctx.sync(stream) == cc.CC_OK
     same_single = bool(torch.equal(P, L_ref))
-    del buf
+    # the messages delivered to host memory: drained launch by launch while the
+    # pass runs (cc_hook_log_drain, 8 launches), against the logged hook followed
+    # by one copy of the whole log (the same pinned buffer); wall time of each
+    host = torch.empty((n, 2), dtype=torch.int32, pin_memory=True)
+    t_drain, t_after = [], []
+    for rep in range(reps + 1):
+        ctx.init(n, P, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k_drain = ctx.hook_log_drain(ed, n, P, buf, host, chunks=8, stream=stream)
+        t1 = time.perf_counter()
+        ctx.init(n, P, stream)
+        cnt.zero_()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        ctx.hook_log(ed, n, P, buf, cnt, stream=stream)
+        k_after = int(cnt.item())                       # waits for the hook
+        host[:k_after].copy_(buf[:k_after])
+        t3 = time.perf_counter()
+        assert k_drain == k_after == want, (k_drain, k_after, want)
+        if rep:
+            t_drain.append((t1 - t0) * 1e3)
+            t_after.append((t3 - t2) * 1e3)
+    assert ctx.sync(stream) == cc.CC_OK
+    drained = {"launches": 8, "messages": k_drain,
+               "drained_ms": round(float(np.median(t_drain)), 3),
+               "hook_then_copy_ms": round(float(np.median(t_after)), 3),
+               "message_bytes_to_host": 8 * k_drain}
+    del buf, host
     torch.cuda.empty_cache()
 
     u = ed[:, 0].to(torch.int64) & 0xFFFFFFFF
@@ -553,6 +581,7 @@ def bench_update_log(cc, torch, ed, n, L_ref, g=16, reps=3):
     return {"messages": want, "n_minus_components": want,
             "hook_log_ms": round(hl, 3), "hook_ms": round(hook_plain_ms, 3),
             "overhead": round(hl / hook_plain_ms - 1.0, 4), "identical_labels": same_single,
+            "drained_to_host": drained,
             "siskin_shares": g, "siskin_messages": res[-1][2],
             "siskin_bound_min_E_gV": min(m, g * n),
             "siskin_message_bytes": res[-1][2] * 2 * id_bytes,

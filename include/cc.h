@@ -299,6 +299,32 @@ int cc_hook_log(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edges, uint
                 uint32_t flags, uint32_t* log, uint64_t log_cap, uint64_t* log_count,
                 void* stream);
 
+/* cc_hook_log with the messages sent on while the pass runs (Sec. III:
+   SiskinCC sends its updates as it makes them, not after its pass). The entries
+   are hooked in `chunks` consecutive launches on `stream` (entries
+   [k*ceil(m/chunks), ...) in launch k), all enqueued at once; after each, the
+   messages that launch appended are copied, on the context's own copy stream,
+   from `log` into host_log while the later launches run (R-MAT-26, 8 launches:
+   the 265 MB of messages arrive 0.3 ms after the last launch ends, against
+   5 ms for one copy after a single logged launch).
+     log, log_cap    device, the messages as they are made (as cc_hook_log;
+                     log_cap >= n - 1 holds every message a solve can make)
+     host_log        host, 2*host_cap uint32, owned by the caller: message i is
+                     host_log[2i], host_log[2i+1] once the call returns. Pinned
+                     memory (hipHostMalloc, torch pin_memory) lets the copies
+                     overlap the launches; pageable memory works but does not
+     chunks          1..CC_DRAIN_MAX_CHUNKS
+     n_messages      host, out: the messages of this call (the context's own
+                     counter starts at 0)
+   Synchronous: returns when every message is in host_log. CC_ENOMEM when the
+   messages exceed min(log_cap, host_cap) (the first that many are delivered).
+   Other arguments and errors as for cc_hook_log (an endpoint >= n: the next
+   cc_sync returns CC_ERANGE). */
+#define CC_DRAIN_MAX_CHUNKS 1024
+int cc_hook_log_drain(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
+                      uint32_t flags, uint32_t* log, uint64_t log_cap, uint32_t* host_log,
+                      uint64_t host_cap, uint32_t chunks, uint64_t* n_messages, void* stream);
+
 /* Pointer jumping (Algorithm 1 / 3 final loop): P_v <- root of v for every
    v. On the plain path the result is the min-ID labelling. With CC_F_ZROOT
    (requires cc_init then cc_zroot on the same n, else CC_EINVAL) a tree that

@@ -30,6 +30,7 @@ CC_OK, CC_EINVAL, CC_ERANGE, CC_ENOMEM, CC_EDEVICE, CC_EAGAIN, CC_ECANCELED, CC_
 F_ZROOT, F_ZROOT_EXACT, F_ZROOT_HINT, F_NO_SPLIT, F_NO_TILE = 0x1, 0x2, 0x4, 0x8, 0x10
 F_CANON, F_SYMMETRIC = 0x20, 0x40
 STATUS_RING = 256
+DRAIN_MAX_CHUNKS = 1024
 NOALLOC_SCRATCH_BYTES = 16 << 20
 
 
@@ -121,6 +122,8 @@ SIGNATURES = {
     "cc_push": (_I32, [_P, _U64, _U64, _P, _P, _P]),
     "cc_hook": (_I32, [_P, _U64, _U64, _P, _P, _U32, _P]),
     "cc_hook_log": (_I32, [_P, _U64, _U64, _P, _P, _U32, _P, _U64, _P, _P]),
+    "cc_hook_log_drain": (_I32, [_P, _U64, _U64, _P, _P, _U32, _P, _U64, _P, _U64, _U32,
+                                 ctypes.POINTER(_U64), _P]),
     "cc_compress": (_I32, [_P, _U64, _P, _U32, _P]),
     "cc_canon": (_I32, [_P, _U64, _P, _P]),
     "cc_get_zroot": (_I32, [_P, _P, ctypes.POINTER(_U32)]),
@@ -345,6 +348,21 @@ class Context:
         _check(self.lib.cc_hook_log(self._h, n, edges.shape[0], _dptr(edges, _ID), _dptr(P, _ID),
                                     flags, _dptr(log, _ID), 0 if log is None else log.shape[0],
                                     _dptr(count, (torch.int64,)), _stream(stream)), "cc_hook_log")
+
+    def hook_log_drain(self, edges, n, P, log, host_log, chunks=8, flags=0, stream=None):
+        """cc_hook_log_drain: log (cap, 2) device tensor of P's dtype; host_log a
+        (cap, 2) CPU tensor (pinned for overlap) of the same dtype, filled; returns
+        the number of messages."""
+        if host_log.device.type != "cpu" or host_log.dtype != log.dtype:
+            raise TypeError("host_log must be a CPU tensor of the log's dtype")
+        if not host_log.is_contiguous():
+            raise ValueError("host_log must be contiguous")
+        out = ctypes.c_uint64(0)
+        rc = self.lib.cc_hook_log_drain(self._h, n, edges.shape[0], _dptr(edges, _ID), _dptr(P, _ID),
+                                        flags, _dptr(log, _ID), log.shape[0], host_log.data_ptr(),
+                                        host_log.shape[0], chunks, ctypes.byref(out), _stream(stream))
+        _check(rc, "cc_hook_log_drain")
+        return int(out.value)
 
     def compress(self, n, P, flags=0, stream=None):
         _check(self.lib.cc_compress(self._h, n, _dptr(P, _ID), flags, _stream(stream)), "cc_compress")

@@ -30,6 +30,12 @@ struct cc_ctx {
     uint64_t st_seq = 0;
     // batch schedules: forced one, stored picks, the cache file
     ccm::Tuner tuner;
+    // cc_hook_log_drain: the copy stream, per-launch events and pinned counter
+    // snapshots (created on first use)
+    std::mutex dr_mu;
+    hipStream_t dr_stream = nullptr;
+    hipEvent_t dr_ev[CC_DRAIN_MAX_CHUNKS] = {};
+    uint64_t* dr_counts = nullptr;
 };
 
 namespace ccm {
@@ -217,6 +223,10 @@ extern "C" void cc_destroy(cc_ctx* ctx) {
     for (auto& e : ctx->st_ev)
         if (e) (void)hipEventDestroy(e);
     if (ctx->st_ring) (void)hipHostFree(ctx->st_ring);
+    for (auto& e : ctx->dr_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->dr_counts) (void)hipHostFree(ctx->dr_counts);
+    if (ctx->dr_stream) (void)hipStreamDestroy(ctx->dr_stream);
     delete ctx;
 }
 
@@ -473,6 +483,87 @@ extern "C" int cc_hook_log(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* 
                            (hipStream_t)stream)))
         return rc;
     return cohere((hipStream_t)stream);
+}
+
+// The context's drain resources, created on first use (caller holds dr_mu).
+static int drain_setup(cc_ctx* ctx, uint32_t chunks) {
+    if (!ctx->dr_stream) {
+        hipStream_t s = nullptr;
+        CCM_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        ctx->dr_stream = s;
+    }
+    if (!ctx->dr_counts) {
+        void* p = nullptr;
+        if (hipHostMalloc(&p, sizeof(uint64_t) * CC_DRAIN_MAX_CHUNKS, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CC_ENOMEM, "pinned drain counters");
+        }
+        ctx->dr_counts = static_cast<uint64_t*>(p);
+    }
+    for (uint32_t k = 0; k < chunks; ++k)
+        if (!ctx->dr_ev[k]) CCM_HIP(hipEventCreateWithFlags(&ctx->dr_ev[k], hipEventDisableTiming));
+    return CC_OK;
+}
+
+extern "C" int cc_hook_log_drain(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edges,
+                                 uint32_t* P, uint32_t flags, uint32_t* log, uint64_t log_cap,
+                                 uint32_t* host_log, uint64_t host_cap, uint32_t chunks,
+                                 uint64_t* n_messages, void* stream) {
+    if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    if (!n_messages) return fail(CC_EINVAL, "n_messages is NULL");
+    *n_messages = 0;
+    int rc = check_graph(n, m, edges, P);
+    if (rc || n == 0) return rc;
+    if (chunks == 0 || chunks > CC_DRAIN_MAX_CHUNKS) return fail(CC_EINVAL, "chunks must be in 1..1024");
+    if (log_cap && !log) return fail(CC_EINVAL, "log is NULL with a nonzero capacity");
+    if (host_cap && !host_log) return fail(CC_EINVAL, "host_log is NULL with a nonzero capacity");
+    if (flags & CC_F_ZROOT)
+        return fail(CC_EINVAL, "the update log is defined for the plain path (no CC_F_ZROOT)");
+    if ((rc = set_dev(ctx))) return rc;
+    std::lock_guard<std::mutex> lk(ctx->dr_mu);
+    if ((rc = drain_setup(ctx, chunks))) return rc;
+    hipStream_t hs = (hipStream_t)stream;
+    Slot* s = &ctx->slot;
+    uint64_t* hc = ctx->dr_counts;
+    // every launch is enqueued first, so the device never waits for the host
+    if ((rc = cohere(hs))) return rc;
+    if ((rc = log_count_reset(s, hs))) return rc;
+    const uint64_t per = (m + chunks - 1) / chunks;
+    uint32_t used = 0;
+    for (uint64_t k = 0; k < chunks; ++k) {
+        const uint64_t a = std::min(m, k * per), b = std::min(m, a + per);
+        if (k > 0 && a >= m) break;
+        if (b > a)
+            if ((rc = run_hook_log(s, n, b - a, edges + 2 * a, P, flags, log, log_cap,
+                                   &s->st->log_count, hs)))
+                return rc;
+        // the messages appended so far, and the point after which the copy
+        // engine may read them
+        if ((rc = cohere(hs))) return rc;
+        if ((rc = log_count_snap(s, &hc[k], hs))) return rc;
+        CCM_HIP(hipEventRecord(ctx->dr_ev[k], hs));
+        ++used;
+    }
+    // the copies: each finished range, while the later launches run
+    const uint64_t cap = std::min(log_cap, host_cap);
+    uint64_t done = 0, total = 0;
+    for (uint32_t k = 0; k < used; ++k) {
+        CCM_HIP(hipEventSynchronize(ctx->dr_ev[k]));
+        total = __atomic_load_n(&hc[k], __ATOMIC_ACQUIRE);
+        const uint64_t upto = std::min(total, cap);
+        if (upto > done) {
+            CCM_HIP(hipStreamWaitEvent(ctx->dr_stream, ctx->dr_ev[k], 0));
+            CCM_HIP(hipMemcpyAsync(host_log + 2 * done, log + 2 * done, (upto - done) * 8,
+                                   hipMemcpyDeviceToHost, ctx->dr_stream));
+            done = upto;
+        }
+    }
+    CCM_HIP(hipStreamSynchronize(ctx->dr_stream));
+    *n_messages = total;
+    if (total > cap)
+        return fail(CC_ENOMEM, "update log capacity exceeded: " + std::to_string(total) +
+                                   " messages, room for " + std::to_string(cap));
+    return CC_OK;
 }
 
 extern "C" int cc_compress(cc_ctx* ctx, uint64_t n, uint32_t* P, uint32_t flags, void* stream) {

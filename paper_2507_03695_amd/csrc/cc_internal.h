@@ -24,7 +24,8 @@ struct DevState {
     uint32_t zroot;     // the zero root chosen for the current solve
     uint32_t pad0;
     uint64_t zsel;      // packed argmax (count << 32) | (0xFFFFFFFF - id); 0 = none
-    uint64_t pad1[5];
+    uint64_t log_count; // messages of a drained update log (cc_hook_log_drain)
+    uint64_t pad1[4];
 };
 static_assert(sizeof(DevState) == 64, "DevState is one 64-byte block");
 
@@ -128,6 +129,10 @@ int run_compress(Slot* s, uint64_t n, uint32_t* P, uint32_t flags, hipStream_t s
 int run_hook_log(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
                  uint32_t flags, uint32_t* log, uint64_t log_cap, uint64_t* log_count,
                  hipStream_t stream);
+// The log counter of the slot's DevState set to 0 (a kernel: capturable).
+int log_count_reset(Slot* s, hipStream_t stream);
+// The counter's value written to a pinned host word (a kernel, ordered on stream).
+int log_count_snap(Slot* s, uint64_t* host_word, hipStream_t stream);
 int run_canon(Slot* s, uint64_t n, uint32_t* L, hipStream_t stream);
 int run_hook_ids(Slot* s, uint64_t n, uint64_t count, const uint32_t* ids, uint32_t target,
                  uint32_t* P, uint32_t flags, hipStream_t stream);

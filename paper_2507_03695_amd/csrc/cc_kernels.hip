@@ -932,6 +932,28 @@ int run_hook_log(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_
     return CC_OK;
 }
 
+__global__ void k_log_count_reset(DevState* st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) st_agent64(&st->log_count, 0ull);
+}
+
+__global__ void k_log_count_snap(DevState* st, uint64_t* host_word) {
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        __hip_atomic_store(host_word, ld_agent64(&st->log_count), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+int log_count_reset(Slot* s, hipStream_t stream) {
+    k_log_count_reset<<<1, 64, 0, stream>>>(s->st);
+    CCM_HIP(hipGetLastError());
+    return CC_OK;
+}
+
+int log_count_snap(Slot* s, uint64_t* host_word, hipStream_t stream) {
+    k_log_count_snap<<<1, 64, 0, stream>>>(s->st, host_word);
+    CCM_HIP(hipGetLastError());
+    return CC_OK;
+}
+
 int run_compress(Slot* s, uint64_t n, uint32_t* P, uint32_t flags, hipStream_t stream,
                  bool final_labels) {
     const uint32_t g = grid_for(n, kBlock, kGridCap);

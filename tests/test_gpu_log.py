@@ -100,6 +100,65 @@ def test_log_capacity_and_arguments():
         assert int(cnt.item()) == 1                # (2, 1); the bad entry is skipped
 
 
+@pytest.mark.parametrize("chunks", [1, 7, 64])
+def test_log_drained_while_hooking(chunks):
+    """cc_hook_log_drain: the log copied to pinned host memory launch by launch.
+    The host copy holds exactly the links (each vertex but its component's lowest
+    ID once; the messages as edges give the oracle's labels), as many as the
+    sequential Algorithm 2 sends, and P is left hooked as by cc_hook_log."""
+    n = 1 << 20
+    e = graphgen.rmat(20, (1 << 22) + 333, 86)               # ragged against the chunks
+    want = oracle.cc_labels(n, e)
+    ed = to_dev(e)
+    with cc.Context() as c:
+        P = torch.empty(n, dtype=torch.int32, device="cuda")
+        dev_log = torch.empty((n, 2), dtype=torch.int32, device="cuda")
+        host = torch.empty((n, 2), dtype=torch.int32, pin_memory=True)
+        c.init(n, P)
+        k = c.hook_log_drain(ed, n, P, dev_log, host, chunks=chunks)
+        assert k == n - oracle.count_components(want)
+        check_log(n, host[:k].numpy().view(np.uint32), want, f"drained, {chunks} launches")
+        c.compress(n, P)
+        assert c.sync() == cc.CC_OK
+        assert_same_labels(to_host_u32(P), want, "labels after the drained hook")
+        # a pageable host buffer works too; a second call counts from 0 again
+        host2 = torch.empty((n, 2), dtype=torch.int32)
+        c.init(n, P)
+        k2 = c.hook_log_drain(ed, n, P, dev_log, host2, chunks=chunks)
+        assert k2 == k
+        check_log(n, host2[:k2].numpy().view(np.uint32), want, "pageable host buffer")
+
+
+def test_log_drain_capacity_and_arguments():
+    n = 1 << 12
+    e = graphgen.er(n, 4 * n, 87)
+    want = oracle.cc_labels(n, e)
+    total = n - oracle.count_components(want)
+    ed = to_dev(e)
+    with cc.Context() as c:
+        P = torch.empty(n, dtype=torch.int32, device="cuda")
+        dev_log = torch.empty((n, 2), dtype=torch.int32, device="cuda")
+        small = torch.empty((100, 2), dtype=torch.int32, pin_memory=True)
+        c.init(n, P)
+        with pytest.raises(cc.CCError) as ei:                 # host room for 100 only
+            c.hook_log_drain(ed, n, P, dev_log, small, chunks=5)
+        assert ei.value.code == cc.CC_ENOMEM
+        kept = small.numpy().view(np.uint32)
+        assert len(np.unique(kept[:, 0])) == 100 and np.array_equal(want[kept[:, 0]], want[kept[:, 1]])
+        assert total > 100
+        host = torch.empty((n, 2), dtype=torch.int32, pin_memory=True)
+        for bad_chunks in (0, cc.DRAIN_MAX_CHUNKS + 1):
+            with pytest.raises(cc.CCError) as ei:
+                c.hook_log_drain(ed, n, P, dev_log, host, chunks=bad_chunks)
+            assert ei.value.code == cc.CC_EINVAL
+        with pytest.raises(cc.CCError) as ei:
+            c.hook_log_drain(ed, n, P, dev_log, host, flags=cc.F_ZROOT)
+        assert ei.value.code == cc.CC_EINVAL
+        c.init(n, P)
+        assert c.hook_log_drain(ed[:0], n, P, dev_log, host, chunks=3) == 0
+        assert c.sync() == cc.CC_OK
+
+
 def test_siskin_reducer_16_shares():
     """Each of 16 edge shares hooks into its own P with a log and sends nothing
     else; the Reducer hooks all messages as edges and compresses (Sec. III)."""
