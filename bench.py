@@ -36,8 +36,8 @@ PEAK_HBM_GBS = 8000.0
 # each counter scaled by what it reads for a 4 GiB device copy. Keyed by
 # (workload, variant); valid only for the kernel sources they were taken on.
 TRAFFIC = {
-    ("rmat26", "zroot"): {"bytes": 47179537125,
-                          "src_sha256": "b86ead0a5cc6855af89cc6d65e163c2d67520c696d164f37eb75a0854b4bb992"},
+    ("rmat26", "zroot"): {"bytes": 47664574359,
+                          "src_sha256": "f86f75c862ab688ea9b50c6e99969ff6c1a1a31bfd404897c9997a37157efc9e"},
 }
 
 HOOK_KERNELS = {
