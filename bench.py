@@ -92,9 +92,22 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(edges, n, target_s=15.0):
-    """The oracle on a bounded prefix of the same entries (1 host thread)."""
+    """The oracle on a bounded prefix of the same entries, on one host thread
+    pinned to one core (the first core this process may run on)."""
     import oracle
+    allowed = sorted(os.sched_getaffinity(0))
+    os.sched_setaffinity(0, {allowed[0]})
     m = len(edges)
     k = min(m, 1 << 22)
     while True:
@@ -106,9 +119,11 @@ def cpu_baseline(edges, n, target_s=15.0):
         # the time per entry grows with the prefix (the touched part of the
         # parent array outgrows the caches), so grow the sample in steps
         k = int(min(m, k * min(4.0, max(1.5, target_s / max(t1, 1e-3)))))
+    os.sched_setaffinity(0, set(allowed))
     return {"value": round(k / t1 / 1e9, 6), "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "host_cpu": host_cpu_model(), "pinned_core": allowed[0],
             "sample": f"first {k} of {m} entries with all {n} vertices; union-find + min-ID pass, "
-                      f"{t1:.2f} s on one host thread"}
+                      f"{t1:.2f} s on one host thread pinned to core {allowed[0]}"}
 
 
 def bench_single(cc, torch, ed, n, m, steps, warmup, flags):
@@ -284,13 +299,10 @@ def bench_batch(cc, torch, reps=5):
             "speedup": round(t_loop / t_batch, 2), "identical_labels": same}
 
 
-def bench_batch_tail(cc, torch, reps=5):
-    """The 4,096-graph mix with its last 8 graphs replaced by R-MAT scale-20,
-    edgefactor-8 graphs: the tuner's candidates and pick vs the fixed
-    workgroup-per-graph schedule (labels equal; oracle parity of this batch's
-    schedules is a GPU test)."""
-    import graphgen
-    b = graphgen.batch_with_tail(graphgen.config_seed(4))
+def _bench_batch_mix(cc, torch, b, reps=5):
+    """The tuner's candidates and pick on batch b, then b under the pick against
+    the fixed workgroup-per-graph schedule (labels equal; the oracle parity of
+    every schedule is a GPU test)."""
     vo = torch.from_numpy(b.vtx_off).cuda()
     eo = torch.from_numpy(b.edge_off).cuda()
     ed = torch.from_numpy(np.ascontiguousarray(b.edges)).cuda()
@@ -311,6 +323,22 @@ def bench_batch_tail(cc, torch, reps=5):
             "pick_speedup_over_fixed": round(t_fixed / t_pick, 2),
             "pick_graphs_per_s": round(b.G / t_pick, 1),
             "identical_labels": same}
+
+
+def bench_batch_tail(cc, torch, reps=5):
+    """The 4,096-graph mix with its last 8 graphs replaced by R-MAT scale-20,
+    edgefactor-8 graphs (the whole-device role's case)."""
+    import graphgen
+    return _bench_batch_mix(cc, torch, graphgen.batch_with_tail(graphgen.config_seed(4)), reps)
+
+
+def bench_batch_tiny(cc, torch, reps=5):
+    """16,384 small graphs: n log-uniform in [2^5, 2^10], average degree uniform in
+    [2, 8] (the wavefront role's case)."""
+    import graphgen
+    b = graphgen.batch(16384, graphgen.config_seed(4) ^ 0x7157, lg_n_lo=5.0, lg_n_hi=10.0,
+                       deg_lo=2.0, deg_hi=8.0)
+    return _bench_batch_mix(cc, torch, b, reps)
 
 
 def bench_reducer(cc, torch, ed, n, L_ref, g=16, reps=3):
@@ -726,7 +754,7 @@ def main():
                     help="skip every section after the headline and the other variant")
     ap.add_argument("--only", default=None,
                     choices=["small_configs", "reducer", "update_log", "csr", "u64_ids",
-                             "share_rmat30", "batch", "batch_tail", "serve"],
+                             "share_rmat30", "batch", "batch_tail", "batch_tiny", "serve"],
                     help="run just this one further section (for profiling it)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 4 GiB device copy (reference for HBM byte counters)")
@@ -848,6 +876,10 @@ def main():
         t1 = time.time()
         line["batch_tail"] = bench_batch_tail(cc, torch)
         log(f"batch with tail done in {time.time() - t1:.1f} s")
+    if want("batch_tiny"):
+        t1 = time.time()
+        line["batch_tiny"] = bench_batch_tiny(cc, torch)
+        log(f"batch of small graphs done in {time.time() - t1:.1f} s")
     if want("serve"):
         t1 = time.time()
         line["serve"] = bench_serve(cc, torch)
