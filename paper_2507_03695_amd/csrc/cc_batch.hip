@@ -6,10 +6,11 @@
 //  - tile: one workgroup takes whole graphs from a largest-first work list (one
 //    atomic ticket per graph), its steps separated by workgroup barriers, so
 //    the launch needs no grid-wide synchronisation. A graph of at most 2^16
-//    vertices keeps its parent array in the workgroup's LDS as 16-bit entries
-//    (128 KB at n = 2^16; a link is a compare-and-swap on the 32-bit word
-//    holding the entry); labels go to HBM once, coalesced. A larger graph keeps
-//    its parent array in its label slice in HBM.
+//    vertices keeps its parent array in the workgroup's LDS (32-bit entries up
+//    to 2^15 vertices, else 16-bit entries: 128 KB at n = 2^16, a link being a
+//    compare-and-swap on the 32-bit word holding the entry); labels go to HBM
+//    once, coalesced. A larger graph keeps its parent array in its label slice
+//    in HBM.
 //  - wave: one wavefront takes a small graph from a second work list and solves
 //    it in an 8 KB partition of the workgroup's LDS, its steps separated by
 //    wavefront-level ordering only; 16 graphs per workgroup run at once. The
@@ -61,25 +62,32 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// ---- 16-bit parent array in LDS (n <= 2^16) ------------------------------------------
+// ---- parent array in LDS: 32-bit entries up to half the capacity, else 16-bit --------
+// A graph of at most 2^15 vertices keeps 32-bit entries (a link is one CAS on
+// the entry); up to 2^16 vertices the entries are 16-bit and a link is a CAS on
+// the 32-bit word holding the entry (4,096-graph batch: 1.55 ms against 1.64 ms
+// with 16-bit entries throughout).
 
-__device__ __forceinline__ uint32_t bfind16(uint16_t* P, uint32_t x, uint32_t px) {
+template <typename PT>
+__device__ __forceinline__ uint32_t lfind(PT* P, uint32_t x, uint32_t px) {
     while (px != x) {
         const uint32_t gp = P[px];
         if (gp == px) return px;
         stress_delay(x);
-        P[x] = (uint16_t)gp;
+        P[x] = (PT)gp;
         x = px;
         px = gp;
     }
     return x;
 }
 
-// CAS of the 16-bit entry hi from hi (a root) to lo, on the 32-bit word that
-// holds it; a change of the other half only makes the word CAS retry. Returns
-// hi on success, else the entry's current (non-root) value.
-__device__ __forceinline__ uint32_t cas16(uint32_t* P32, uint32_t hi, uint32_t lo) {
-    uint32_t* w = &P32[hi >> 1];
+// CAS of the entry hi from hi (a root) to lo. Returns hi on success, else the
+// entry's current (non-root) value. 16-bit entries: the CAS is on the 32-bit
+// word that holds the entry; a change of the other half only makes it retry.
+template <typename PT>
+__device__ __forceinline__ uint32_t lcas(PT* P, uint32_t hi, uint32_t lo) {
+    if (sizeof(PT) == 4) return atomicCAS(reinterpret_cast<uint32_t*>(&P[hi]), hi, lo);
+    uint32_t* w = reinterpret_cast<uint32_t*>(P) + (hi >> 1);
     const uint32_t sh = (hi & 1u) << 4;
     uint32_t cur = *w;
     while (true) {
@@ -93,70 +101,85 @@ __device__ __forceinline__ uint32_t cas16(uint32_t* P32, uint32_t hi, uint32_t l
 }
 
 // Hooking of one entry whose endpoints u, v have parents pu, pv (read earlier).
-__device__ __forceinline__ void blink16(uint16_t* P, uint32_t* P32, uint32_t u, uint32_t pu,
-                                        uint32_t v, uint32_t pv) {
+template <typename PT>
+__device__ __forceinline__ void llink(PT* P, uint32_t u, uint32_t pu, uint32_t v, uint32_t pv) {
     if (pu == pv || pu == v || pv == u) return;
     while (true) {
-        const uint32_t ru = bfind16(P, u, pu);
-        const uint32_t rv = bfind16(P, v, pv);
+        const uint32_t ru = lfind(P, u, pu);
+        const uint32_t rv = lfind(P, v, pv);
         if (ru == rv) return;
         const uint32_t hi = ru < rv ? rv : ru;
         const uint32_t lo = ru < rv ? ru : rv;
         stress_delay(hi);
-        const uint32_t old = cas16(P32, hi, lo);
+        const uint32_t old = lcas(P, hi, lo);
         if (old == hi) return;
         u = hi; pu = old;
         v = lo; pv = lo;
     }
 }
 
-// One graph with its parent array in LDS, by a group of T threads (T = 64: one
-// wavefront; T = kBatchBlock: the workgroup); idx is the thread's index in the
-// group. Returns whether this thread saw an endpoint out of range.
-template <int T>
-__device__ __forceinline__ bool solve_graph16(uint32_t* P32, uint32_t n, gedge_t* E, int64_t m,
-                                              glabel_t* out, int idx) {
+// One graph with its parent array in LDS (entries of type PT), by a group of T
+// threads (T = 64: one wavefront; T = kBatchBlock: the workgroup); idx is the
+// thread's index in the group. Returns whether this thread saw an endpoint out
+// of range.
+template <int T, typename PT>
+__device__ __forceinline__ bool solve_graph_lds(uint32_t* S, uint32_t n, gedge_t* E, int64_t m,
+                                                glabel_t* out, int idx) {
     auto sync = [] {
         if (T == 64) wave_sync();
         else __syncthreads();
     };
-    uint16_t* P = reinterpret_cast<uint16_t*>(P32);
-    for (uint32_t i = idx; 2 * i < n; i += T) P32[i] = (2 * i) | ((2 * i + 1) << 16);
+    PT* P = reinterpret_cast<PT*>(S);
+    if (sizeof(PT) == 4) {
+        for (uint32_t i = idx; i < n; i += T) S[i] = i;
+    } else {
+        for (uint32_t i = idx; 2 * i < n; i += T) S[i] = (2 * i) | ((2 * i + 1) << 16);
+    }
     sync();
     bool bad = false;
-    // Software pipeline over rounds of kBatchEPT entries per thread: register k
-    // is reloaded with entry k of the next round right after entry k is linked,
-    // so the next round's loads are in flight while this round is processed.
+    // Two rounds of kBatchEPT entries per thread in flight: A holds round r and
+    // B round r + 1; right after an entry of a round is linked, its register is
+    // reloaded with that entry's place two rounds on. A graph without entries
+    // issues no edge load at all: its entry pointer may be NULL (an edge-free
+    // batch) or point one past the batch's last entry.
     constexpr int64_t kRound = (int64_t)T * kBatchEPT;
-    // A graph without entries issues no edge load at all: its entry pointer may
-    // be NULL (an edge-free batch) or point one past the batch's last entry.
-    i32x2 x[kBatchEPT];
+    i32x2 A[kBatchEPT], B[kBatchEPT];
 #pragma unroll
     for (int k = 0; k < kBatchEPT; ++k) {
-        const int64_t e = idx + (int64_t)k * T;
-        x[k] = i32x2{0, 0};
-        if (m > 0) x[k] = __builtin_nontemporal_load(E + (e < m ? e : 0));
+        const int64_t e = idx + (int64_t)k * T, f = e + kRound;
+        A[k] = i32x2{0, 0};
+        B[k] = i32x2{0, 0};
+        if (m > 0) {
+            A[k] = __builtin_nontemporal_load(E + (e < m ? e : 0));
+            B[k] = __builtin_nontemporal_load(E + (f < m ? f : 0));
+        }
     }
-    for (int64_t e0 = idx; e0 < m; e0 += kRound) {
+    auto round = [&](i32x2 (&x)[kBatchEPT], int64_t e0) {
         // every entry's two parent reads first (LDS latency overlaps), then the links
         uint32_t pu[kBatchEPT], pv[kBatchEPT];
         bool live[kBatchEPT];
+        const int64_t rem = m - e0;
 #pragma unroll
         for (int k = 0; k < kBatchEPT; ++k) {
             const uint32_t u = (uint32_t)x[k].x, v = (uint32_t)x[k].y;
-            const bool in = e0 + (int64_t)k * T < m;
+            const bool in = (int64_t)k * T < rem;
             const bool ok = u < n && v < n;
             bad |= in && !ok;
             live[k] = in && ok && u != v;
-            pu[k] = live[k] ? P[u] : 0u;
-            pv[k] = live[k] ? P[v] : 0u;
+            pu[k] = live[k] ? (uint32_t)P[u] : 0u;
+            pv[k] = live[k] ? (uint32_t)P[v] : 0u;
         }
 #pragma unroll
         for (int k = 0; k < kBatchEPT; ++k) {
-            if (live[k]) blink16(P, P32, (uint32_t)x[k].x, pu[k], (uint32_t)x[k].y, pv[k]);
-            const int64_t e = e0 + kRound + (int64_t)k * T;
+            if (live[k]) llink(P, (uint32_t)x[k].x, pu[k], (uint32_t)x[k].y, pv[k]);
+            const int64_t e = e0 + 2 * kRound + (int64_t)k * T;
             x[k] = __builtin_nontemporal_load(E + (e < m ? e : 0));
         }
+    };
+    for (int64_t e0 = idx; e0 < m; e0 += 2 * kRound) {
+        round(A, e0);
+        if (e0 + kRound >= m) break;
+        round(B, e0 + kRound);
     }
     sync();
     for (uint32_t v = idx; v < n; v += T) {
@@ -305,8 +328,12 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(const GraphDesc* __restri
         if (t >= Gt) break;
         const GraphDesc d = descs[order[t]];
         gedge_t* E = (gedge_t*)d.edges;
-        if (d.n <= lds16_cap) {
-            if (solve_graph16<kBatchBlock>(sP, d.n, E, d.m, (glabel_t*)d.L, threadIdx.x)) s_bad = 1;
+        if (d.n <= lds16_cap / 2) {
+            if (solve_graph_lds<kBatchBlock, uint32_t>(sP, d.n, E, d.m, (glabel_t*)d.L, threadIdx.x))
+                s_bad = 1;
+        } else if (d.n <= lds16_cap) {
+            if (solve_graph_lds<kBatchBlock, uint16_t>(sP, d.n, E, d.m, (glabel_t*)d.L, threadIdx.x))
+                s_bad = 1;
         } else {
             solve_graph_hbm((glabel_t*)d.L, d.n, E, d.m, &s_bad);
         }
@@ -324,7 +351,10 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(const GraphDesc* __restri
         t = __shfl(t, 0);
         if (t >= Gw) break;
         const GraphDesc d = descs[order[Gt + t]];
-        const bool bad = solve_graph16<64>(wP, d.n, (gedge_t*)d.edges, d.m, (glabel_t*)d.L, lane);
+        gedge_t* E = (gedge_t*)d.edges;
+        const bool bad = d.n <= wave_words
+                             ? solve_graph_lds<64, uint32_t>(wP, d.n, E, d.m, (glabel_t*)d.L, lane)
+                             : solve_graph_lds<64, uint16_t>(wP, d.n, E, d.m, (glabel_t*)d.L, lane);
         const bool any_bad = __ballot(bad) != 0;
         if (lane == 0) *(CCM_GLOBAL int32_t*)d.status = any_bad ? CC_ERANGE : CC_OK;
         wave_sync();   // the next graph's init must not overtake this one's reads
