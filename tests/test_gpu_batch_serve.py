@@ -166,6 +166,12 @@ def _mixed_batch(seed, large=True):
     graphs += [(graphgen.er(4096, 65536, seed + 2), 4096),      # at both wave limits
                (graphgen.er(4096, 65537, seed + 3), 4096),      # one entry too many
                (graphgen.er(64, 70_000, seed + 4), 64),         # dense tiny: tile role
+               # either side of the 32-bit / 16-bit LDS entry limits (wave: 2,048
+               # vertices; workgroup: 2^15) and of the LDS limit (2^16)
+               (graphgen.er(2048, 9000, seed + 9), 2048), (graphgen.er(2049, 9000, seed + 10), 2049),
+               (graphgen.er(1 << 15, 150_000, seed + 11), 1 << 15),
+               (graphgen.er((1 << 15) + 1, 150_000, seed + 12), (1 << 15) + 1),
+               (graphgen.er(1 << 16, 300_000, seed + 13), 1 << 16),
                (np.zeros((0, 2), np.uint32), 0), (np.zeros((0, 2), np.uint32), 5),
                (np.zeros((0, 2), np.uint32), 70_000)]
     if large:
