@@ -268,8 +268,8 @@ int cc_push(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t
    CC_F_ZROOT key(z) = 0 and key(x) = x + 1 (R of Formula 1). With
    CC_F_ZROOT the context also keeps a membership bitmap of the vertices
    known to be connected to z: an entry with both endpoints in it is skipped,
-   and on the tiled path an entry with exactly one endpoint in it only adds
-   the other endpoint (that bit is the entry's link to z). After a CC_F_ZROOT
+   and an entry with exactly one endpoint in it only adds the other endpoint
+   (that bit is the entry's link to z). After a CC_F_ZROOT
    hook the components are therefore given by P and the bitmap together;
    cc_compress with CC_F_ZROOT resolves both. Requires cc_init then cc_zroot
    on the same n (else CC_EINVAL). Out-of-range endpoints set the status word

@@ -119,6 +119,24 @@ int run_zroot(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t f
               uint32_t hint, hipStream_t stream);
 int run_push(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
              hipStream_t stream);
+// How the direct zero-root hooks settle an entry with exactly one endpoint in
+// the membership bitmap. Linking the other endpoint's tree under z costs a walk,
+// a coherent read and a CAS on P, but every vertex of that tree then walks to z
+// and is marked when an entry reaches it, so the bitmap grows faster; marking
+// the endpoint alone (compress passes the mark on to its tree) touches no P.
+// Once P outgrows the MALL (256 MB) each of those P accesses goes to HBM and
+// marking wins: R-MAT-30 1/16 share (4 GiB P), 46.9 -> 40.8 ms; R-MAT-26 +
+// extras direct, 21.7 -> 21.1 ms. Below it linking wins: R-MAT-22 direct 2.2
+// against 2.8 ms, R-MAT-24 5.5 against 5.8, R-MAT-26 1/16 share 2.8 against
+// 3.2. kHookLinkZ, an internal flag of run_hook (beside the public CC_F_*,
+// never accepted from a caller), asks for linking at any size: the regrouped
+// hook's warm-up seeds its filter's bitmap (10.1 against 10.4 ms on R-MAT-26 +
+// extras).
+constexpr uint32_t kHookLinkZ = 0x80000000u;
+constexpr uint64_t kMallBytes = 256ull << 20;
+inline bool hook_links_z(uint32_t flags, uint64_t n) {
+    return (flags & kHookLinkZ) || n * 4 <= kMallBytes;
+}
 int run_hook(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
              uint32_t flags, hipStream_t stream);
 // final_labels (zero root): z's component ends labelled with its smallest ID

@@ -189,7 +189,8 @@ __global__ __launch_bounds__(kBlock) void k_push(const uint32_t* __restrict__ ed
     }
 }
 
-// Membership bitmap of the zero root's tree: cleared, with only z itself set.
+// Membership bitmap of the vertices connected to the zero root: cleared, with
+// only z itself set.
 __global__ __launch_bounds__(kBlock) void k_zbits_clear(uint32_t* zbits, uint64_t words,
                                                         const DevState* st) {
     const uint32_t z = ld_agent(&st->zroot);
@@ -345,7 +346,7 @@ __device__ __forceinline__ void log_append(const uint32_t (&child)[kEPT],
 // (see log_append); every thread of the block must then call it. sym: the
 // list holds every pair in both orders, so only the entries with u < v are
 // hooked (each edge once; Sec. II: processing (u,v) makes (v,u) a no-op).
-template <bool ZR, int SPLIT, bool LOG>
+template <bool ZR, int SPLIT, bool LOG, bool LINKZ = false>
 __device__ __forceinline__ void hook_entries(uint32_t (&u)[kEPT], uint32_t (&v)[kEPT], uint32_t n,
                                              uint32_t z, uint32_t* P, uint32_t* zbits,
                                              DevState* st, uint32_t* log, uint64_t log_cap,
@@ -360,6 +361,15 @@ __device__ __forceinline__ void hook_entries(uint32_t (&u)[kEPT], uint32_t (&v)[
     bool live[kEPT];
 #pragma unroll
     for (int k = 0; k < kEPT; ++k) live[k] = sym ? u[k] < v[k] : u[k] != v[k];
+    // A set bit means "connected to z". Both endpoints set: the entry is
+    // redundant. Exactly one set: by default the entry's whole effect is to
+    // connect the other endpoint to z, which its bit records (compress passes a
+    // mark on to the root of its tree), so it is set and P is not touched; only
+    // entries with neither endpoint marked go on to the walks. LINKZ instead
+    // walks the unmarked endpoint's tree and links it under z, marking both:
+    // dearer per entry, but every vertex of that tree then walks to z and is
+    // marked when an entry reaches it, so the bitmap grows faster (the
+    // regrouped hook's short warm-up, which seeds its filter, wants that).
     bool inu[kEPT] = {}, inv[kEPT] = {};
     if (ZR) {
         uint32_t bu[kEPT], bv[kEPT];
@@ -372,21 +382,22 @@ __device__ __forceinline__ void hook_entries(uint32_t (&u)[kEPT], uint32_t (&v)[
         for (int k = 0; k < kEPT; ++k) {
             inu[k] = (bu[k] >> (u[k] & 31)) & 1u;
             inv[k] = (bv[k] >> (v[k] & 31)) & 1u;
-            live[k] = live[k] && !(inu[k] && inv[k]);
+            if (!LINKZ && live[k] && inu[k] != inv[k]) zbit_set(zbits, inu[k] ? v[k] : u[k]);
+            live[k] = live[k] && !(inu[k] && inv[k]) && (LINKZ || (!inu[k] && !inv[k]));
         }
     }
-    // An endpoint whose bit is set has root z: walk from z instead (no read of P).
+    // LINKZ: a marked endpoint has root z (walk from z, no read of P)
     uint32_t wu[kEPT], wv[kEPT];
 #pragma unroll
     for (int k = 0; k < kEPT; ++k) {
-        wu[k] = (ZR && inu[k]) ? z : u[k];
-        wv[k] = (ZR && inv[k]) ? z : v[k];
+        wu[k] = (LINKZ && inu[k]) ? z : u[k];
+        wv[k] = (LINKZ && inv[k]) ? z : v[k];
     }
     uint32_t pu[kEPT], pv[kEPT];
 #pragma unroll
     for (int k = 0; k < kEPT; ++k) {
-        pu[k] = !live[k] ? 0u : ((ZR && inu[k]) ? z : P[wu[k]]);
-        pv[k] = !live[k] ? 0u : ((ZR && inv[k]) ? z : P[wv[k]]);
+        pu[k] = !live[k] ? 0u : ((LINKZ && inu[k]) ? z : P[wu[k]]);
+        pv[k] = !live[k] ? 0u : ((LINKZ && inv[k]) ? z : P[wv[k]]);
     }
     uint32_t child[kEPT], parent[kEPT];
 #pragma unroll
@@ -413,11 +424,12 @@ __device__ __forceinline__ void hook_entries(uint32_t (&u)[kEPT], uint32_t (&v)[
 // entries (coalesced, non-temporal: the edge stream must not evict P) and
 // issues all their parent reads before walking any of them.
 // With a zero root (ZR) the membership bitmap is consulted first: an entry
-// whose endpoints are both known to be in z's tree is dropped without reading P
-// (the single-GPU form of treating zero-converged vertices specially, Sec. IV).
-// Bits only go from 0 to 1 and only for vertices in z's tree, so a stale or
-// missing bit just sends the entry down the ordinary path.
-template <bool ZR, int SPLIT, bool LOG = false>
+// with an endpoint known to be connected to z is settled by its bits without
+// reading P (the single-GPU form of treating zero-converged vertices
+// specially, Sec. IV). Bits only go from 0 to 1 and only for vertices
+// connected to z, so a stale or missing bit just sends the entry down the
+// ordinary path.
+template <bool ZR, int SPLIT, bool LOG = false, bool LINKZ = false>
 __global__ __launch_bounds__(kBlock) void k_hook(const uint32_t* __restrict__ edges, uint64_t m,
                                                  uint32_t n, uint32_t* P, uint32_t* zbits,
                                                  DevState* st, uint32_t sym,
@@ -435,7 +447,8 @@ __global__ __launch_bounds__(kBlock) void k_hook(const uint32_t* __restrict__ ed
         u[k] = uv.x;
         v[k] = uv.y;
     }
-    hook_entries<ZR, SPLIT, LOG>(u, v, n, z, P, zbits, st, log, log_cap, log_count, sym != 0);
+    hook_entries<ZR, SPLIT, LOG, LINKZ>(u, v, n, z, P, zbits, st, log, log_cap, log_count,
+                                        sym != 0);
 }
 
 // ---- CSR input -------------------------------------------------------------------
@@ -531,7 +544,7 @@ __global__ __launch_bounds__(kBlock) void k_csr_push(const uint64_t* __restrict_
 
 // Workgroup t takes tile t (a launch may cover a prefix of the tiles, as the
 // warm-up does).
-template <bool ZR, int SPLIT>
+template <bool ZR, int SPLIT, bool LINKZ = false>
 __global__ __launch_bounds__(kBlock) void k_csr_hook(const uint64_t* __restrict__ off,
                                                      const uint32_t* __restrict__ adj, uint32_t n,
                                                      uint64_t m, const uint32_t* __restrict__ tstart,
@@ -618,7 +631,8 @@ __global__ __launch_bounds__(kBlock) void k_csr_hook(const uint64_t* __restrict_
         const uint64_t p = p0 + (uint64_t)k * kBlock + threadIdx.x;
         if (p >= m) u[k] = v[k] = 0;
     }
-    hook_entries<ZR, SPLIT, false>(u, v, n, z, P, zbits, st, nullptr, 0, nullptr, sym != 0);
+    hook_entries<ZR, SPLIT, false, LINKZ>(u, v, n, z, P, zbits, st, nullptr, 0, nullptr,
+                                          sym != 0);
     __syncthreads();                                    // head of this tile fully used
     }
 }
@@ -902,7 +916,12 @@ int run_hook(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P
     const uint32_t n32 = (uint32_t)n;
     uint32_t* zb = s->zbits;
     const uint32_t g = (uint32_t)blocks;
-    if (zr && split) k_hook<true, 1><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st, sym);
+    const bool linkz = hook_links_z(flags, n);
+    if (zr && linkz && split)
+        k_hook<true, 1, false, true><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st, sym);
+    else if (zr && linkz)
+        k_hook<true, 0, false, true><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st, sym);
+    else if (zr && split) k_hook<true, 1><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st, sym);
     else if (zr) k_hook<true, 0><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st, sym);
     else if (split) k_hook<false, 1><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st, sym);
     else k_hook<false, 0><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st, sym);
@@ -1071,9 +1090,8 @@ int run_solve_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, const ui
         // entries again too, which finds them joined)
         const uint64_t w = ntiles >> 10;
         if (w) {
-            k_csr_hook<true, 1><<<(uint32_t)w, kBlock, 0, stream>>>(off, adj, (uint32_t)n, m,
-                                                                   s->csr_tiles, ntiles, L,
-                                                                   s->zbits, s->st, sym);
+            k_csr_hook<true, 1, true><<<(uint32_t)w, kBlock, 0, stream>>>(
+                off, adj, (uint32_t)n, m, s->csr_tiles, ntiles, L, s->zbits, s->st, sym);
             CCM_HIP(hipGetLastError());
         }
         if ((rc = run_hook_tiled_csr(s, n, m, off, adj, L, stream, sym != 0))) return rc;
@@ -1081,7 +1099,13 @@ int run_solve_csr(Slot* s, uint64_t n, uint64_t m, const uint64_t* off, const ui
         const uint32_t g = (uint32_t)ntiles;
         const uint32_t n32 = (uint32_t)n;
         uint32_t* zb = s->zbits;
-        if (zr && split) k_csr_hook<true, 1><<<g, kBlock, 0, stream>>>(off, adj, n32, m, s->csr_tiles, ntiles, L, zb, s->st, sym);
+        const uint32_t* ts = s->csr_tiles;
+        const bool linkz = hook_links_z(flags, n);
+        if (zr && linkz && split)
+            k_csr_hook<true, 1, true><<<g, kBlock, 0, stream>>>(off, adj, n32, m, ts, ntiles, L, zb, s->st, sym);
+        else if (zr && linkz)
+            k_csr_hook<true, 0, true><<<g, kBlock, 0, stream>>>(off, adj, n32, m, ts, ntiles, L, zb, s->st, sym);
+        else if (zr && split) k_csr_hook<true, 1><<<g, kBlock, 0, stream>>>(off, adj, n32, m, s->csr_tiles, ntiles, L, zb, s->st, sym);
         else if (zr) k_csr_hook<true, 0><<<g, kBlock, 0, stream>>>(off, adj, n32, m, s->csr_tiles, ntiles, L, zb, s->st, sym);
         else if (split) k_csr_hook<false, 1><<<g, kBlock, 0, stream>>>(off, adj, n32, m, s->csr_tiles, ntiles, L, zb, s->st, sym);
         else k_csr_hook<false, 0><<<g, kBlock, 0, stream>>>(off, adj, n32, m, s->csr_tiles, ntiles, L, zb, s->st, sym);

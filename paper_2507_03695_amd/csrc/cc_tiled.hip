@@ -705,8 +705,8 @@ __global__ __launch_bounds__(kPartBlock) void k_t2_csr(const uint64_t* __restric
 
 // ---- 5. the filter over bucket (a, b) with both slices' bitmap words in LDS ---------------
 //
-// From here on a set bit means "connected to the zero root" (the warm-up's and
-// the Initial Push's bits are stronger: in z's tree already). An entry with
+// A set bit means "connected to the zero root" (the Initial Push's bits are
+// stronger: in z's tree already), as in the direct hook. An entry with
 // both endpoints marked is dropped: the two are connected anyway. An entry with
 // exactly one marked endpoint is dropped too, after marking the other endpoint:
 // that mark is the entry's link to z, and compress later puts every tree that
@@ -1197,7 +1197,8 @@ int run_hook_tiled(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint3
     const uint64_t m0 = plain ? 0 : m >> 10;
     if (m0) {
         int rc0 = run_hook(s, n, m0, edges, P,
-                           CC_F_ZROOT | CC_F_NO_TILE | (sym ? CC_F_SYMMETRIC : 0u), stream);
+                           CC_F_ZROOT | CC_F_NO_TILE | kHookLinkZ | (sym ? CC_F_SYMMETRIC : 0u),
+                           stream);
         if (rc0) return rc0;
         edges += 2 * m0;
         m -= m0;

@@ -2,7 +2,8 @@
 race-testing build (libccmi_stress.so: every link CAS and path-splitting store
 is preceded by a varying pause of its wave). Every solve, each on the entries
 in a new seeded order, must give the oracle's labels; the direct hooks (with
-path splitting above 4 MB of parent array, without it below), the regrouped
+path splitting above 4 MB of parent array, without it below; the zero-root
+one linking under z below 256 MB, marking above), the regrouped
 hooks, the 64-bit path and the batched launch (parent arrays in LDS and in HBM)
 are all exercised. Exit status 0 when every
 solve agrees. Started by tests/test_gpu_stress_delays.py; with --full it also
@@ -31,6 +32,9 @@ def main(full: bool = False) -> int:
         ("rmat_2^16", 1 << 16, graphgen.rmat(16, 1 << 20, 302), 3),   # small array: no splitting
         ("rmat_2^21", 1 << 21, graphgen.rmat(21, 1 << 22, 304), 2),   # direct hooks split
         ("rmat_2^22_2^24", 1 << 22, graphgen.rmat(22, 1 << 24, 303), 2),  # regrouped hooks
+        # a 512 MB parent array: the direct zero-root hook only marks the other
+        # endpoint of an entry with one marked endpoint
+        ("rmat_2^27_2^22", 1 << 27, graphgen.rmat(27, 1 << 22, 309), 1),
     ]
     flagsets = {"plain": 0, "plain_nosplit": cc.F_NO_SPLIT, "plain_direct": cc.F_NO_TILE,
                 "zroot": cc.F_ZROOT, "zroot_direct": cc.F_ZROOT | cc.F_NO_TILE}

@@ -4,8 +4,10 @@ The hook kernels run Algorithm 1 (Algorithm 3 with the zero root's keys when a
 zero root is used, Sec. IV) with many threads on one parent array. This file
 models the steps one thread takes, in the order the kernels take them:
 
-- a thread holds a few entries; it tests all their bitmap bits, then reads all
-  their endpoints' parents, then hooks them one after the other;
+- a thread holds a few entries; it tests all their bitmap bits, marks the
+  unmarked endpoint of every entry with exactly one marked endpoint (that mark
+  is the entry's link to the zero root), then reads the parents of the
+  entries with neither endpoint marked, then hooks those one after the other;
 - the walks use path splitting;
 - a link is a CAS on the root's own entry, retried from the new parent when
   it fails;
@@ -21,11 +23,17 @@ Every schedule must:
 - link each vertex at most once, only while it is a root, and never one the
   Initial Push already placed;
 - leave a forest whose parents have smaller keys;
-- set bitmap bits only for vertices in the zero root's tree.
+- set bitmap bits only for vertices in the zero root's component;
+- with a zero root, give the oracle's labels after the compress and resolve
+  model below (marks passed on to roots), in more than one vertex order.
 
 Planted mistakes in the model (a link that is a plain store, a failed CAS
-taken as done, the plain keys with a zero root) must each be caught by one of
-these checks.
+taken as done, an entry with one marked endpoint dropped without its mark)
+must each be caught by one of these checks. In this model the zero root never
+takes part in a link: its tree is z and the pushed vertices, all marked before
+the hook starts, so an entry reaching it is settled by its bits. (On the
+device a stale bit can still send such an entry to a walk that ends in z,
+which is why the kernels keep Formula 1's keys.)
 
 A second model, at the end of the file, covers the regrouped zero-root hook:
 - the filter's marks stand in for links to z;
@@ -59,6 +67,12 @@ class Shared:
         self.links = [0] * n          # successful link CASes per vertex
         self.linked_nonroot = False
         self.pushed = set()
+
+    def copy(self):
+        c = Shared(self.n, self.z)
+        c.P, c.bit = list(self.P), list(self.bit)
+        c.links, c.linked_nonroot, c.pushed = list(self.links), self.linked_nonroot, set(self.pushed)
+        return c
 
 
 def key(x, z):
@@ -112,55 +126,49 @@ def link(sh, u, pu, v, pv, split, bug, keyz):
 
 
 def thread(sh, entries, split, bug=None):
-    """One thread's entries: bitmap tests, then parent reads, then the hooks."""
+    """One thread's entries: bitmap tests and marks, then parent reads, then the
+    hooks."""
     z = sh.z
-    keyz = None if bug == "plain_keys" else z
+    keyz = z
     k = len(entries)
     live = [u != v for u, v in entries]
-    inu, inv = [False] * k, [False] * k
     if z is not None:
+        inu, inv = [False] * k, [False] * k
         for i, (u, v) in enumerate(entries):
             if live[i]:
                 yield
                 inu[i] = sh.bit[u]
                 yield
                 inv[i] = sh.bit[v]
-                live[i] = not (inu[i] and inv[i])
-    wu = [z if inu[i] else entries[i][0] for i in range(k)]
-    wv = [z if inv[i] else entries[i][1] for i in range(k)]
+        for i, (u, v) in enumerate(entries):
+            if live[i] and inu[i] != inv[i] and bug != "no_mark":
+                yield
+                sh.bit[v if inu[i] else u] = True
+            live[i] = live[i] and not inu[i] and not inv[i]
     pu, pv = [0] * k, [0] * k
-    for i in range(k):
+    for i, (u, v) in enumerate(entries):
         if not live[i]:
             continue
-        if inu[i]:
-            pu[i] = z
-        else:
-            yield
-            pu[i] = sh.P[wu[i]]
-        if inv[i]:
-            pv[i] = z
-        else:
-            yield
-            pv[i] = sh.P[wv[i]]
-    for i in range(k):
+        yield
+        pu[i] = sh.P[u]
+        yield
+        pv[i] = sh.P[v]
+    for i, (u, v) in enumerate(entries):
         if not live[i]:
             continue
         if pu[i] == pv[i]:
             r = pu[i]
-        elif pu[i] == wv[i]:
-            r = wv[i]
-        elif pv[i] == wu[i]:
-            r = wu[i]
+        elif pu[i] == v:
+            r = v
+        elif pv[i] == u:
+            r = u
         else:
-            r = yield from link(sh, wu[i], pu[i], wv[i], pv[i], split, bug, keyz)
+            r = yield from link(sh, u, pu[i], v, pv[i], split, bug, keyz)
         if z is not None and r == z:
-            u, v = entries[i]
-            if not inu[i]:
-                yield
-                sh.bit[u] = True
-            if not inv[i]:
-                yield
-                sh.bit[v] = True
+            yield
+            sh.bit[u] = True
+            yield
+            sh.bit[v] = True
 
 
 def initial_push(sh, edges):
@@ -226,18 +234,27 @@ def problems(sh, n, edges):
         out.append("a pushed vertex was linked again")
     want = oracle.cc_labels(n, np.asarray(edges, np.uint32).reshape(-1, 2))
     ncomp = oracle.count_components(want)
-    if sum(sh.links) + len(sh.pushed) != n - ncomp:
-        out.append(f"{sum(sh.links)} links + {len(sh.pushed)} pushed != n - #components")
-    roots = [root(P, x) for x in range(n)]
+    if z is None:
+        if sum(sh.links) != n - ncomp:
+            out.append(f"{sum(sh.links)} links != n - #components")
+        roots = [root(P, x) for x in range(n)]
+        low = {}
+        for x in range(n):
+            low.setdefault(roots[x], x)     # x increasing: the first member is the least
+        got = np.array([low[r] for r in roots], np.uint32)
+        if not np.array_equal(got, want):
+            out.append(f"labels {got.tolist()} != oracle {want.tolist()}")
+        return out
+    # with a zero root some connections are recorded only as marks
+    if sum(sh.links) + len(sh.pushed) > n - ncomp:
+        out.append(f"{sum(sh.links)} links + {len(sh.pushed)} pushed > n - #components")
     for x in range(n):
-        if sh.bit[x] and roots[x] != z:
-            out.append(f"{x} is marked but its root is {roots[x]}, not z = {z}")
-    low = {}
-    for x in range(n):
-        low.setdefault(roots[x], x)     # x increasing: the first member is the least
-    got = np.array([low[r] for r in roots], np.uint32)
-    if not np.array_equal(got, want):
-        out.append(f"labels {got.tolist()} != oracle {want.tolist()}")
+        if sh.bit[x] and want[x] != want[z]:
+            out.append(f"{x} is marked but not in the zero root's component")
+    for order in (list(range(n)), list(range(n - 1, -1, -1))):
+        got = compress_resolve(sh.copy(), order)
+        if not np.array_equal(got, want):
+            out.append(f"labels {got.tolist()} != oracle {want.tolist()} (order {order})")
     return out
 
 
@@ -346,7 +363,8 @@ def test_random_schedules(seed):
     ("store", (3, None, [[(2, 0)], [(2, 1)]], True)),
     ("no_retry", (3, None, [[(2, 0)], [(2, 1)]], True)),
     ("store", (5, 2, [[(4, 1)], [(4, 3)]], True)),
-    ("plain_keys", (3, 2, [[(2, 0)], [(0, 1)]], True)),
+    ("no_mark", (3, 2, [[(2, 0)], [(0, 1)]], True)),
+    ("no_mark", (5, 0, [[(0, 1), (3, 4)], [(1, 2), (2, 3)]], True)),
 ])
 def test_planted_mistakes_are_caught(bug, case):
     n, z, per_thread, split = case
