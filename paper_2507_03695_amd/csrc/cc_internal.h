@@ -125,8 +125,9 @@ int run_push(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P
 // and is marked when an entry reaches it, so the bitmap grows faster; marking
 // the endpoint alone (compress passes the mark on to its tree) touches no P.
 // Once P outgrows the MALL (256 MB) each of those P accesses goes to HBM and
-// marking wins: R-MAT-30 1/16 share (4 GiB P), 46.9 -> 40.8 ms; R-MAT-26 +
-// extras direct, 21.7 -> 21.1 ms. Below it linking wins: R-MAT-22 direct 2.2
+// marking wins: R-MAT-30 1/16 share (4 GiB P), 46.9 -> 40.8 ms (37.6 with the
+// second endpoint's word read coherently, so that its mark is one atomic);
+// R-MAT-26 + extras direct, 21.7 -> 21.1 ms. Below it linking wins: R-MAT-22 direct 2.2
 // against 2.8 ms, R-MAT-24 5.5 against 5.8, R-MAT-26 1/16 share 2.8 against
 // 3.2. kHookLinkZ, an internal flag of run_hook (beside the public CC_F_*,
 // never accepted from a caller), asks for linking at any size: the regrouped

@@ -372,17 +372,22 @@ __device__ __forceinline__ void hook_entries(uint32_t (&u)[kEPT], uint32_t (&v)[
     // regrouped hook's short warm-up, which seeds its filter, wants that).
     bool inu[kEPT] = {}, inv[kEPT] = {};
     if (ZR) {
+        // Marking: the second endpoint's word is read coherently, so that the
+        // commonest mark (first endpoint marked, second not) needs only the atomic.
         uint32_t bu[kEPT], bv[kEPT];
 #pragma unroll
         for (int k = 0; k < kEPT; ++k) {
             bu[k] = live[k] ? zbits[u[k] >> 5] : 0u;
-            bv[k] = live[k] ? zbits[v[k] >> 5] : 0u;
+            bv[k] = !live[k] ? 0u : (LINKZ ? zbits[v[k] >> 5] : ld_agent(&zbits[v[k] >> 5]));
         }
 #pragma unroll
         for (int k = 0; k < kEPT; ++k) {
             inu[k] = (bu[k] >> (u[k] & 31)) & 1u;
             inv[k] = (bv[k] >> (v[k] & 31)) & 1u;
-            if (!LINKZ && live[k] && inu[k] != inv[k]) zbit_set(zbits, inu[k] ? v[k] : u[k]);
+            if (!LINKZ && live[k] && inu[k] != inv[k]) {
+                if (inu[k]) atomicOr(&zbits[v[k] >> 5], 1u << (v[k] & 31));
+                else zbit_set(zbits, u[k]);
+            }
             live[k] = live[k] && !(inu[k] && inv[k]) && (LINKZ || (!inu[k] && !inv[k]));
         }
     }
