@@ -99,6 +99,8 @@ int cc_version(void);
    not symmetric the labels are those of its u < v entries alone. Accepted by
    the whole-path calls (also cc_solve_u64), cc_hook and cc_hook_log. */
 #define CC_F_SYMMETRIC    0x40u
+/* Every other bit is reserved: each call that takes flags returns CC_EINVAL
+   when one is set. */
 
 /* ---- context ----------------------------------------------------------- */
 typedef struct cc_ctx cc_ctx;

@@ -436,6 +436,7 @@ extern "C" int cc_init(cc_ctx* ctx, uint64_t n, uint32_t* P, void* stream) {
 extern "C" int cc_zroot(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edges,
                         uint32_t flags, uint32_t zroot_hint, void* stream) {
     if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    if (check_flags(flags)) return CC_EINVAL;
     int rc = check_graph(n, m, edges, (const void*)1);
     if (rc) return rc;
     if (n == 0) return fail(CC_EINVAL, "zero root of an empty vertex set");
@@ -461,6 +462,7 @@ extern "C" int cc_push(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edge
 extern "C" int cc_hook(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P,
                        uint32_t flags, void* stream) {
     if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    if (check_flags(flags)) return CC_EINVAL;
     int rc = check_graph(n, m, edges, P);
     if (rc || n == 0) return rc;
     if ((rc = set_dev(ctx))) return rc;
@@ -473,6 +475,7 @@ extern "C" int cc_hook_log(cc_ctx* ctx, uint64_t n, uint64_t m, const uint32_t* 
                            uint32_t* P, uint32_t flags, uint32_t* log, uint64_t log_cap,
                            uint64_t* log_count, void* stream) {
     if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    if (check_flags(flags)) return CC_EINVAL;
     int rc = check_graph(n, m, edges, P);
     if (rc || n == 0) return rc;
     if (!log_count) return fail(CC_EINVAL, "log_count is NULL");
@@ -512,6 +515,7 @@ extern "C" int cc_hook_log_drain(cc_ctx* ctx, uint64_t n, uint64_t m, const uint
     if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
     if (!n_messages) return fail(CC_EINVAL, "n_messages is NULL");
     *n_messages = 0;
+    if (check_flags(flags)) return CC_EINVAL;
     int rc = check_graph(n, m, edges, P);
     if (rc || n == 0) return rc;
     if (chunks == 0 || chunks > CC_DRAIN_MAX_CHUNKS) return fail(CC_EINVAL, "chunks must be in 1..1024");
@@ -568,6 +572,7 @@ extern "C" int cc_hook_log_drain(cc_ctx* ctx, uint64_t n, uint64_t m, const uint
 
 extern "C" int cc_compress(cc_ctx* ctx, uint64_t n, uint32_t* P, uint32_t flags, void* stream) {
     if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    if (check_flags(flags)) return CC_EINVAL;
     int rc = check_graph(n, 0, nullptr, P);
     if (rc || n == 0) return rc;
     if ((rc = set_dev(ctx))) return rc;
@@ -602,6 +607,7 @@ extern "C" int cc_export(cc_ctx* ctx, uint64_t n, const uint32_t* P, uint32_t zr
 extern "C" int cc_hook_ids(cc_ctx* ctx, uint64_t n, uint64_t count, const uint32_t* ids,
                            uint32_t target, uint32_t* P, uint32_t flags, void* stream) {
     if (!ctx) return fail(CC_EINVAL, "ctx is NULL");
+    if (check_flags(flags)) return CC_EINVAL;
     int rc = check_graph(n, count, ids, P);
     if (rc || n == 0 || count == 0) return rc;
     if (target >= n) return fail(CC_EINVAL, "target must be < n");

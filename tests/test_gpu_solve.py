@@ -100,6 +100,11 @@ def test_errors(ctx):
                               9, None, None) == cc.CC_EINVAL
     assert lib.cc_solve_async(ctx.handle, 4, 0, None, L.data_ptr(), 0x100, 0, None,
                               None) == cc.CC_EINVAL                    # unknown flag bit
+    assert lib.cc_solve_async(ctx.handle, 4, 0, None, L.data_ptr(), 1 << 31, 0, None,
+                              None) == cc.CC_EINVAL                    # the library's own bit
+    with pytest.raises(cc.CCError) as ei:
+        ctx.hook(e, 4, L, flags=cc.F_ZROOT | (1 << 31))
+    assert ei.value.code == cc.CC_EINVAL
     # a zero-root hook needs cc_zroot after the latest cc_init
     ctx.init(4, L)
     with pytest.raises(cc.CCError) as ei:
