@@ -19,7 +19,7 @@
 //    kernel: three launches (init, hook, compress) cover all such graphs of the
 //    batch, each block taking a chunk of one graph's vertices or entries from a
 //    host-built chunk table; the parent array is the label slice in HBM.
-// Every thread keeps kBatchEPT edge loads in flight.
+// Every thread keeps two rounds of edge loads in flight.
 #include <algorithm>
 #include <cstring>
 #include <numeric>
@@ -43,7 +43,9 @@ constexpr size_t kTicketBytes = 256;
 constexpr int kTileTicket = 0;     // word of the tile list's ticket
 constexpr int kWaveTicket = 16;    // the wave list's, on its own 64-byte line
 
-constexpr int kBatchEPT = 8;
+constexpr int kBatchEPT = 8;     // entries per thread and round on the HBM paths
+constexpr int kLdsEPT = 4;       // the same with the parent array in LDS
+constexpr int kLinkQueue = 127;  // per-wave LDS slots of entries that need a walk
 
 // Agent-scope store to a global word (see the store rule in cc_kernels.hip).
 __device__ __forceinline__ void gstore(glabel_t* p, uint32_t v) {
@@ -124,7 +126,7 @@ __device__ __forceinline__ void llink(PT* P, uint32_t u, uint32_t pu, uint32_t v
 // of range.
 template <int T, typename PT>
 __device__ __forceinline__ bool solve_graph_lds(uint32_t* S, uint32_t n, gedge_t* E, int64_t m,
-                                                glabel_t* out, int idx) {
+                                                glabel_t* out, int idx, uint2* q) {
     auto sync = [] {
         if (T == 64) wave_sync();
         else __syncthreads();
@@ -137,15 +139,27 @@ __device__ __forceinline__ bool solve_graph_lds(uint32_t* S, uint32_t n, gedge_t
     }
     sync();
     bool bad = false;
-    // Two rounds of kBatchEPT entries per thread in flight: A holds round r and
-    // B round r + 1; right after an entry of a round is linked, its register is
+    // Two rounds of kLdsEPT entries per thread in flight: A holds round r and
+    // B round r + 1; right after an entry of a round is tested, its register is
     // reloaded with that entry's place two rounds on. A graph without entries
     // issues no edge load at all: its entry pointer may be NULL (an edge-free
     // batch) or point one past the batch's last entry.
-    constexpr int64_t kRound = (int64_t)T * kBatchEPT;
-    i32x2 A[kBatchEPT], B[kBatchEPT];
+    //
+    // An entry whose endpoints' parents already show them joined (a common
+    // parent, or one endpoint the other's parent) is done. The others need
+    // walks and a link, of very different lengths from lane to lane; linked in
+    // place they would leave most of the wave idle while its longest walk
+    // runs. They go to the wave's queue q (kLinkQueue slots: endpoints and the
+    // parents read for them, 16 bits each, as n <= 2^16 here), and whenever 64
+    // are queued the wave links them together, one per lane (4,096-graph
+    // batch: 1.55 -> 1.28 ms). The parents read may have changed meanwhile;
+    // they are still ancestors, which is all a walk needs.
+    constexpr int64_t kRound = (int64_t)T * kLdsEPT;
+    const int lane = idx & 63;
+    uint32_t qn = 0;                 // queued entries: the same in every lane
+    i32x2 A[kLdsEPT], B[kLdsEPT];
 #pragma unroll
-    for (int k = 0; k < kBatchEPT; ++k) {
+    for (int k = 0; k < kLdsEPT; ++k) {
         const int64_t e = idx + (int64_t)k * T, f = e + kRound;
         A[k] = i32x2{0, 0};
         B[k] = i32x2{0, 0};
@@ -154,13 +168,13 @@ __device__ __forceinline__ bool solve_graph_lds(uint32_t* S, uint32_t n, gedge_t
             B[k] = __builtin_nontemporal_load(E + (f < m ? f : 0));
         }
     }
-    auto round = [&](i32x2 (&x)[kBatchEPT], int64_t e0) {
-        // every entry's two parent reads first (LDS latency overlaps), then the links
-        uint32_t pu[kBatchEPT], pv[kBatchEPT];
-        bool live[kBatchEPT];
+    auto round = [&](i32x2 (&x)[kLdsEPT], int64_t e0) {
+        // every entry's two parent reads first (LDS latency overlaps), then the tests
+        uint32_t pu[kLdsEPT], pv[kLdsEPT];
+        bool live[kLdsEPT];
         const int64_t rem = m - e0;
 #pragma unroll
-        for (int k = 0; k < kBatchEPT; ++k) {
+        for (int k = 0; k < kLdsEPT; ++k) {
             const uint32_t u = (uint32_t)x[k].x, v = (uint32_t)x[k].y;
             const bool in = (int64_t)k * T < rem;
             const bool ok = u < n && v < n;
@@ -170,16 +184,41 @@ __device__ __forceinline__ bool solve_graph_lds(uint32_t* S, uint32_t n, gedge_t
             pv[k] = live[k] ? (uint32_t)P[v] : 0u;
         }
 #pragma unroll
-        for (int k = 0; k < kBatchEPT; ++k) {
-            if (live[k]) llink(P, (uint32_t)x[k].x, pu[k], (uint32_t)x[k].y, pv[k]);
+        for (int k = 0; k < kLdsEPT; ++k) {
+            const uint32_t u = (uint32_t)x[k].x, v = (uint32_t)x[k].y;
+            const bool walk = live[k] && !(pu[k] == pv[k] || pu[k] == v || pv[k] == u);
+            const uint64_t ball = __ballot(walk);
+            if (walk)
+                q[qn + (uint32_t)__popcll(ball & ((1ull << lane) - 1ull))] =
+                    uint2{u | (v << 16), pu[k] | (pv[k] << 16)};
+            qn += (uint32_t)__popcll(ball);
+            if (qn >= 64) {
+                wave_sync();
+                const uint2 a = q[lane];
+                llink(P, a.x & 0xFFFFu, a.y & 0xFFFFu, a.x >> 16, a.y >> 16);
+                const uint2 rest = (uint32_t)lane < qn - 64 ? q[64 + lane] : uint2{0u, 0u};
+                wave_sync();
+                if ((uint32_t)lane < qn - 64) q[lane] = rest;
+                qn -= 64;
+                wave_sync();
+            }
             const int64_t e = e0 + 2 * kRound + (int64_t)k * T;
             x[k] = __builtin_nontemporal_load(E + (e < m ? e : 0));
         }
     };
-    for (int64_t e0 = idx; e0 < m; e0 += 2 * kRound) {
-        round(A, e0);
-        if (e0 + kRound >= m) break;
-        round(B, e0 + kRound);
+    // loop control from the wave's first index, so that every lane of the wave
+    // runs every round (the queue's ballots and count need the whole wave)
+    for (int64_t b0 = idx - lane; b0 < m; b0 += 2 * kRound) {
+        round(A, b0 + lane);
+        if (b0 + kRound >= m) break;
+        round(B, b0 + lane + kRound);
+    }
+    if (qn) {
+        wave_sync();
+        if ((uint32_t)lane < qn) {
+            const uint2 a = q[lane];
+            llink(P, a.x & 0xFFFFu, a.y & 0xFFFFu, a.x >> 16, a.y >> 16);
+        }
     }
     sync();
     for (uint32_t v = idx; v < n; v += T) {
@@ -318,6 +357,8 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(const GraphDesc* __restri
     extern __shared__ uint32_t sP[];
     __shared__ uint32_t s_next;
     __shared__ int s_bad;
+    __shared__ uint2 s_q[kWaves * kLinkQueue];          // each wave's link queue
+    uint2* const myq = s_q + (threadIdx.x >> 6) * kLinkQueue;
     while (Gt) {
         if (threadIdx.x == 0) {
             s_next = atomicAdd(&tickets[kTileTicket], 1u);
@@ -329,10 +370,10 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(const GraphDesc* __restri
         const GraphDesc d = descs[order[t]];
         gedge_t* E = (gedge_t*)d.edges;
         if (d.n <= lds16_cap / 2) {
-            if (solve_graph_lds<kBatchBlock, uint32_t>(sP, d.n, E, d.m, (glabel_t*)d.L, threadIdx.x))
+            if (solve_graph_lds<kBatchBlock, uint32_t>(sP, d.n, E, d.m, (glabel_t*)d.L, threadIdx.x, myq))
                 s_bad = 1;
         } else if (d.n <= lds16_cap) {
-            if (solve_graph_lds<kBatchBlock, uint16_t>(sP, d.n, E, d.m, (glabel_t*)d.L, threadIdx.x))
+            if (solve_graph_lds<kBatchBlock, uint16_t>(sP, d.n, E, d.m, (glabel_t*)d.L, threadIdx.x, myq))
                 s_bad = 1;
         } else {
             solve_graph_hbm((glabel_t*)d.L, d.n, E, d.m, &s_bad);
@@ -353,8 +394,8 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch(const GraphDesc* __restri
         const GraphDesc d = descs[order[Gt + t]];
         gedge_t* E = (gedge_t*)d.edges;
         const bool bad = d.n <= wave_words
-                             ? solve_graph_lds<64, uint32_t>(wP, d.n, E, d.m, (glabel_t*)d.L, lane)
-                             : solve_graph_lds<64, uint16_t>(wP, d.n, E, d.m, (glabel_t*)d.L, lane);
+                             ? solve_graph_lds<64, uint32_t>(wP, d.n, E, d.m, (glabel_t*)d.L, lane, myq)
+                             : solve_graph_lds<64, uint16_t>(wP, d.n, E, d.m, (glabel_t*)d.L, lane, myq);
         const bool any_bad = __ballot(bad) != 0;
         if (lane == 0) *(CCM_GLOBAL int32_t*)d.status = any_bad ? CC_ERANGE : CC_OK;
         wave_sync();   // the next graph's init must not overtake this one's reads
@@ -493,7 +534,8 @@ struct LdsPlan {
 static int lds_plan(int device, LdsPlan* out) {
     int max_lds = 0;
     CCM_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
-    size_t b = (size_t)max_lds > 1024 ? (size_t)max_lds - 1024 : 0;   // static words beside
+    // beside it: the link queues (16 KB) and a few static words
+    size_t b = (size_t)max_lds > 20480 ? (size_t)max_lds - 20480 : 0;
     b = std::min<size_t>(b, (size_t)1 << 17);
     b &= ~(size_t)255;
     out->bytes = b;
