@@ -423,7 +423,8 @@ def bench_serve(cc, torch, count=3000, seed=0x2507036950000005):
     8-32, R-MAT/ER) through cc_serve and through a FIFO plain-path server (one
     stream, no batching, one request in flight) at the same offered rates:
     rho = 0.5, 0.9 and 1.2 of the FIFO server's capacity, and 1.25 of the
-    server's own. Capacities are whole streams submitted at once. At rho = 0.9
+    server's own. Capacities are whole streams submitted at once (the better of
+    two runs). At rho = 0.9
     the R-MAT-30 share (one machine's 1/16 vertex range with the global 2^30
     parent array) is submitted in the middle of the stream. p50/p99 latency from
     submission to labels in host memory."""
@@ -471,9 +472,15 @@ def bench_serve(cc, torch, count=3000, seed=0x2507036950000005):
 
     fifo = {"streams": 1, "small_n": 1, "max_inflight": 1}
     served = {"streams": 4}
-    outs_fifo, st_fifo, _ = run(fifo, 1e12)
+
+    def capacity(kw):
+        # the better of two all-at-once runs (a single one varied by a third)
+        a, b = run(kw, 1e12), run(kw, 1e12)
+        return a if a[1]["served_graphs_per_s"] >= b[1]["served_graphs_per_s"] else b
+
+    outs_fifo, st_fifo, _ = capacity(fifo)
     cap_fifo = st_fifo["served_graphs_per_s"]
-    outs_cap, st_cap, _ = run(served, 1e12)
+    outs_cap, st_cap, _ = capacity(served)
     cap_srv = st_cap["served_graphs_per_s"]
     same = all(np.array_equal(a, b) for a, b in zip(outs_cap, outs_fifo))
     # the share, generated on the device and held in host memory like any request
