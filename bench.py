@@ -36,8 +36,8 @@ PEAK_HBM_GBS = 8000.0
 # each counter scaled by what it reads for a 4 GiB device copy. Keyed by
 # (workload, variant); valid only for the kernel sources they were taken on.
 TRAFFIC = {
-    ("rmat26", "zroot"): {"bytes": 47673421549,
-                          "src_sha256": "1a3fbe883146c80aa7c86dd6742332d2db19d63995c50d6c52ae8df02a8fc868"},
+    ("rmat26", "zroot"): {"bytes": 47675782755,
+                          "src_sha256": "26188cd29cf80a3c61b006ddf964a4d0a3b12a2c240200acf83aaf73895544e2"},
 }
 
 HOOK_KERNELS = {
