@@ -442,19 +442,28 @@ __global__ __launch_bounds__(kMultiBlock) void k_bm_init(const GraphDesc* __rest
 }
 
 // Hooking of every multi graph's entries, a chunk of kMultiEChunk entries per
-// block step (Algorithm 1, as the HBM tile role, across the device).
+// block step (Algorithm 1, as the HBM tile role, across the device). part 0
+// takes each graph's entries below its split point (the first quarter of a
+// graph hooked in two parts, hook_in_two_parts; all entries of any other
+// graph), part 1 the rest, after a pointer-jumping pass.
 __global__ __launch_bounds__(kMultiBlock) void k_bm_hook(const GraphDesc* __restrict__ descs,
                                                          const uint32_t* __restrict__ mlist,
-                                                         const uint32_t* __restrict__ epre, uint32_t K) {
+                                                         const uint32_t* __restrict__ epre, uint32_t K,
+                                                         int part) {
     const uint32_t total = epre[K];
     for (uint32_t b = blockIdx.x; b < total; b += gridDim.x) {
         const uint32_t k = chunk_owner(epre, K, b);
         const GraphDesc d = descs[mlist[k]];
         glabel_t* P = (glabel_t*)d.L;
         gedge_t* E = (gedge_t*)d.edges;
-        const int64_t e0 = (int64_t)(b - epre[k]) * (int64_t)kMultiEChunk;
-        const int64_t e1 = std::min<int64_t>(e0 + (int64_t)kMultiEChunk, d.m);
-        const bool bad = hook_hbm<kMultiBlock>(P, d.n, E, e0, e1, threadIdx.x, split_walks(0, d.n));
+        const bool split = split_walks(0, d.n);
+        const int64_t q = hook_in_two_parts(d.n, (uint64_t)d.m, split) ? d.m / 4 : d.m;
+        int64_t e0 = (int64_t)(b - epre[k]) * (int64_t)kMultiEChunk;
+        int64_t e1 = std::min<int64_t>(e0 + (int64_t)kMultiEChunk, d.m);
+        if (part == 0) e1 = std::min<int64_t>(e1, q);
+        else e0 = std::max<int64_t>(e0, q);
+        if (e0 >= e1) continue;
+        const bool bad = hook_hbm<kMultiBlock>(P, d.n, E, e0, e1, threadIdx.x, split);
         if (bad) gstore((glabel_t*)d.status, (uint32_t)CC_ERANGE);
     }
 }
@@ -584,6 +593,7 @@ BatchSched batch_default_sched() {
 struct BatchPlan {
     uint32_t G = 0, Gt = 0, Gw = 0, Gm = 0;
     uint32_t vchunks = 0, echunks = 0;
+    bool two_part = false;   // some multi graph is hooked in two parts
 };
 
 // Host staging of one launch: the zeroed tickets, the role lists (tile and wave
@@ -621,6 +631,8 @@ static int batch_prepare(BatchScratch* bs, uint32_t G, const GraphDesc* descs,
             return fail(CC_EINVAL, "multi graphs too large for one batch");
         vpre[k + 1] = (uint32_t)vt;
         epre[k + 1] = (uint32_t)et;
+        plan->two_part = plan->two_part ||
+                         hook_in_two_parts(d.n, (uint64_t)d.m, split_walks(0, d.n));
     }
     std::copy(descs, descs + G, reinterpret_cast<GraphDesc*>(h + l.descs));
     plan->G = G;
@@ -654,7 +666,18 @@ static int batch_enqueue(int device, BatchScratch* bs, const BatchPlan& p, const
         CCM_HIP(hipGetLastError());
         if ((rc = cohere(stream))) return rc;
         if (p.echunks) {
-            k_bm_hook<<<std::min(p.echunks, cap), kMultiBlock, 0, stream>>>(descs, mlist, epre, p.Gm);
+            k_bm_hook<<<std::min(p.echunks, cap), kMultiBlock, 0, stream>>>(descs, mlist, epre, p.Gm,
+                                                                          0);
+            CCM_HIP(hipGetLastError());
+            if ((rc = cohere(stream))) return rc;
+        }
+        if (p.two_part) {
+            k_bm_compress<<<std::min(p.vchunks, cap), kMultiBlock, 0, stream>>>(descs, mlist, vpre,
+                                                                              p.Gm);
+            CCM_HIP(hipGetLastError());
+            if ((rc = cohere(stream))) return rc;
+            k_bm_hook<<<std::min(p.echunks, cap), kMultiBlock, 0, stream>>>(descs, mlist, epre, p.Gm,
+                                                                          1);
             CCM_HIP(hipGetLastError());
             if ((rc = cohere(stream))) return rc;
         }

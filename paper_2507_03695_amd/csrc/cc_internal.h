@@ -45,6 +45,15 @@ constexpr uint64_t kSplitMinBytes = 4ull << 20;
 __host__ __device__ inline bool split_walks(uint32_t flags, uint64_t n, uint64_t entry_bytes = 4) {
     return !(flags & CC_F_NO_SPLIT) && n * entry_bytes > kSplitMinBytes;
 }
+// Hooking in two parts: without path splitting the walks of one pass grow long
+// while the forest forms (link by index makes chains that nothing shortens),
+// and every later entry walks them. Where that applies to enough entries per
+// vertex, the first quarter of the entries is hooked, the forest pointer-jumped
+// (a flat forest with the same components, from which Algorithm 1 continues)
+// and the rest hooked over it.
+__host__ __device__ inline bool hook_in_two_parts(uint64_t n, uint64_t m, bool split) {
+    return !split && m >= (1ull << 18) && m >= 4 * n;
+}
 constexpr uint32_t kGridCap = 256 * 32;   // blocks of a grid-stride launch over n
 
 // One graph of a batched launch: where its entries and labels live.

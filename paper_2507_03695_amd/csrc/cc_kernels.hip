@@ -921,12 +921,9 @@ int run_hook(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P
     const uint32_t n32 = (uint32_t)n;
     uint32_t* zb = s->zbits;
     const uint32_t g = (uint32_t)blocks;
-    if (!zr && !split && m >= (1ull << 18) && m >= 4 * n) {
-        // Without path splitting (a small array) the walks of one pass grow long
-        // while the forest forms, and every later entry pays for them. So the
-        // first quarter of the entries is hooked, the forest pointer-jumped (a
-        // flat forest with the same components), and the rest hooked over it
-        // (ER n = 2^16, 2^20 entries: 0.124 -> 0.099 ms through separate calls).
+    if (!zr && hook_in_two_parts(n, m, split)) {
+        // the plain hook in two parts (ER n = 2^16, 2^20 entries: whole solve
+        // 0.150 -> 0.115 ms)
         const uint64_t m1 = m / 4;
         const uint32_t g1 = (uint32_t)((m1 + per - 1) / per);
         const uint32_t g2 = (uint32_t)((m - m1 + per - 1) / per);
