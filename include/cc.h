@@ -71,10 +71,13 @@ int cc_version(void);
 /* With CC_F_ZROOT: the zero root is `zroot_hint` (must be < n).            */
 #define CC_F_ZROOT_HINT   0x4u
 /* Plain root walks without path splitting (Algorithm 1's finds as printed)
-   everywhere. Without the flag the regrouped hooks and the batch's workgroup
-   role split paths, and the direct hooks split them where the parent array
-   exceeds 4 MB (one XCD's L2; below that the walks are L2 hits and the
-   splitting stores cost more than they save).                              */
+   everywhere, and no pointer jumping inside a hook. Without the flag the
+   regrouped hooks and the batch's workgroup role split paths, and the direct
+   hooks split them where the parent array exceeds 4 MB (one XCD's L2; below
+   that the walks are L2 hits and the splitting stores cost more than they
+   save). Below that size the plain direct hook, given at least 2^18 entries
+   and 4 per vertex, instead runs one pointer-jumping pass after the first
+   quarter of the entries, so that the rest walk a flat forest.             */
 #define CC_F_NO_SPLIT     0x8u
 /* Keep the direct hook, which takes the entries in their given order, where
    the regrouped hooks would apply (4 <= ceil(n / 2^19) <= 256, or 8 <= with

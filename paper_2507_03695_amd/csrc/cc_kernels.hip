@@ -921,7 +921,7 @@ int run_hook(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P
     const uint32_t n32 = (uint32_t)n;
     uint32_t* zb = s->zbits;
     const uint32_t g = (uint32_t)blocks;
-    if (!zr && hook_in_two_parts(n, m, split)) {
+    if (!zr && !(flags & CC_F_NO_SPLIT) && hook_in_two_parts(n, m, split)) {
         // the plain hook in two parts (ER n = 2^16, 2^20 entries: whole solve
         // 0.150 -> 0.115 ms)
         const uint64_t m1 = m / 4;
