@@ -36,8 +36,8 @@ PEAK_HBM_GBS = 8000.0
 # each counter scaled by what it reads for a 4 GiB device copy. Keyed by
 # (workload, variant); valid only for the kernel sources they were taken on.
 TRAFFIC = {
-    ("rmat26", "zroot"): {"bytes": 47670001468,
-                          "src_sha256": "289b8827293df595b14da10ff6d4b658aed1d2853e7348dfccf275a20ddba39b"},
+    ("rmat26", "zroot"): {"bytes": 47715121089,
+                          "src_sha256": "8aa40efbe11bbfb1aa5bbdfe1fb5dc4cb0994940934d749fd3d1a9076181fd82"},
 }
 
 HOOK_KERNELS = {
