@@ -533,6 +533,28 @@ def test_labels_read_back_by_the_next_kernel():
             assert np.array_equal(host, want), f"rep {rep}: labels changed between solves"
 
 
+def test_two_part_small_array_hook():
+    """The plain direct hook on a small array takes its entries in two parts with
+    a pointer-jumping pass between: an out-of-range entry is reported from
+    either part, a symmetric list (every pair in both orders, u < v hooked)
+    gives the oracle's labels of its pairs, and CC_F_NO_SPLIT (one part, no
+    pass) gives the same labels."""
+    n = 1 << 16
+    e = graphgen.er(n, 1 << 20, 131)
+    want = oracle.cc_labels(n, e)
+    with cc.Context() as c:
+        L = torch.empty(n, dtype=torch.int32, device="cuda")
+        for at in (5, (1 << 18) - 1, 1 << 18, len(e) - 3):   # both sides of the split point
+            bad = e.copy()
+            bad[at] = (n + 7, 1)
+            c.solve_async(to_dev(bad), n, L)
+            assert c.sync() == cc.CC_ERANGE, at
+        sym = np.ascontiguousarray(np.concatenate([e, e[:, ::-1]]))
+        for fl in (cc.F_SYMMETRIC, cc.F_SYMMETRIC | cc.F_NO_SPLIT, 0, cc.F_NO_SPLIT):
+            Ls = c.solve(to_dev(sym if fl & cc.F_SYMMETRIC else e), n, flags=fl)
+            assert_same_labels(to_host_u32(Ls), want, f"flags {fl:#x}")
+
+
 @pytest.mark.parametrize("case", ["er_16", "er_18", "rmat_17"])
 def test_small_array_hook(case):
     """Small parent arrays with many entries per vertex (the case where walks end
