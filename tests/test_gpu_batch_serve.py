@@ -216,6 +216,37 @@ def test_batch_every_schedule(ctx):
         assert all(wst[g] == cc.CC_ERANGE for g in bad)
 
 
+def _walk_heavy_batch(seed):
+    """Graphs whose entries need long walks and many links at once: paths in
+    shuffled, increasing and decreasing order (chains under link by index),
+    stars with the hub last, a complete graph, on both sides of the wave role's
+    2,048-vertex and the workgroup role's 2^15-vertex entry-width limits."""
+    rng = np.random.default_rng(seed)
+    graphs = []
+    for n in (300, 2048, 2049, 4096, 20_000, 1 << 15, (1 << 15) + 1, 60_000):
+        v = np.arange(n - 1, dtype=np.uint32)
+        path = np.stack([v, v + 1], 1)
+        graphs.append((path[rng.permutation(n - 1)], n))        # shuffled
+        graphs.append((path, n))                                # increasing
+        graphs.append((path[::-1].copy(), n))                   # decreasing
+        star = np.stack([np.full(n - 1, n - 1, np.uint32), v], 1)
+        graphs.append((star, n))
+    k = 200
+    iu = np.triu_indices(k, 1)
+    graphs.append((np.stack(iu, 1).astype(np.uint32), k))       # complete graph
+    return graphgen.batch_from_graphs(graphs)
+
+
+def test_batch_long_walks(ctx):
+    """Walk-heavy graphs under every schedule: labels equal the oracle's."""
+    b = _walk_heavy_batch(63)
+    vo, eo, ed = batch_to_dev(b)
+    for sc in SCHEDULES:
+        L, st = ctx.batch(vo, eo, ed, sched=sc)
+        wst = _check_batch(b, L, st, f"walk-heavy schedule {sc}")
+        assert np.all(wst == 0)
+
+
 def test_batch_schedule_captured(ctx):
     """A captured batch takes the context's forced schedule (every role at once
     here) and its replays equal the oracle, with eager batches between them."""
