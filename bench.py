@@ -36,8 +36,8 @@ PEAK_HBM_GBS = 8000.0
 # each counter scaled by what it reads for a 4 GiB device copy. Keyed by
 # (workload, variant); valid only for the kernel sources they were taken on.
 TRAFFIC = {
-    ("rmat26", "zroot"): {"bytes": 47715121089,
-                          "src_sha256": "8aa40efbe11bbfb1aa5bbdfe1fb5dc4cb0994940934d749fd3d1a9076181fd82"},
+    ("rmat26", "zroot"): {"bytes": 47675427858,
+                          "src_sha256": "79fdac7860482c903d4075846773a3fa101d6720866dc40dfa7e87b00ae6162c"},
 }
 
 HOOK_KERNELS = {

@@ -75,9 +75,10 @@ int cc_version(void);
    regrouped hooks and the batch's workgroup role split paths, and the direct
    hooks split them where the parent array exceeds 4 MB (one XCD's L2; below
    that the walks are L2 hits and the splitting stores cost more than they
-   save). Below that size the plain direct hook, given at least 2^18 entries
-   and 4 per vertex, instead runs one pointer-jumping pass after the first
-   quarter of the entries, so that the rest walk a flat forest.             */
+   save). Below that size the direct hook, given at least 2^18 entries and 4
+   per vertex, instead runs one pointer-jumping pass (with CC_F_ZROOT, the
+   compress pass) after the first quarter of the entries, so that the rest
+   walk a flat forest.                                                      */
 #define CC_F_NO_SPLIT     0x8u
 /* Keep the direct hook, which takes the entries in their given order, where
    the regrouped hooks would apply (4 <= ceil(n / 2^19) <= 256, or 8 <= with

@@ -921,24 +921,36 @@ int run_hook(Slot* s, uint64_t n, uint64_t m, const uint32_t* edges, uint32_t* P
     const uint32_t n32 = (uint32_t)n;
     uint32_t* zb = s->zbits;
     const uint32_t g = (uint32_t)blocks;
-    if (!zr && !(flags & CC_F_NO_SPLIT) && hook_in_two_parts(n, m, split)) {
-        // the plain hook in two parts (ER n = 2^16, 2^20 entries: whole solve
-        // 0.150 -> 0.115 ms)
+    const bool linkz = hook_links_z(flags, n);
+    if (!(flags & CC_F_NO_SPLIT) && hook_in_two_parts(n, m, split)) {
+        // in two parts (whole solves, ER n = 2^16 with 2^20 entries: plain 0.150
+        // -> 0.115 ms; the zero-root hook alone 0.266 -> 0.198 ms). With a zero
+        // root the pass between is compress's: trees pointer-jumped and the
+        // roots of marked vertices marked, which the rest of the hook reads as
+        // connections to z like any other mark.
         const uint64_t m1 = m / 4;
         const uint32_t g1 = (uint32_t)((m1 + per - 1) / per);
         const uint32_t g2 = (uint32_t)((m - m1 + per - 1) / per);
-        k_hook<false, 0><<<g1, kBlock, 0, stream>>>(edges, m1, n32, P, zb, s->st, sym);
-        int rc = cohere(stream);
-        if (rc) return rc;
-        k_compress<false><<<grid_for(n, kBlock, kGridCap), kBlock, 0, stream>>>(P, n, s->st,
-                                                                               nullptr, nullptr);
-        if ((rc = cohere(stream))) return rc;
-        k_hook<false, 0><<<g2, kBlock, 0, stream>>>(edges + 2 * m1, m - m1, n32, P, zb, s->st,
-                                                   sym);
-        CCM_HIP(hipGetLastError());
+        const uint32_t gn = grid_for(n, kBlock, kGridCap);
+        for (int part = 0; part < 2; ++part) {
+            const uint32_t* e = part ? edges + 2 * m1 : edges;
+            const uint64_t mp = part ? m - m1 : m1;
+            const uint32_t gp = part ? g2 : g1;
+            if (!zr) k_hook<false, 0><<<gp, kBlock, 0, stream>>>(e, mp, n32, P, zb, s->st, sym);
+            else if (linkz)
+                k_hook<true, 0, false, true><<<gp, kBlock, 0, stream>>>(e, mp, n32, P, zb, s->st, sym);
+            else k_hook<true, 0><<<gp, kBlock, 0, stream>>>(e, mp, n32, P, zb, s->st, sym);
+            CCM_HIP(hipGetLastError());
+            if (part) break;
+            int rc = cohere(stream);
+            if (rc) return rc;
+            if (zr) k_compress<true><<<gn, kBlock, 0, stream>>>(P, n, s->st, zb, s->bmin);
+            else k_compress<false><<<gn, kBlock, 0, stream>>>(P, n, s->st, nullptr, nullptr);
+            CCM_HIP(hipGetLastError());
+            if ((rc = cohere(stream))) return rc;
+        }
         return CC_OK;
     }
-    const bool linkz = hook_links_z(flags, n);
     if (zr && linkz && split)
         k_hook<true, 1, false, true><<<g, kBlock, 0, stream>>>(edges, m, n32, P, zb, s->st, sym);
     else if (zr && linkz)
