@@ -125,21 +125,25 @@ def link(sh, u, pu, v, pv, split, bug, keyz):
         u, pu, v, pv = hi, old, lo, lo
 
 
-def thread(sh, entries, split, bug=None):
+def thread(sh, entries, split, bug=None, stale=False):
     """One thread's entries: bitmap tests and marks, then parent reads, then the
-    hooks."""
+    hooks. stale: the bit tests read a copy of the bitmap taken when the thread
+    starts (the device may read bits through a stale cache line: set bits can
+    read as clear, never the reverse)."""
     z = sh.z
     keyz = z
     k = len(entries)
     live = [u != v for u, v in entries]
     if z is not None:
         inu, inv = [False] * k, [False] * k
+        yield
+        bits = list(sh.bit) if stale else sh.bit
         for i, (u, v) in enumerate(entries):
             if live[i]:
                 yield
-                inu[i] = sh.bit[u]
+                inu[i] = bits[u]
                 yield
-                inv[i] = sh.bit[v]
+                inv[i] = bits[v]
         for i, (u, v) in enumerate(entries):
             if live[i] and inu[i] != inv[i] and bug != "no_mark":
                 yield
@@ -188,14 +192,14 @@ def initial_push(sh, edges):
 class Run:
     """A fresh shared state and its threads, advanced one step at a time."""
 
-    def __init__(self, n, z, per_thread, split, bug=None):
+    def __init__(self, n, z, per_thread, split, bug=None, stale=False):
         self.sh = Shared(n, z)
         edges = [e for t in per_thread for e in t]
         if z is not None:
             initial_push(self.sh, edges)
         self.gens = {}
         for t, entries in enumerate(per_thread):
-            g = thread(self.sh, entries, split, bug)
+            g = thread(self.sh, entries, split, bug, stale)
             try:
                 next(g)                     # up to the first shared access
                 self.gens[t] = g
@@ -341,6 +345,34 @@ def test_every_interleaving(i, split):
 
 
 # ---- random: three or four threads, random multigraphs ------------------------------
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_schedules_stale_bits(seed):
+    """As below, with every thread testing bits against a copy of the bitmap
+    taken when it starts: a mark made meanwhile is missed, so the entry takes
+    the walk (or marks again), and the labels are still the oracle's."""
+    rng = random.Random(3000 + seed)
+    n = rng.randint(3, 9)
+    m = rng.randint(2, 12)
+    edges = [(rng.randrange(n), rng.randrange(n)) for _ in range(m)]
+    nt = rng.randint(2, 4)
+    per_thread = [edges[t::nt] for t in range(nt)]
+    z = rng.randrange(n)
+    for split in (True, False):
+        runs = []
+        for _ in range(150):
+            r = Run(n, z, per_thread, split, None, True)
+            t = None
+            while True:
+                en = r.enabled()
+                if not en:
+                    break
+                if t not in en or rng.random() > 0.7:
+                    t = rng.choice(en)
+                r.step(t)
+            runs.append((None, r.sh))
+        assert first_failure((n, z, per_thread, split), runs) is None, (n, z, per_thread, split)
+
 
 @pytest.mark.parametrize("seed", range(12))
 def test_random_schedules(seed):
