@@ -49,6 +49,20 @@ def test_noalloc_equals_solve_async_twice(ctx, flags):
         assert_same_labels(got, oracle.cc_labels(n, e), f"noalloc vs oracle n={n}")
 
 
+@pytest.mark.parametrize("flags", [0, 0x1])
+def test_noalloc_two_part_hook(ctx, flags):
+    """Small arrays with many entries per vertex, where the direct hook runs in
+    two parts with a pointer-jumping (or, with a zero root, compress) pass between
+    them on the fixed scratch: two calls in a row, the second smaller."""
+    for e, n in ((graphgen.er(1 << 16, 1 << 20, 15), 1 << 16),
+                 (graphgen.rmat(15, (1 << 18) + 33, 16), 1 << 15)):
+        log(f"noalloc two-part flags={flags:#x} n={n} m={len(e)}")
+        got, ref, st = _pair(ctx, e, n, flags)
+        assert st == cc.CC_OK
+        assert_same_labels(got, ref, f"noalloc two-part vs cc_solve_async n={n}")
+        assert_same_labels(got, oracle.cc_labels(n, e), f"noalloc two-part vs oracle n={n}")
+
+
 def test_noalloc_status_and_limits(ctx):
     n = 5000
     e = graphgen.er(n, 20_000, 21)
